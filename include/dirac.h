@@ -1,0 +1,210 @@
+/*
+ * dirac.h -- C ABI of libdirac, an MI355X (gfx950) implementation of the
+ * directional-split pseudospectral time step ("Numerical Scheme II") for the
+ * time-dependent Dirac equation in static curved 2-D space.
+ *
+ * Reference: X. Antoine, F. Fillion-Gourdeau, E. Lorin, S. McLean,
+ * "Pseudospectral computational methods for the time-dependent Dirac equation
+ * in static curved spaces", arXiv:1909.02894.
+ *
+ * One time step (Sec. 5.2, eqs. (poly_mod) and (second_scheme), 2-D form of
+ * Numerical Experiment 3 with the absorbing layer of Sec. 3):
+ *   1. psi <- E psi, E = exp(-i dt/2 [beta(x) m c^2 + F(x)])      (Step 1)
+ *   2. x:  psi <- b_x F_1^{-1}[K_x(xi) F_1 psi] + (1 - b_x) psi     (direction 1)
+ *   3. y:  psi <- b_y F_2^{-1}[K_y(xi) F_2 psi] + (1 - b_y) psi     (direction 2)
+ *   4. psi <- E psi                                                 (Step 5)
+ * with K_i(xi) = exp(-i c dt xi sigma_i), b_i = a(x)/S^i(x^i), a = e^{Phi-Psi}.
+ *
+ * Conventions shared by every call:
+ *  - Every function returns dirac_status (0 = OK, < 0 = error); no C++
+ *    exception crosses the ABI.  dirac_last_error() gives a thread-local
+ *    message for the last failure on the calling thread.
+ *  - A failed call leaves the solver as it was.
+ *  - Host spinor arrays are complex128, layout [n2][n1][2] (y outer, x inner,
+ *    spinor component innermost), each complex number as (re, im) doubles:
+ *    4 doubles per grid point.  The caller owns them; they are copied.
+ *  - The device buffer and the HIP stream are owned by the caller (for
+ *    instance a torch uint8 tensor and torch's current stream); the library
+ *    carves all of its device data out of that buffer and never frees it.
+ *  - A solver handle is not thread safe.  Distinct handles on distinct
+ *    streams may run concurrently.
+ */
+#ifndef DIRAC_H
+#define DIRAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dirac_status;
+enum {
+    DIRAC_OK = 0,
+    DIRAC_E_ARG = -1,        /* null pointer or out-of-range parameter          */
+    DIRAC_E_SIZE = -2,       /* grid size not a power of two in [16, 8192], or a */
+                             /* device buffer smaller than the footprint          */
+    DIRAC_E_UNSTABLE = -3,   /* a blend coefficient b = a/S outside [0, 1]       */
+    DIRAC_E_NOMEM = -4,      /* host allocation failed                          */
+    DIRAC_E_DEVICE = -5,     /* a HIP call failed                               */
+    DIRAC_E_STATE = -6,      /* call out of order (e.g. step before set_initial)*/
+    DIRAC_E_NONFINITE = -7   /* non-finite values in an input array              */
+};
+
+/* Arithmetic of the state, FFTs and pointwise stages.  DIRAC_FP32 keeps the
+ * tables generated in FP64 and rounded once, and all reductions in FP64. */
+enum { DIRAC_FP64 = 0, DIRAC_FP32 = 1 };
+
+/* Periodic grid on [-a1, a1) x [-a2, a2): x_i = -a1 + i h1, h1 = 2 a1 / n1
+ * (Sec. 5).  n1, n2: powers of two in [16, 8192].  dt > 0, c > 0, m >= 0. */
+typedef struct {
+    int32_t n1, n2;
+    double a1, a2;
+    double dt, c, m;
+} dirac_grid;
+
+/* Static metric ds^2 = e^{2 Phi} dt^2 - e^{2 Psi} (dx^2 + dy^2) (Numerical
+ * Experiment 3, Appendix A). */
+enum {
+    DIRAC_METRIC_FLAT = 0,        /* Phi = Psi = 0                                    */
+    DIRAC_METRIC_GAUSS_BUMP = 1,  /* Phi = 0, Psi = ln(1 + |grad h|^2)/4,             */
+                                  /* h = bump_A exp(-r^2 / bump_s^2) (static sheet)   */
+    DIRAC_METRIC_PAPER_EXP3 = 2,  /* Phi = exp(-0.01 r^2), Psi = exp(-0.005 r^2)     */
+    DIRAC_METRIC_FIELDS = 3       /* caller-given Phi, Psi and their gradients        */
+};
+/* Spin-connection potential chi: the Hamiltonian carries -i c a sigma_j d_j chi / 2. */
+enum {
+    DIRAC_SPIN_NONE = 0,   /* chi = 0                                               */
+    DIRAC_SPIN_PAPER = 1,  /* chi = Phi (the printed 2-D equation)                   */
+    DIRAC_SPIN_2P1 = 2     /* chi = Phi + Psi (conformal 2+1-D connection)          */
+};
+typedef struct {
+    int32_t kind;                 /* DIRAC_METRIC_*                                  */
+    int32_t spin;                 /* DIRAC_SPIN_*                                    */
+    double bump_A, bump_s;        /* GAUSS_BUMP only (bump_s > 0)                    */
+    /* FIELDS only: host arrays [n2][n1] of doubles, copied at create time. */
+    const double *phi, *psi, *dphi_dx, *dphi_dy, *dpsi_dx, *dpsi_dy;
+} dirac_metric;
+
+/* Absorbing layer (Sec. 3): S^i = 1 + e^{i theta} Sigma~(x^i) on the width_pts
+ * grid points next to the periodic seam x = +-a (layer L* <= |x| <= L, L = a,
+ * L* = a - width_pts h; distance to the seam counted in whole grid steps).
+ * type 1..6 = the paper's types I..VI with parameter sigma0.  width_pts = 0
+ * switches the layer off.  Scheme II is stable only for real blend
+ * coefficients in [0, 1] (stability proposition of Sec. 5.2), so a nonzero
+ * theta inside an active layer is rejected with DIRAC_E_UNSTABLE. */
+typedef struct {
+    int32_t width_pts;
+    int32_t type;
+    double sigma0, theta;
+} dirac_pml;
+
+/* FP64 observables of the current state (dA = h1 h2):
+ *   norm_l2 = dA sum |psi|^2,   norm_w = dA sum w |psi|^2 with w = e^{chi - Phi + Psi}
+ *   (the weight the continuous equation conserves),
+ *   energy = dA sum w psi^dag H psi with H the 2-D Hamiltonian of Numerical
+ *   Experiment 3 (spectral derivative of eq. (trick), no layer stretch),
+ *   x_mean, y_mean = density-weighted mean position, finite = 1 iff every
+ *   state value is finite. */
+typedef struct {
+    int64_t step;
+    double t;
+    double norm_l2, norm_w, energy_re, energy_im, x_mean, y_mean;
+    int32_t finite;
+    int32_t reserved;
+} dirac_obs;
+
+typedef struct dirac_solver dirac_solver;
+
+/* Bytes of device memory a solver needs (including 256-byte alignment slack).
+ * Returns 0 for invalid arguments. */
+size_t dirac_footprint_bytes(const dirac_grid* grid, const dirac_metric* metric,
+                             const dirac_pml* pml, int32_t precision);
+
+/* Build a solver: validates the grid, builds every table on the device in FP64
+ * (grid, momenta xi_p = p pi / a with the Nyquist index p = -n/2, metric fields,
+ * a, the closed-form 2x2 half-step exponential E, layer profile 1/S, symbols
+ * K_i, FFT twiddles, observable weights), checks the blend coefficients, and
+ * synchronises the stream once.  device_buffer: caller-owned device memory of
+ * at least dirac_footprint_bytes(...) bytes, 256-byte aligned.  hip_stream:
+ * caller-owned hipStream_t (NULL = the null stream).  On success *out owns
+ * host memory only; release it with dirac_destroy. */
+dirac_status dirac_create_metric(const dirac_grid* grid, const dirac_metric* metric,
+                                 const dirac_pml* pml, int32_t precision,
+                                 void* device_buffer, size_t bytes, void* hip_stream,
+                                 dirac_solver** out);
+
+/* Upload the initial spinor (host [n2][n1][2] complex128, not normalised) and
+ * reset the step counter and time to 0.  Synchronises the stream. */
+dirac_status dirac_set_initial_spinor(dirac_solver* s, const double* psi_host);
+
+/* Same from device memory: psi_dev holds [n2][n1][2] complex128 on the
+ * solver's device.  Asynchronous on the solver's stream. */
+dirac_status dirac_set_initial_spinor_device(dirac_solver* s, const void* psi_dev);
+
+/* Advance nsteps >= 0 time steps (Step 1, x, y, Step 5 each), asynchronously
+ * on the solver's stream.  Between consecutive steps Step 5 and the next Step 1
+ * are applied back to back in registers (E then E), which is the same
+ * arithmetic as the unfused order. */
+dirac_status dirac_step_n(dirac_solver* s, int64_t nsteps);
+
+/* Compute the observables of the current state (two spectral-derivative
+ * passes with fused FP64 partial sums, then one fixed-order FP64 reduction;
+ * bitwise reproducible).  Synchronises the stream. */
+dirac_status dirac_observables(dirac_solver* s, dirac_obs* out);
+
+/* Copy the state to host memory as complex128 [n2][n1][2].  Synchronises. */
+dirac_status dirac_get_spinor(dirac_solver* s, double* psi_host_out);
+
+/* Release the handle (host memory only; the caller's device buffer is untouched). */
+dirac_status dirac_destroy(dirac_solver* s);
+
+/* Thread-local message for the last failed call on this thread ("" if none). */
+const char* dirac_last_error(void);
+
+/* --- schedules, timing and tuning ---------------------------------------------- */
+
+/* FFT schedule of one direction: register radix (2, 4, 8 or 16) and lines
+ * (rows or columns) per workgroup.  Every per-line operation, and so every
+ * result bit, depends on (n, precision, radix) only, never on lines_per_wg. */
+typedef struct {
+    int32_t radix;
+    int32_t lines_per_wg;
+} dirac_schedule;
+
+/* Number of compiled schedules for (n, precision, direction 0 = x / 1 = y) and
+ * the i-th of them. */
+int32_t dirac_schedule_count(int32_t n, int32_t precision, int32_t direction);
+dirac_status dirac_schedule_get(int32_t n, int32_t precision, int32_t direction, int32_t i,
+                                dirac_schedule* out);
+
+/* Read / override the schedules a solver uses (direction 0 = x, 1 = y). */
+dirac_status dirac_get_schedule(const dirac_solver* s, int32_t direction, dirac_schedule* out);
+dirac_status dirac_set_schedule(dirac_solver* s, int32_t direction, const dirac_schedule* sch);
+
+/* Launch mode of dirac_step_n: 0 = one kernel launch per stage, 1 = replay a
+ * HIP graph of 2 * graph_chunk stage kernels (default, chunk 32). */
+dirac_status dirac_set_launch_mode(dirac_solver* s, int32_t use_graph, int32_t graph_chunk);
+
+/* Advance nsteps like dirac_step_n with one kernel launch per stage and a HIP
+ * event pair around every launch on the solver's stream, then synchronise.
+ * ms_out[0] / ms_out[1] = summed duration of the x / y stage kernels in
+ * milliseconds, counts_out[0..1] = number of launches of each. */
+dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
+                                int64_t* counts_out);
+
+/* Autotuner: time every compiled schedule of both directions on this solver's
+ * own buffers (the state is saved and restored, so the solve is unchanged),
+ * keep the fastest per (n, precision, direction, grid shape) in a process-wide
+ * cache and apply it.  reps = timed steps per candidate (>= 1). */
+dirac_status dirac_autotune(dirac_solver* s, int32_t reps);
+
+/* Save / load the tuning cache as a text file (one line per entry). */
+dirac_status dirac_tune_cache_save(const char* path);
+dirac_status dirac_tune_cache_load(const char* path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIRAC_H */

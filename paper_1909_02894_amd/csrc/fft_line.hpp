@@ -1,0 +1,204 @@
+// fft_line.hpp -- register/LDS Stockham FFT of one grid line (row or column)
+// for both spinor components, for gfx950 (wave64).
+//
+// The partial transforms F_i / F_i^{-1} of Sec. 5 (unnormalised forward sum
+// psi_k exp(-2 pi i p k / n); the 1/n of the inverse is folded into the
+// Fourier symbol by the caller) are computed with the iterative Stockham
+// autosort decimation-in-time formulation (Govindaraju et al., SC'08): pass
+// with radix Rp after Ns = product of earlier radices reads butterfly jj's
+// inputs at jj + r n/Rp, multiplies input r by W_n^{r (jj mod Ns) n/(Ns Rp)},
+// takes a radix-Rp DFT and writes output s at (jj / Ns) Ns Rp + jj mod Ns + s Ns.
+//
+// Thread layout.  A line of n points is handled by P = n / R threads; thread j
+// keeps R values per component in registers.  The first and the last pass
+// have radix R, so on entry thread j holds positions j + r P and on exit it
+// holds modes j + s P: the symbol multiply and the blend with the untouched
+// input happen in registers, and only the interior passes go through LDS.
+// Radix schedule: n = R^e * rem (rem < R), passes [R, rem, R, ..., R].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dirac {
+
+template <typename T> struct cpx { T re, im; };
+
+template <typename T> __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename T> __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename T> __device__ __forceinline__ cpx<T> conjc(cpx<T> a) { return {a.re, -a.im}; }
+template <typename T> __device__ __forceinline__ cpx<T> mul_i(cpx<T> a) { return {-a.im, a.re}; }   // * i
+template <typename T> __device__ __forceinline__ cpx<T> mul_mi(cpx<T> a) { return {a.im, -a.re}; }  // * -i
+template <typename T> __device__ __forceinline__ cpx<T> scal(T s, cpx<T> a) { return {s * a.re, s * a.im}; }
+
+// cos / sin of 2 pi m / 16 (m = 0..15), as double literals.
+__host__ __device__ constexpr double cos16(int m) {
+    return m == 0 ? 1.0 : m == 1 ? 0.92387953251128673848 : m == 2 ? 0.70710678118654752440
+         : m == 3 ? 0.38268343236508977173 : m == 4 ? 0.0 : m == 5 ? -0.38268343236508977173
+         : m == 6 ? -0.70710678118654752440 : m == 7 ? -0.92387953251128673848 : m == 8 ? -1.0
+         : m == 9 ? -0.92387953251128673848 : m == 10 ? -0.70710678118654752440
+         : m == 11 ? -0.38268343236508977173 : m == 12 ? 0.0 : m == 13 ? 0.38268343236508977173
+         : m == 14 ? 0.70710678118654752440 : 0.92387953251128673848;
+}
+__host__ __device__ constexpr double sin16(int m) { return cos16((m + 12) % 16); }
+
+// v * exp(-+ 2 pi i M / 16): forward sign -, inverse sign +.
+template <typename T, int M, bool INV>
+__device__ __forceinline__ cpx<T> rot16(cpx<T> v) {
+    if constexpr (M == 0) {
+        return v;
+    } else if constexpr (M == 4) {
+        return INV ? mul_i(v) : mul_mi(v);
+    } else if constexpr (M == 8) {
+        return {-v.re, -v.im};
+    } else if constexpr (M == 12) {
+        return INV ? mul_mi(v) : mul_i(v);
+    } else {
+        const T c = (T)cos16(M);
+        const T s = INV ? (T)sin16(M) : (T)(-sin16(M));
+        return {v.re * c - v.im * s, v.re * s + v.im * c};
+    }
+}
+
+__host__ __device__ constexpr int bitrev(int i, int R) {
+    int r = 0;
+    for (int b = 1; b < R; b <<= 1) { r = (r << 1) | (i & 1); i >>= 1; }
+    return r;
+}
+
+template <typename T, int LEN, int K, bool INV>
+__device__ __forceinline__ void dft_butterflies(cpx<T>* y) {
+    if constexpr (K < LEN / 2) {
+        const cpx<T> u = y[K];
+        const cpx<T> t = rot16<T, (16 / LEN) * K, INV>(y[K + LEN / 2]);
+        y[K] = u + t;
+        y[K + LEN / 2] = u - t;
+        dft_butterflies<T, LEN, K + 1, INV>(y);
+    }
+}
+
+template <typename T, int R, int LEN, bool INV>
+__device__ __forceinline__ void dft_stages(cpx<T>* y) {
+    if constexpr (LEN <= R) {
+#pragma unroll
+        for (int i = 0; i < R; i += LEN) dft_butterflies<T, LEN, 0, INV>(y + i);
+        dft_stages<T, R, LEN * 2, INV>(y);
+    }
+}
+
+// In-register DFT of size R (2, 4, 8, 16): x_s <- sum_r x_r exp(-+ 2 pi i r s / R).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft(cpx<T>* x) {
+    static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 16, "radix");
+    if constexpr (R > 1) {
+        cpx<T> y[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) y[i] = x[bitrev(i, R)];
+        dft_stages<T, R, 2, INV>(y);
+#pragma unroll
+        for (int i = 0; i < R; ++i) x[i] = y[i];
+    }
+}
+
+__host__ __device__ constexpr int ilog(int n, int r) {  // largest e with r^e | n
+    int e = 0;
+    while (n % r == 0 && n > 1) { n /= r; ++e; }
+    return e;
+}
+__host__ __device__ constexpr int ipow(int r, int e) { int v = 1; for (int i = 0; i < e; ++i) v *= r; return v; }
+
+// One line geometry: N-point transform, R values per thread per component,
+// L lines per workgroup, COLS = lines are columns (line index fastest among
+// threads, for coalesced row segments), SPLIT = exchange one spinor component
+// at a time through LDS (half the LDS, twice the barriers).
+template <typename T, int N, int R, int L, bool COLS, bool SPLIT>
+struct LineFFT {
+    static constexpr int P = N / R;
+    static constexpr int NT = P * L;
+    static constexpr int E = ilog(N, R);
+    static constexpr int REM = N / ipow(R, E);
+    static constexpr int NPASS = E + (REM > 1 ? 1 : 0);
+    static constexpr int NC = SPLIT ? 1 : 2;
+    static constexpr int LDS_ELEMS = (NPASS > 1) ? NC * N * L : 1;
+    static_assert(N % R == 0, "R must divide N");
+    static_assert(NPASS == 1 ? N == R : E >= 2, "schedule needs radix-R first and last passes");
+    static_assert(NT >= 1 && NT <= 1024, "workgroup size");
+
+    __host__ __device__ static constexpr int radix_of(int p) { return (p == 1 && REM > 1) ? REM : R; }
+    __host__ __device__ static constexpr int ns_of(int p) {
+        int ns = 1;
+        for (int q = 0; q < p; ++q) ns *= radix_of(q);
+        return ns;
+    }
+    __device__ static __forceinline__ int lidx(int l, int slot, int pos) {
+        if constexpr (COLS) return (slot * N + pos) * L + l;
+        else return (l * NC + slot) * N + pos;
+    }
+
+    // Exchange after pass PASS-1 and compute pass PASS (PASS >= 1).
+    template <bool INV, int PASS>
+    __device__ static __forceinline__ void pass(cpx<T> (&v)[2][R], cpx<T>* lds, int l, int j,
+                                                const cpx<T>* __restrict__ tw) {
+        constexpr int Rq = radix_of(PASS - 1), Nq = ns_of(PASS - 1);
+        constexpr int Rp = radix_of(PASS), Ns = ns_of(PASS);
+#pragma unroll
+        for (int cg = 0; cg < 2 / NC; ++cg) {
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) {
+                const int comp = cg * NC + cc;
+#pragma unroll
+                for (int t = 0; t < R / Rq; ++t) {
+                    const int jj = j + t * P;
+                    const int base = (jj / Nq) * Nq * Rq + (jj % Nq);
+#pragma unroll
+                    for (int s = 0; s < Rq; ++s) lds[lidx(l, cc, base + s * Nq)] = v[comp][t * Rq + s];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int cc = 0; cc < NC; ++cc) {
+                const int comp = cg * NC + cc;
+#pragma unroll
+                for (int t = 0; t < R / Rp; ++t) {
+                    const int jj = j + t * P;
+#pragma unroll
+                    for (int r = 0; r < Rp; ++r) v[comp][t * Rp + r] = lds[lidx(l, cc, jj + r * (N / Rp))];
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < R / Rp; ++t) {
+            const int jj = j + t * P;
+            const int k = jj % Ns;
+#pragma unroll
+            for (int r = 1; r < Rp; ++r) {
+                const cpx<T> w = tw[r * k * (N / (Ns * Rp))];
+                v[0][t * Rp + r] = INV ? cmulc(v[0][t * Rp + r], w) : cmul(v[0][t * Rp + r], w);
+                v[1][t * Rp + r] = INV ? cmulc(v[1][t * Rp + r], w) : cmul(v[1][t * Rp + r], w);
+            }
+            dft<T, Rp, INV>(&v[0][t * Rp]);
+            dft<T, Rp, INV>(&v[1][t * Rp]);
+        }
+        if constexpr (PASS + 1 < NPASS) pass<INV, PASS + 1>(v, lds, l, j, tw);
+    }
+
+    // Transform both components of the line.  Entry: v[c][r] = position j + r P.
+    // Exit: v[c][s] = mode (forward) / position (inverse) j + s P.  tw[k] =
+    // exp(-2 pi i k / N); the inverse uses conjugates and is unnormalised.
+    template <bool INV>
+    __device__ static __forceinline__ void fft(cpx<T> (&v)[2][R], cpx<T>* lds, int l, int j,
+                                               const cpx<T>* __restrict__ tw) {
+        dft<T, R, INV>(v[0]);
+        dft<T, R, INV>(v[1]);
+        if constexpr (NPASS > 1) pass<INV, 1>(v, lds, l, j, tw);
+    }
+};
+
+}  // namespace dirac

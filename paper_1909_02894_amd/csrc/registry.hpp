@@ -1,0 +1,43 @@
+// registry.hpp -- compiled kernel variants of the direction and observable
+// kernels, registered per (precision, n, direction, schedule) by the
+// translation units that instantiate them.
+#pragma once
+#include <vector>
+
+namespace dirac {
+
+struct KernelEntry {
+    int prec;       // 0 = FP64, 1 = FP32
+    int n;          // transform length
+    int dir;        // 0 = x (rows), 1 = y (columns)
+    int radix;      // values per thread per component
+    int lines;      // lines per workgroup
+    int split;      // exchange one component at a time
+    int nthreads;   // workgroup size
+    const void* stage_fn;
+    const void* obs_fn;
+};
+
+std::vector<KernelEntry>& kernel_registry();
+
+struct Registrar {
+    Registrar(const KernelEntry& e) { kernel_registry().push_back(e); }
+};
+
+}  // namespace dirac
+
+// REG(N, R, L, SPLIT) inside a translation unit that defines DIRAC_T (double /
+// float), DIRAC_PREC (0/1), DIRAC_COLS (false/true), DIRAC_DIR (0/1).
+#define DIRAC_CAT2(a, b) a##b
+#define DIRAC_CAT(a, b) DIRAC_CAT2(a, b)
+#define DIRAC_REG_IMPL(N, R, L, SPLIT, OBS)                                                          \
+    static ::dirac::Registrar DIRAC_CAT(reg_, __LINE__)(::dirac::KernelEntry{                      \
+        DIRAC_PREC, N, DIRAC_DIR, R, L, SPLIT,                                                      \
+        ::dirac::LineFFT<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0)>::NT,                            \
+        reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0)>), \
+        OBS});
+// REG: a direction-kernel schedule.  REGO: the same plus the observable kernel
+// with that schedule (one per precision, n and direction).
+#define REG(N, R, L, SPLIT) DIRAC_REG_IMPL(N, R, L, SPLIT, nullptr)
+#define REGO(N, R, L, SPLIT) \
+    DIRAC_REG_IMPL(N, R, L, SPLIT, reinterpret_cast<const void*>(&::dirac::obs_kernel<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0)>))

@@ -1,0 +1,666 @@
+// runtime.hip -- the C ABI of libdirac: validation, device-buffer layout,
+// setup, the step launcher (direct or HIP-graph replay), observables,
+// conversions, schedules, timing and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dirac.h"
+#include "fft_line.hpp"
+#include "registry.hpp"
+#include "setup_kernels.hpp"
+#include "solver.hpp"
+#include "stage_kernels.hpp"
+
+namespace dirac {
+
+std::vector<KernelEntry>& kernel_registry() {
+    static std::vector<KernelEntry> r;
+    return r;
+}
+
+static thread_local std::string g_last_error;
+
+dirac_status fail(dirac_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+static dirac_status hip_fail(hipError_t e, const char* what) {
+    return fail(DIRAC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+#define HIP_TRY(expr, what)                                   \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) return hip_fail(e_, (what));    \
+    } while (0)
+
+static bool is_pow2_in_range(int n) { return n >= 16 && n <= 8192 && (n & (n - 1)) == 0; }
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------- validation
+
+dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec) {
+    if (!g || !m || !pml) return fail(DIRAC_E_ARG, "null grid, metric or pml");
+    if (prec != DIRAC_FP64 && prec != DIRAC_FP32) return fail(DIRAC_E_ARG, "precision must be 0 (FP64) or 1 (FP32)");
+    if (!is_pow2_in_range(g->n1) || !is_pow2_in_range(g->n2))
+        return fail(DIRAC_E_SIZE, "n1 = %d, n2 = %d: each must be a power of two in [16, 8192]", g->n1, g->n2);
+    if (!(g->a1 > 0) || !(g->a2 > 0) || !std::isfinite(g->a1) || !std::isfinite(g->a2))
+        return fail(DIRAC_E_ARG, "half-widths a1, a2 must be finite and > 0");
+    if (!(g->dt > 0) || !std::isfinite(g->dt)) return fail(DIRAC_E_ARG, "dt must be finite and > 0");
+    if (!(g->c > 0) || !std::isfinite(g->c)) return fail(DIRAC_E_ARG, "c must be finite and > 0");
+    if (!(g->m >= 0) || !std::isfinite(g->m)) return fail(DIRAC_E_ARG, "m must be finite and >= 0");
+    if (m->kind < 0 || m->kind > 3) return fail(DIRAC_E_ARG, "unknown metric kind %d", m->kind);
+    if (m->spin < 0 || m->spin > 2) return fail(DIRAC_E_ARG, "unknown spin selector %d", m->spin);
+    if (m->kind == DIRAC_METRIC_GAUSS_BUMP && (!(m->bump_s > 0) || !std::isfinite(m->bump_s) || !std::isfinite(m->bump_A)))
+        return fail(DIRAC_E_ARG, "bump_s must be finite and > 0, bump_A finite");
+    if (m->kind == DIRAC_METRIC_FIELDS &&
+        (!m->phi || !m->psi || !m->dphi_dx || !m->dphi_dy || !m->dpsi_dx || !m->dpsi_dy))
+        return fail(DIRAC_E_ARG, "FIELDS metric needs all six host arrays");
+    if (pml->width_pts < 0 || pml->width_pts > std::min(g->n1, g->n2) / 2)
+        return fail(DIRAC_E_ARG, "pml width %d outside [0, min(n1, n2)/2]", pml->width_pts);
+    if (pml->width_pts > 0) {
+        if (pml->type < 1 || pml->type > 6) return fail(DIRAC_E_ARG, "pml type must be 1..6");
+        if (!std::isfinite(pml->sigma0) || pml->sigma0 < 0) return fail(DIRAC_E_ARG, "pml sigma0 must be finite and >= 0");
+        if (!std::isfinite(pml->theta)) return fail(DIRAC_E_ARG, "pml theta must be finite");
+        if (std::fabs(std::sin(pml->theta)) > 0 && pml->sigma0 > 0)
+            return fail(DIRAC_E_UNSTABLE,
+                        "complex stretch (theta = %g) makes the blend coefficient complex; the directional "
+                        "step is stable only for real b in [0, 1]", pml->theta);
+    }
+    return DIRAC_OK;
+}
+
+Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec) {
+    Layout L{};
+    const size_t N = (size_t)g->n1 * g->n2;
+    const size_t sz = prec == DIRAC_FP32 ? 4 : 8;
+    const bool curved = m->kind != DIRAC_METRIC_FLAT;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    L.psi = take(N * 4 * sz);
+    L.a = curved ? take(N * sz) : SIZE_MAX;
+    L.E = curved ? take(N * 4 * sz) : SIZE_MAX;
+    L.obs = take(5 * N * 8);
+    L.fields = m->kind == DIRAC_METRIC_FIELDS ? take(6 * N * 8) : SIZE_MAX;
+    L.scratch = take(N * 4 * 8);
+    for (int ax = 0; ax < 2; ++ax) {
+        const size_t n = ax == 0 ? g->n1 : g->n2;
+        L.inv_s[ax] = take(n * sz);
+        L.K[ax] = take(n * 2 * sz);
+        L.D[ax] = take(n * sz);
+        L.tw[ax] = take(n * 2 * sz);
+    }
+    const size_t setup_parts = ((N + 255) / 256) * 3;
+    const size_t obs_parts = ((size_t)g->n1 + g->n2) * 8;
+    L.partials = take(std::max(setup_parts, obs_parts) * 8);
+    L.out = take(64 * 8);
+    L.total = off + 256;     // slack so that an unaligned caller buffer can be aligned up
+    (void)pml;
+    return L;
+}
+
+// ---------------------------------------------------------------- schedules
+
+const KernelEntry* find_entry(int prec, int n, int dir, const dirac_schedule& s) {
+    for (const auto& e : kernel_registry())
+        if (e.prec == prec && e.n == n && e.dir == dir && e.radix == s.radix && e.lines == s.lines_per_wg)
+            return &e;
+    return nullptr;
+}
+const KernelEntry* default_entry(int prec, int n, int dir) {
+    for (const auto& e : kernel_registry())
+        if (e.prec == prec && e.n == n && e.dir == dir) return &e;
+    return nullptr;
+}
+const KernelEntry* obs_entry(int prec, int n, int dir) {
+    for (const auto& e : kernel_registry())
+        if (e.prec == prec && e.n == n && e.dir == dir && e.obs_fn) return &e;
+    return nullptr;
+}
+
+struct TuneKey {
+    int prec, n, dir, other, mode;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(prec, n, dir, other, mode) < std::tie(o.prec, o.n, o.dir, o.other, o.mode);
+    }
+};
+struct TuneVal { int radix, lines; double ms; };
+static std::map<TuneKey, TuneVal>& tune_cache() { static std::map<TuneKey, TuneVal> c; return c; }
+static std::mutex& tune_mutex() { static std::mutex m; return m; }
+
+int solver_mode(const dirac_solver* s) { return (s->curved ? 2 : 0) + (s->pml ? 1 : 0); }
+
+const KernelEntry* pick_entry(int prec, int n, int dir, int other, int mode) {
+    {
+        std::lock_guard<std::mutex> lk(tune_mutex());
+        auto it = tune_cache().find(TuneKey{prec, n, dir, other, mode});
+        if (it != tune_cache().end()) {
+            dirac_schedule sc{it->second.radix, it->second.lines};
+            if (const KernelEntry* e = find_entry(prec, n, dir, sc)) return e;
+        }
+    }
+    return default_entry(prec, n, dir);
+}
+
+// ---------------------------------------------------------------- launches
+
+template <typename T>
+StageParams<T> stage_params(const dirac_solver* s, int dir, int e_pre, int e_post) {
+    StageParams<T> p{};
+    char* b = s->base;
+    p.psi = reinterpret_cast<T*>(b + s->lay.psi);
+    p.a = s->curved ? reinterpret_cast<const T*>(b + s->lay.a) : nullptr;
+    p.E = s->curved ? reinterpret_cast<const T*>(b + s->lay.E) : nullptr;
+    p.inv_s = s->pml ? reinterpret_cast<const T*>(b + s->lay.inv_s[dir]) : nullptr;
+    p.K = reinterpret_cast<const cpx<T>*>(b + s->lay.K[dir]);
+    p.tw = reinterpret_cast<const cpx<T>*>(b + s->lay.tw[dir]);
+    p.n1 = s->g.n1;
+    p.nlines = dir == 0 ? s->g.n2 : s->g.n1;
+    p.e_pre = e_pre;
+    p.e_post = e_post;
+    p.e0u = cpx<T>{(T)s->e0u_re, (T)s->e0u_im};
+    return p;
+}
+
+// One stage launch description (kernel + by-value parameter block).
+struct Launch {
+    const void* fn;
+    dim3 grid, block;
+    alignas(16) unsigned char params[sizeof(StageParams<double>)];
+    size_t psize;
+};
+
+Launch make_launch(const dirac_solver* s, int dir, int e_pre, int e_post) {
+    Launch L{};
+    const KernelEntry* e = s->sched[dir];
+    const int nlines = dir == 0 ? s->g.n2 : s->g.n1;
+    L.fn = e->stage_fn;
+    L.grid = dim3((nlines + e->lines - 1) / e->lines);
+    L.block = dim3(e->nthreads);
+    if (s->prec == DIRAC_FP64) {
+        auto p = stage_params<double>(s, dir, e_pre, e_post);
+        std::memcpy(L.params, &p, sizeof p);
+        L.psize = sizeof p;
+    } else {
+        auto p = stage_params<float>(s, dir, e_pre, e_post);
+        std::memcpy(L.params, &p, sizeof p);
+        L.psize = sizeof p;
+    }
+    return L;
+}
+
+static hipError_t do_launch(Launch& L, hipStream_t st) {
+    void* args[] = {L.params};
+    return hipLaunchKernel(L.fn, L.grid, L.block, args, 0, st);
+}
+
+static void drop_graph(dirac_solver* s) {
+    if (s->gexec) { (void)hipGraphExecDestroy(s->gexec); s->gexec = nullptr; }
+    if (s->graph) { (void)hipGraphDestroy(s->graph); s->graph = nullptr; }
+}
+
+// Graph of `chunk` middle steps: [y (no Step 5), x (Step 5 + Step 1)] repeated.
+static dirac_status build_graph(dirac_solver* s) {
+    drop_graph(s);
+    HIP_TRY(hipGraphCreate(&s->graph, 0), "hipGraphCreate");
+    Launch ly = make_launch(s, 1, 0, 0);
+    Launch lx = make_launch(s, 0, 2, 0);
+    hipGraphNode_t prev = nullptr;
+    for (int c = 0; c < s->graph_chunk; ++c) {
+        for (Launch* L : {&ly, &lx}) {
+            void* args[] = {L->params};
+            hipKernelNodeParams kp{};
+            kp.func = const_cast<void*>(L->fn);
+            kp.gridDim = L->grid;
+            kp.blockDim = L->block;
+            kp.sharedMemBytes = 0;
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            HIP_TRY(hipGraphAddKernelNode(&node, s->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp),
+                    "hipGraphAddKernelNode");
+            prev = node;
+        }
+    }
+    HIP_TRY(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    return DIRAC_OK;
+}
+
+// Enqueue nsteps steps: x(E once) y, then (y, x(E twice)) pairs, then y(+E).
+dirac_status enqueue_steps(dirac_solver* s, int64_t nsteps, bool allow_graph) {
+    if (nsteps <= 0) return DIRAC_OK;
+    hipStream_t st = s->stream;
+    Launch x1 = make_launch(s, 0, 1, 0);
+    HIP_TRY(do_launch(x1, st), "launch x stage");
+    int64_t middle = nsteps - 1;     // number of (y, x(E E)) pairs
+    if (allow_graph && s->use_graph && middle >= s->graph_chunk) {
+        if (!s->gexec) {
+            dirac_status r = build_graph(s);
+            if (r != DIRAC_OK) return r;
+        }
+        while (middle >= s->graph_chunk) {
+            HIP_TRY(hipGraphLaunch(s->gexec, st), "hipGraphLaunch");
+            middle -= s->graph_chunk;
+        }
+    }
+    if (middle > 0) {
+        Launch y0 = make_launch(s, 1, 0, 0);
+        Launch x2 = make_launch(s, 0, 2, 0);
+        for (int64_t k = 0; k < middle; ++k) {
+            HIP_TRY(do_launch(y0, st), "launch y stage");
+            HIP_TRY(do_launch(x2, st), "launch x stage");
+        }
+    }
+    Launch y1 = make_launch(s, 1, 0, 1);
+    HIP_TRY(do_launch(y1, st), "launch y stage");
+    return DIRAC_OK;
+}
+
+}  // namespace dirac
+
+using namespace dirac;
+
+// ============================================================== C ABI
+
+extern "C" {
+
+const char* dirac_last_error(void) { return g_last_error.c_str(); }
+
+size_t dirac_footprint_bytes(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec) {
+    if (validate(g, m, pml, prec) != DIRAC_OK) return 0;
+    return make_layout(g, m, pml, prec).total;
+}
+
+dirac_status dirac_create_metric(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml,
+                                 int32_t prec, void* device_buffer, size_t bytes, void* hip_stream,
+                                 dirac_solver** out) {
+    g_last_error.clear();
+    if (!out) return fail(DIRAC_E_ARG, "null output handle");
+    *out = nullptr;
+    dirac_status st = validate(g, m, pml, prec);
+    if (st != DIRAC_OK) return st;
+    if (!device_buffer) return fail(DIRAC_E_ARG, "null device buffer");
+    Layout lay = make_layout(g, m, pml, prec);
+    if (bytes < lay.total)
+        return fail(DIRAC_E_SIZE, "device buffer of %zu bytes < footprint %zu", bytes, lay.total);
+    for (int dir = 0; dir < 2; ++dir) {
+        const int n = dir == 0 ? g->n1 : g->n2;
+        if (!default_entry(prec, n, dir) || !obs_entry(prec, n, dir))
+            return fail(DIRAC_E_SIZE, "no compiled kernel for n = %d (precision %d, direction %d)", n, prec, dir);
+    }
+    // Check the pointer is device memory of the current device.
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, device_buffer) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(DIRAC_E_ARG, "device_buffer is not device memory");
+    }
+    dirac_solver* s = new (std::nothrow) dirac_solver();
+    if (!s) return fail(DIRAC_E_NOMEM, "host allocation failed");
+    s->g = *g;
+    s->metric = *m;
+    s->metric.phi = s->metric.psi = s->metric.dphi_dx = s->metric.dphi_dy = s->metric.dpsi_dx = s->metric.dpsi_dy = nullptr;
+    s->pmlp = *pml;
+    s->prec = prec;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    const uintptr_t raw = reinterpret_cast<uintptr_t>(device_buffer);
+    s->base = reinterpret_cast<char*>((raw + 255) & ~uintptr_t(255));
+    s->lay = lay;
+    s->curved = m->kind != DIRAC_METRIC_FLAT;
+    s->pml = pml->width_pts > 0;
+    const double mu = g->dt * g->m * g->c * g->c / 2.0;
+    s->e0u_re = std::cos(mu);
+    s->e0u_im = -std::sin(mu);
+    hipGetDevice(&s->device);
+
+    auto bail = [&](dirac_status r) { delete s; return r; };
+    const size_t N = (size_t)g->n1 * g->n2;
+    const bool fp32 = prec == DIRAC_FP32;
+    char* b = s->base;
+    if (m->kind == DIRAC_METRIC_FIELDS) {
+        const double* planes[6] = {m->phi, m->psi, m->dphi_dx, m->dphi_dy, m->dpsi_dx, m->dpsi_dy};
+        for (int k = 0; k < 6; ++k) {
+            hipError_t e = hipMemcpyAsync(b + lay.fields + k * N * 8, planes[k], N * 8, hipMemcpyHostToDevice, s->stream);
+            if (e != hipSuccess) return bail(hip_fail(e, "upload metric fields"));
+        }
+    }
+    for (int ax = 0; ax < 2; ++ax) {
+        SetupAxisParams ap{};
+        ap.n = ax == 0 ? g->n1 : g->n2;
+        ap.a = ax == 0 ? g->a1 : g->a2;
+        ap.c = g->c;
+        ap.dt = g->dt;
+        ap.pml_width = pml->width_pts;
+        ap.pml_type = pml->type;
+        ap.sigma0 = pml->sigma0;
+        ap.ctheta = std::cos(pml->theta);
+        ap.fp32 = fp32;
+        ap.inv_s = b + lay.inv_s[ax];
+        ap.K = b + lay.K[ax];
+        ap.D = b + lay.D[ax];
+        ap.tw = b + lay.tw[ax];
+        hipError_t e = launch_setup_axis(ap, s->stream);
+        if (e != hipSuccess) return bail(hip_fail(e, "setup axis tables"));
+    }
+    SetupPointParams pp{};
+    pp.n1 = g->n1; pp.n2 = g->n2; pp.a1 = g->a1; pp.a2 = g->a2;
+    pp.dt = g->dt; pp.c = g->c; pp.m = g->m;
+    pp.kind = m->kind; pp.spin = m->spin; pp.bump_A = m->bump_A; pp.bump_s = m->bump_s;
+    pp.fields = m->kind == DIRAC_METRIC_FIELDS ? reinterpret_cast<const double*>(b + lay.fields) : nullptr;
+    pp.pml_width = pml->width_pts; pp.pml_type = pml->type; pp.sigma0 = pml->sigma0;
+    pp.ctheta = std::cos(pml->theta);
+    pp.fp32 = fp32;
+    pp.a_out = s->curved ? b + lay.a : nullptr;
+    pp.E_out = s->curved ? b + lay.E : nullptr;
+    pp.obs = reinterpret_cast<double*>(b + lay.obs);
+    pp.partial = reinterpret_cast<double*>(b + lay.partials);
+    double* fold = reinterpret_cast<double*>(b + lay.out);
+    hipError_t e = launch_setup_points(pp, fold, s->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "setup point tables"));
+    double host_fold[3];
+    e = hipMemcpyAsync(host_fold, fold, sizeof host_fold, hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "read setup check"));
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return bail(hip_fail(e, "setup synchronise"));
+    if (host_fold[2] != 0.0)
+        return bail(fail(DIRAC_E_NONFINITE, "%.0f grid points have non-finite metric fields or tables", host_fold[2]));
+    if (host_fold[0] < 0.0 || host_fold[1] > 1.0 + 1e-12)
+        return bail(fail(DIRAC_E_UNSTABLE,
+                         "blend coefficient b = a/S ranges over [%.17g, %.17g]; the directional step is "
+                         "stable only for b in [0, 1]", host_fold[0], host_fold[1]));
+    s->b_min = host_fold[0];
+    s->b_max = host_fold[1];
+    const int mode = solver_mode(s);
+    s->sched[0] = pick_entry(prec, g->n1, 0, g->n2, mode);
+    s->sched[1] = pick_entry(prec, g->n2, 1, g->n1, mode);
+    *out = s;
+    return DIRAC_OK;
+}
+
+dirac_status dirac_set_initial_spinor(dirac_solver* s, const double* psi_host) {
+    if (!s || !psi_host) return fail(DIRAC_E_ARG, "null solver or spinor");
+    const size_t N = (size_t)s->g.n1 * s->g.n2;
+    for (size_t i = 0; i < 4 * N; ++i)
+        if (!std::isfinite(psi_host[i])) return fail(DIRAC_E_NONFINITE, "initial spinor has a non-finite value at real index %zu", i);
+    char* b = s->base;
+    if (s->prec == DIRAC_FP64) {
+        HIP_TRY(hipMemcpyAsync(b + s->lay.psi, psi_host, N * 32, hipMemcpyHostToDevice, s->stream), "upload spinor");
+    } else {
+        HIP_TRY(hipMemcpyAsync(b + s->lay.scratch, psi_host, N * 32, hipMemcpyHostToDevice, s->stream), "upload spinor");
+        HIP_TRY(launch_c128_to_f32(reinterpret_cast<const double*>(b + s->lay.scratch),
+                                   reinterpret_cast<float*>(b + s->lay.psi), 4 * N, s->stream), "convert spinor");
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream), "synchronise");
+    s->step = 0;
+    s->has_state = true;
+    return DIRAC_OK;
+}
+
+dirac_status dirac_set_initial_spinor_device(dirac_solver* s, const void* psi_dev) {
+    if (!s || !psi_dev) return fail(DIRAC_E_ARG, "null solver or spinor");
+    const size_t N = (size_t)s->g.n1 * s->g.n2;
+    char* b = s->base;
+    if (s->prec == DIRAC_FP64) {
+        HIP_TRY(hipMemcpyAsync(b + s->lay.psi, psi_dev, N * 32, hipMemcpyDeviceToDevice, s->stream), "copy spinor");
+    } else {
+        HIP_TRY(launch_c128_to_f32(static_cast<const double*>(psi_dev), reinterpret_cast<float*>(b + s->lay.psi),
+                                   4 * N, s->stream), "convert spinor");
+    }
+    s->step = 0;
+    s->has_state = true;
+    return DIRAC_OK;
+}
+
+dirac_status dirac_step_n(dirac_solver* s, int64_t nsteps) {
+    if (!s) return fail(DIRAC_E_ARG, "null solver");
+    if (nsteps < 0) return fail(DIRAC_E_ARG, "nsteps must be >= 0");
+    if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
+    dirac_status r = enqueue_steps(s, nsteps, true);
+    if (r != DIRAC_OK) return r;
+    s->step += nsteps;
+    return DIRAC_OK;
+}
+
+dirac_status dirac_observables(dirac_solver* s, dirac_obs* out) {
+    if (!s || !out) return fail(DIRAC_E_ARG, "null solver or output");
+    if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
+    const size_t N = (size_t)s->g.n1 * s->g.n2;
+    char* b = s->base;
+    ObsParams p{};
+    p.psi = b + s->lay.psi;
+    const double* obs = reinterpret_cast<const double*>(b + s->lay.obs);
+    p.w = obs; p.ca = obs + N; p.gx = obs + 2 * N; p.gy = obs + 3 * N; p.V = obs + 4 * N;
+    p.n1 = s->g.n1; p.n2 = s->g.n2;
+    p.a1 = s->g.a1; p.a2 = s->g.a2;
+    p.h1 = 2.0 * s->g.a1 / s->g.n1; p.h2 = 2.0 * s->g.a2 / s->g.n2;
+    double* parts = reinterpret_cast<double*>(b + s->lay.partials);
+    int nparts = 0;
+    for (int dir = 0; dir < 2; ++dir) {
+        const KernelEntry* e = obs_entry(s->prec, dir == 0 ? s->g.n1 : s->g.n2, dir);
+        p.nlines = dir == 0 ? s->g.n2 : s->g.n1;
+        p.D = b + s->lay.D[dir];
+        p.tw = b + s->lay.tw[dir];
+        p.partials = parts + 8 * (size_t)nparts;
+        const int nb = (p.nlines + e->lines - 1) / e->lines;
+        void* args[] = {&p};
+        HIP_TRY(hipLaunchKernel(e->obs_fn, dim3(nb), dim3(e->nthreads), args, 0, s->stream), "launch observables");
+        nparts += nb;
+    }
+    double* dout = reinterpret_cast<double*>(b + s->lay.out);
+    HIP_TRY(launch_reduce_partials(parts, nparts, dout, s->stream), "reduce observables");
+    double h[8];
+    HIP_TRY(hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s->stream), "read observables");
+    HIP_TRY(hipStreamSynchronize(s->stream), "synchronise");
+    const double dA = (2.0 * s->g.a1 / s->g.n1) * (2.0 * s->g.a2 / s->g.n2);
+    out->step = s->step;
+    out->t = s->step * s->g.dt;
+    out->norm_l2 = dA * h[0];
+    out->norm_w = dA * h[1];
+    out->x_mean = h[2] / h[0];
+    out->y_mean = h[3] / h[0];
+    out->energy_re = dA * h[4];
+    out->energy_im = dA * h[5];
+    out->finite = h[6] == 0.0 && std::isfinite(h[0]);
+    out->reserved = 0;
+    return DIRAC_OK;
+}
+
+dirac_status dirac_get_spinor(dirac_solver* s, double* psi_host_out) {
+    if (!s || !psi_host_out) return fail(DIRAC_E_ARG, "null solver or output");
+    if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
+    const size_t N = (size_t)s->g.n1 * s->g.n2;
+    char* b = s->base;
+    if (s->prec == DIRAC_FP64) {
+        HIP_TRY(hipMemcpyAsync(psi_host_out, b + s->lay.psi, N * 32, hipMemcpyDeviceToHost, s->stream), "download spinor");
+    } else {
+        HIP_TRY(launch_f32_to_c128(reinterpret_cast<const float*>(b + s->lay.psi),
+                                   reinterpret_cast<double*>(b + s->lay.scratch), 4 * N, s->stream), "convert spinor");
+        HIP_TRY(hipMemcpyAsync(psi_host_out, b + s->lay.scratch, N * 32, hipMemcpyDeviceToHost, s->stream), "download spinor");
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream), "synchronise");
+    return DIRAC_OK;
+}
+
+dirac_status dirac_destroy(dirac_solver* s) {
+    if (!s) return fail(DIRAC_E_ARG, "null solver");
+    drop_graph(s);
+    for (auto& ev : s->events) (void)hipEventDestroy(ev);
+    delete s;
+    return DIRAC_OK;
+}
+
+// ------------------------------------------------------------- schedules
+
+int32_t dirac_schedule_count(int32_t n, int32_t prec, int32_t dir) {
+    int c = 0;
+    for (const auto& e : kernel_registry()) c += (e.prec == prec && e.n == n && e.dir == dir);
+    return c;
+}
+
+dirac_status dirac_schedule_get(int32_t n, int32_t prec, int32_t dir, int32_t i, dirac_schedule* out) {
+    if (!out) return fail(DIRAC_E_ARG, "null output");
+    int c = 0;
+    for (const auto& e : kernel_registry()) {
+        if (e.prec == prec && e.n == n && e.dir == dir) {
+            if (c == i) { out->radix = e.radix; out->lines_per_wg = e.lines; return DIRAC_OK; }
+            ++c;
+        }
+    }
+    return fail(DIRAC_E_ARG, "no schedule %d for n = %d", i, n);
+}
+
+dirac_status dirac_get_schedule(const dirac_solver* s, int32_t dir, dirac_schedule* out) {
+    if (!s || !out || dir < 0 || dir > 1) return fail(DIRAC_E_ARG, "bad arguments");
+    out->radix = s->sched[dir]->radix;
+    out->lines_per_wg = s->sched[dir]->lines;
+    return DIRAC_OK;
+}
+
+dirac_status dirac_set_schedule(dirac_solver* s, int32_t dir, const dirac_schedule* sch) {
+    if (!s || !sch || dir < 0 || dir > 1) return fail(DIRAC_E_ARG, "bad arguments");
+    const KernelEntry* e = find_entry(s->prec, dir == 0 ? s->g.n1 : s->g.n2, dir, *sch);
+    if (!e) return fail(DIRAC_E_ARG, "schedule radix %d lines %d not compiled", sch->radix, sch->lines_per_wg);
+    s->sched[dir] = e;
+    drop_graph(s);
+    return DIRAC_OK;
+}
+
+dirac_status dirac_set_launch_mode(dirac_solver* s, int32_t use_graph, int32_t chunk) {
+    if (!s || chunk < 1 || chunk > 4096) return fail(DIRAC_E_ARG, "bad arguments");
+    s->use_graph = use_graph != 0;
+    s->graph_chunk = chunk;
+    drop_graph(s);
+    return DIRAC_OK;
+}
+
+dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out, int64_t* counts_out) {
+    if (!s || !ms_out || !counts_out) return fail(DIRAC_E_ARG, "null argument");
+    if (nsteps < 0) return fail(DIRAC_E_ARG, "nsteps must be >= 0");
+    if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
+    ms_out[0] = ms_out[1] = 0.0;
+    counts_out[0] = counts_out[1] = 0;
+    if (nsteps == 0) return DIRAC_OK;
+    const size_t nl = (size_t)nsteps * 2;
+    while (s->events.size() < 2 * nl) {
+        hipEvent_t ev;
+        HIP_TRY(hipEventCreate(&ev), "hipEventCreate");
+        s->events.push_back(ev);
+    }
+    hipStream_t st = s->stream;
+    size_t k = 0;
+    std::vector<int> kind;
+    kind.reserve(nl);
+    for (int64_t n = 0; n < nsteps; ++n) {
+        Launch lx = make_launch(s, 0, n == 0 ? 1 : 2, 0);
+        Launch ly = make_launch(s, 1, 0, n == nsteps - 1 ? 1 : 0);
+        HIP_TRY(hipEventRecord(s->events[2 * k], st), "hipEventRecord");
+        HIP_TRY(do_launch(lx, st), "launch x stage");
+        HIP_TRY(hipEventRecord(s->events[2 * k + 1], st), "hipEventRecord");
+        kind.push_back(0); ++k;
+        HIP_TRY(hipEventRecord(s->events[2 * k], st), "hipEventRecord");
+        HIP_TRY(do_launch(ly, st), "launch y stage");
+        HIP_TRY(hipEventRecord(s->events[2 * k + 1], st), "hipEventRecord");
+        kind.push_back(1); ++k;
+    }
+    HIP_TRY(hipStreamSynchronize(st), "synchronise");
+    for (size_t i = 0; i < k; ++i) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, s->events[2 * i], s->events[2 * i + 1]), "hipEventElapsedTime");
+        ms_out[kind[i]] += ms;
+        counts_out[kind[i]] += 1;
+    }
+    s->step += nsteps;
+    return DIRAC_OK;
+}
+
+dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
+    if (!s || reps < 1) return fail(DIRAC_E_ARG, "bad arguments");
+    if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
+    const size_t N = (size_t)s->g.n1 * s->g.n2;
+    const size_t bytes = N * 4 * (s->prec == DIRAC_FP32 ? 4 : 8);
+    char* b = s->base;
+    HIP_TRY(hipMemcpyAsync(b + s->lay.scratch, b + s->lay.psi, bytes, hipMemcpyDeviceToDevice, s->stream), "save state");
+    const int64_t step0 = s->step;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    const int mode = solver_mode(s);
+    dirac_status result = DIRAC_OK;
+    for (int dir = 0; dir < 2 && result == DIRAC_OK; ++dir) {
+        const int n = dir == 0 ? s->g.n1 : s->g.n2;
+        const int other = dir == 0 ? s->g.n2 : s->g.n1;
+        const KernelEntry* best = s->sched[dir];
+        double best_ms = 1e300;
+        for (const auto& e : kernel_registry()) {
+            if (e.prec != s->prec || e.n != n || e.dir != dir) continue;
+            s->sched[dir] = &e;
+            // warm-up then timed
+            if ((result = enqueue_steps(s, 2, false)) != DIRAC_OK) break;
+            hipEventRecord(e0, s->stream);
+            if ((result = enqueue_steps(s, reps, false)) != DIRAC_OK) break;
+            hipEventRecord(e1, s->stream);
+            if (hipEventSynchronize(e1) != hipSuccess) { result = fail(DIRAC_E_DEVICE, "autotune sync"); break; }
+            float ms = 0;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best = &e; }
+        }
+        s->sched[dir] = best;
+        std::lock_guard<std::mutex> lk(tune_mutex());
+        tune_cache()[TuneKey{s->prec, n, dir, other, mode}] = TuneVal{best->radix, best->lines, best_ms / reps};
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    drop_graph(s);
+    HIP_TRY(hipMemcpyAsync(b + s->lay.psi, b + s->lay.scratch, bytes, hipMemcpyDeviceToDevice, s->stream), "restore state");
+    HIP_TRY(hipStreamSynchronize(s->stream), "synchronise");
+    s->step = step0;
+    return result;
+}
+
+dirac_status dirac_tune_cache_save(const char* path) {
+    if (!path) return fail(DIRAC_E_ARG, "null path");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(DIRAC_E_ARG, "cannot open %s", path);
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    std::fprintf(f, "# prec n dir other mode radix lines ms_per_step\n");
+    for (const auto& kv : tune_cache())
+        std::fprintf(f, "%d %d %d %d %d %d %d %.6g\n", kv.first.prec, kv.first.n, kv.first.dir, kv.first.other,
+                     kv.first.mode, kv.second.radix, kv.second.lines, kv.second.ms);
+    std::fclose(f);
+    return DIRAC_OK;
+}
+
+dirac_status dirac_tune_cache_load(const char* path) {
+    if (!path) return fail(DIRAC_E_ARG, "null path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(DIRAC_E_ARG, "cannot open %s", path);
+    char line[256];
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        TuneKey k{};
+        TuneVal v{};
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %lf", &k.prec, &k.n, &k.dir, &k.other, &k.mode, &v.radix,
+                        &v.lines, &v.ms) == 8)
+            tune_cache()[k] = v;
+    }
+    std::fclose(f);
+    return DIRAC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,23 @@
+// Direction-x (rows) kernel schedules, FP32, n = 16..256.  The first entry per n
+// is the default schedule and also carries the observable kernel.
+#include "stage_kernels.hpp"
+#include "registry.hpp"
+#define DIRAC_T float
+#define DIRAC_PREC 1
+#define DIRAC_COLS false
+#define DIRAC_DIR 0
+REGO(16, 4, 16, 0)
+REG(16, 4, 32, 0)
+REG(16, 16, 64, 0)
+REGO(32, 4, 8, 0)
+REG(32, 4, 16, 0)
+REGO(64, 8, 8, 0)
+REG(64, 8, 16, 0)
+REG(64, 4, 4, 0)
+REGO(128, 8, 4, 0)
+REG(128, 8, 8, 0)
+REG(128, 4, 2, 0)
+REGO(256, 16, 4, 0)
+REG(256, 16, 8, 0)
+REG(256, 8, 2, 0)
+REG(256, 8, 4, 0)

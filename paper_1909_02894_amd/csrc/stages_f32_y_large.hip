@@ -1,0 +1,23 @@
+// Direction-y (columns) kernel schedules, FP32, n = 512..8192.  The first entry per n
+// is the default schedule and also carries the observable kernel.
+#include "stage_kernels.hpp"
+#include "registry.hpp"
+#define DIRAC_T float
+#define DIRAC_PREC 1
+#define DIRAC_COLS true
+#define DIRAC_DIR 1
+REGO(512, 8, 8, 0)
+REG(512, 8, 4, 0)
+REG(512, 16, 8, 0)
+REG(512, 16, 16, 0)
+REGO(1024, 8, 4, 0)
+REG(1024, 8, 8, 0)
+REG(1024, 16, 4, 0)
+REG(1024, 16, 8, 0)
+REGO(2048, 8, 2, 0)
+REG(2048, 8, 4, 0)
+REG(2048, 16, 4, 0)
+REGO(4096, 16, 2, 0)
+REG(4096, 8, 2, 0)
+REGO(8192, 16, 1, 0)
+REG(8192, 8, 1, 0)

@@ -1,0 +1,278 @@
+"""Python binding of libdirac (ctypes over include/dirac.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+PyTorch provides the device buffer (a uint8 tensor) and the stream.  If the
+shared library is missing, importing this module raises ImportError -- there
+is no fallback path.
+
+Module-level functions carry the C names without the ``dirac_`` prefix
+(``create_metric``, ``set_initial_spinor``, ``step_n``, ``observables``,
+``get_spinor``, ``destroy``, ...); :class:`Solver` bundles them with a
+torch-allocated device buffer.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdirac.so")
+
+FP64, FP32 = 0, 1
+METRIC_FLAT, METRIC_GAUSS_BUMP, METRIC_PAPER_EXP3, METRIC_FIELDS = 0, 1, 2, 3
+SPIN_NONE, SPIN_PAPER, SPIN_2P1 = 0, 1, 2
+
+STATUS = {0: "DIRAC_OK", -1: "DIRAC_E_ARG", -2: "DIRAC_E_SIZE", -3: "DIRAC_E_UNSTABLE",
+          -4: "DIRAC_E_NOMEM", -5: "DIRAC_E_DEVICE", -6: "DIRAC_E_STATE", -7: "DIRAC_E_NONFINITE"}
+
+_dp = C.POINTER(C.c_double)
+
+
+class Grid(C.Structure):
+    _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("a1", C.c_double), ("a2", C.c_double),
+                ("dt", C.c_double), ("c", C.c_double), ("m", C.c_double)]
+
+
+class Metric(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("spin", C.c_int32), ("bump_A", C.c_double), ("bump_s", C.c_double),
+                ("phi", _dp), ("psi", _dp), ("dphi_dx", _dp), ("dphi_dy", _dp), ("dpsi_dx", _dp),
+                ("dpsi_dy", _dp)]
+
+
+class Pml(C.Structure):
+    _fields_ = [("width_pts", C.c_int32), ("type", C.c_int32), ("sigma0", C.c_double), ("theta", C.c_double)]
+
+
+class Obs(C.Structure):
+    _fields_ = [("step", C.c_int64), ("t", C.c_double), ("norm_l2", C.c_double), ("norm_w", C.c_double),
+                ("energy_re", C.c_double), ("energy_im", C.c_double), ("x_mean", C.c_double),
+                ("y_mean", C.c_double), ("finite", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Schedule(C.Structure):
+    _fields_ = [("radix", C.c_int32), ("lines_per_wg", C.c_int32)]
+
+
+class DiracError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+# Every symbol include/dirac.h declares: name -> (restype, argtypes)
+_vp = C.c_void_p
+SIGNATURES = {
+    "dirac_footprint_bytes": (C.c_size_t, [C.POINTER(Grid), C.POINTER(Metric), C.POINTER(Pml), C.c_int32]),
+    "dirac_create_metric": (C.c_int32, [C.POINTER(Grid), C.POINTER(Metric), C.POINTER(Pml), C.c_int32, _vp,
+                                        C.c_size_t, _vp, C.POINTER(_vp)]),
+    "dirac_set_initial_spinor": (C.c_int32, [_vp, _dp]),
+    "dirac_set_initial_spinor_device": (C.c_int32, [_vp, _vp]),
+    "dirac_step_n": (C.c_int32, [_vp, C.c_int64]),
+    "dirac_observables": (C.c_int32, [_vp, C.POINTER(Obs)]),
+    "dirac_get_spinor": (C.c_int32, [_vp, _dp]),
+    "dirac_destroy": (C.c_int32, [_vp]),
+    "dirac_last_error": (C.c_char_p, []),
+    "dirac_schedule_count": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
+    "dirac_schedule_get": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(Schedule)]),
+    "dirac_get_schedule": (C.c_int32, [_vp, C.c_int32, C.POINTER(Schedule)]),
+    "dirac_set_schedule": (C.c_int32, [_vp, C.c_int32, C.POINTER(Schedule)]),
+    "dirac_set_launch_mode": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
+    "dirac_step_n_timed": (C.c_int32, [_vp, C.c_int64, _dp, C.POINTER(C.c_int64)]),
+    "dirac_autotune": (C.c_int32, [_vp, C.c_int32]),
+    "dirac_tune_cache_save": (C.c_int32, [C.c_char_p]),
+    "dirac_tune_cache_load": (C.c_int32, [C.c_char_p]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1909_02894_amd.build` "
+                          "(there is no non-HIP fallback)")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return lib.dirac_last_error().decode()
+
+
+def _check(status):
+    if status != 0:
+        raise DiracError(status, last_error())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def make_structs(n1, n2, a1, a2, dt, c, m, metric=METRIC_FLAT, spin=SPIN_NONE, bump_A=0.0, bump_s=1.0,
+                 fields=None, pml_width=0, pml_type=1, pml_sigma0=1.0, pml_theta=0.0):
+    g = Grid(n1, n2, a1, a2, dt, c, m)
+    mt = Metric(kind=metric, spin=spin, bump_A=bump_A, bump_s=bump_s)
+    keep = []
+    if fields is not None:
+        names = ("phi", "psi", "dphi_dx", "dphi_dy", "dpsi_dx", "dpsi_dy")
+        for nm, arr in zip(names, fields):
+            arr = np.ascontiguousarray(arr, dtype=np.float64)
+            assert arr.shape == (n2, n1)
+            keep.append(arr)
+            setattr(mt, nm, _ptr(arr))
+    p = Pml(pml_width, pml_type, pml_sigma0, pml_theta)
+    return g, mt, p, keep
+
+
+def spec_structs(spec, fields=None):
+    """Structs for a workloads.SolveSpec."""
+    return make_structs(spec.n1, spec.n2, spec.a1, spec.a2, spec.dt, spec.c, spec.m, spec.metric, spec.spin,
+                        spec.bump_A, spec.bump_s, fields, spec.pml_width, spec.pml_type, spec.pml_sigma0,
+                        spec.pml_theta)
+
+
+# ---- C-named wrappers ---------------------------------------------------------
+
+def footprint_bytes(grid: Grid, metric: Metric, pml: Pml, precision: int) -> int:
+    return int(lib.dirac_footprint_bytes(C.byref(grid), C.byref(metric), C.byref(pml), precision))
+
+
+def create_metric(grid, metric, pml, precision, device_ptr: int, nbytes: int, stream_ptr: int | None):
+    h = _vp()
+    _check(lib.dirac_create_metric(C.byref(grid), C.byref(metric), C.byref(pml), precision, _vp(device_ptr),
+                                   nbytes, _vp(stream_ptr or 0), C.byref(h)))
+    return h
+
+
+def set_initial_spinor(h, psi: np.ndarray):
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    _check(lib.dirac_set_initial_spinor(h, psi.view(np.float64).ctypes.data_as(_dp)))
+
+
+def set_initial_spinor_device(h, dev_ptr: int):
+    _check(lib.dirac_set_initial_spinor_device(h, _vp(dev_ptr)))
+
+
+def step_n(h, nsteps: int):
+    _check(lib.dirac_step_n(h, int(nsteps)))
+
+
+def observables(h) -> dict:
+    o = Obs()
+    _check(lib.dirac_observables(h, C.byref(o)))
+    return o.as_dict()
+
+
+def get_spinor(h, n1: int, n2: int) -> np.ndarray:
+    out = np.empty((n2, n1, 2), dtype=np.complex128)
+    _check(lib.dirac_get_spinor(h, out.view(np.float64).ctypes.data_as(_dp)))
+    return out
+
+
+def destroy(h):
+    _check(lib.dirac_destroy(h))
+
+
+def schedules(n: int, precision: int, direction: int):
+    out = []
+    for i in range(lib.dirac_schedule_count(n, precision, direction)):
+        s = Schedule()
+        _check(lib.dirac_schedule_get(n, precision, direction, i, C.byref(s)))
+        out.append((s.radix, s.lines_per_wg))
+    return out
+
+
+def tune_cache_save(path: str):
+    _check(lib.dirac_tune_cache_save(path.encode()))
+
+
+def tune_cache_load(path: str):
+    _check(lib.dirac_tune_cache_load(path.encode()))
+
+
+# ---- convenience object ----------------------------------------------------------
+
+class Solver:
+    """One solve on a torch-allocated device buffer and torch's current stream."""
+
+    def __init__(self, n1, n2, a1, a2, dt, c=1.0, m=1.0, precision=FP64, metric=METRIC_FLAT, spin=SPIN_NONE,
+                 bump_A=0.0, bump_s=1.0, fields=None, pml_width=0, pml_type=1, pml_sigma0=1.0, pml_theta=0.0,
+                 device=None, stream=None):
+        import torch
+        self.n1, self.n2, self.precision = n1, n2, precision
+        self.grid, self.metric, self.pml, keep = make_structs(n1, n2, a1, a2, dt, c, m, metric, spin, bump_A,
+                                                              bump_s, fields, pml_width, pml_type, pml_sigma0,
+                                                              pml_theta)
+        self.nbytes = footprint_bytes(self.grid, self.metric, self.pml, precision)
+        if self.nbytes == 0:
+            raise DiracError(-1, last_error())
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream or torch.cuda.current_stream(device)
+        self.buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.h = None
+        self.h = create_metric(self.grid, self.metric, self.pml, precision, self.buffer.data_ptr(), self.nbytes,
+                               self.stream.cuda_stream)
+        del keep
+
+    @classmethod
+    def from_spec(cls, spec, precision=FP64, fields=None, **kw):
+        return cls(spec.n1, spec.n2, spec.a1, spec.a2, spec.dt, spec.c, spec.m, precision, spec.metric, spec.spin,
+                   spec.bump_A, spec.bump_s, fields, spec.pml_width, spec.pml_type, spec.pml_sigma0,
+                   spec.pml_theta, **kw)
+
+    def set_initial_spinor(self, psi):
+        set_initial_spinor(self.h, psi)
+
+    def set_initial_spinor_device(self, tensor):
+        assert tensor.is_contiguous() and tensor.numel() * tensor.element_size() == self.n1 * self.n2 * 32
+        set_initial_spinor_device(self.h, tensor.data_ptr())
+
+    def step_n(self, n):
+        step_n(self.h, n)
+
+    def observables(self):
+        return observables(self.h)
+
+    def get_spinor(self):
+        return get_spinor(self.h, self.n1, self.n2)
+
+    def schedule(self, direction):
+        s = Schedule()
+        _check(lib.dirac_get_schedule(self.h, direction, C.byref(s)))
+        return (s.radix, s.lines_per_wg)
+
+    def set_schedule(self, direction, radix, lines):
+        s = Schedule(radix, lines)
+        _check(lib.dirac_set_schedule(self.h, direction, C.byref(s)))
+
+    def set_launch_mode(self, use_graph: bool, chunk: int = 32):
+        _check(lib.dirac_set_launch_mode(self.h, int(use_graph), chunk))
+
+    def step_n_timed(self, n):
+        ms = (C.c_double * 2)()
+        cnt = (C.c_int64 * 2)()
+        _check(lib.dirac_step_n_timed(self.h, int(n), ms, cnt))
+        return [ms[0], ms[1]], [cnt[0], cnt[1]]
+
+    def autotune(self, reps=20):
+        _check(lib.dirac_autotune(self.h, reps))
+
+    def close(self):
+        if self.h is not None:
+            destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,88 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol include/dirac.h declares, sizes footprints and rejects invalid
+arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "dirac.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dirac_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for required in ("dirac_create_metric", "dirac_set_initial_spinor", "dirac_step_n", "dirac_observables",
+                     "dirac_get_spinor", "dirac_destroy", "dirac_footprint_bytes", "dirac_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1909_02894_amd import dirac as D
+    lib = ctypes.CDLL(D.LIB_PATH)
+    for name in header_functions():
+        assert hasattr(lib, name), name
+        assert name in D.SIGNATURES, f"binding lacks {name}"
+
+
+def test_footprint_and_validation():
+    from paper_1909_02894_amd import dirac as D
+    g, m, p, _ = D.make_structs(512, 512, 20.0, 20.0, 0.01, 1.0, 0.0, metric=D.METRIC_GAUSS_BUMP,
+                                spin=D.SPIN_2P1, bump_A=1.0, bump_s=3.0, pml_width=32)
+    f64 = D.footprint_bytes(g, m, p, D.FP64)
+    f32 = D.footprint_bytes(g, m, p, D.FP32)
+    N = 512 * 512
+    # state + a + E (T) + 5 FP64 observable planes + 32-byte staging per point
+    assert f64 >= N * (32 + 8 + 32 + 40 + 32) and f32 >= N * (16 + 4 + 16 + 40 + 32)
+    assert f32 < f64
+    gf, mf, pf, _ = D.make_structs(64, 64, 20.0, 20.0, 0.01, 1.0, 1.0)
+    assert D.footprint_bytes(gf, mf, pf, D.FP64) < D.footprint_bytes(*D.make_structs(64, 64, 20.0, 20.0, 0.01, 1.0, 1.0, metric=D.METRIC_PAPER_EXP3)[:3], D.FP64)
+
+    def create_status(**kw):
+        args = dict(n1=64, n2=64, a1=5.0, a2=5.0, dt=0.01, c=1.0, m=1.0)
+        args.update(kw)
+        g, m, p, keep = D.make_structs(**args)
+        h = ctypes.c_void_p()
+        return D.lib.dirac_create_metric(ctypes.byref(g), ctypes.byref(m), ctypes.byref(p), 0, None, 0, None,
+                                         ctypes.byref(h))
+
+    assert create_status(n1=48) == -2                 # not a power of two
+    assert create_status(n2=8) == -2                  # below 16
+    assert create_status(n1=16384) == -2              # above 8192
+    assert create_status(dt=0.0) == -1
+    assert create_status(c=-1.0) == -1
+    assert create_status(metric=7) == -1
+    assert create_status(metric=D.METRIC_FIELDS) == -1            # arrays missing
+    assert create_status(pml_width=40) == -1                      # wider than half the grid
+    assert create_status(pml_width=8, pml_type=9) == -1
+    assert create_status(pml_width=8, pml_theta=0.3) == -3        # complex stretch: unstable
+    assert "stable only for real b" in D.last_error()
+    assert create_status() == -1                                  # valid grid, null device buffer
+    assert "null device buffer" in D.last_error()
+
+
+def test_null_handles_are_rejected():
+    from paper_1909_02894_amd import dirac as D
+    assert D.lib.dirac_step_n(None, 1) == -1
+    assert D.lib.dirac_observables(None, None) == -1
+    assert D.lib.dirac_destroy(None) == -1
+
+
+def test_every_size_and_precision_has_kernels():
+    from paper_1909_02894_amd import dirac as D
+    for prec in (D.FP64, D.FP32):
+        for d in (0, 1):
+            for k in range(4, 13):
+                n = 1 << k
+                if prec == D.FP64 and n > 4096:
+                    continue
+                sch = D.schedules(n, prec, d)
+                assert sch, (prec, d, n)
+                for r, lines in sch:
+                    assert n % r == 0 and (n // r) * lines <= 1024

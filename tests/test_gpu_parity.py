@@ -1,0 +1,248 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (relative L2 over the whole state, rel = |x - ref|_2 / |ref|_2):
+* FP64 GPU vs FP64 oracle: 1e-11.  Both evaluate the same operations in
+  double precision; they differ only in rounding order (FFT factorisation,
+  FMA contraction, 1-ulp differences of exp/sin/cos), which grows like
+  steps * log2(n) * 1e-16 -- about 1e-12 after 2000 steps at n = 512.
+* FP32 GPU vs FP64 oracle: 2e-5 after 100 steps, 2e-4 after 1000 -- the
+  coherent FP32 rounding of the symbols and twiddles (2^-24 each, applied
+  every step) dominates: about steps * 2^-24 * (a few).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dirac_oracle as O
+from paper_1909_02894_amd import workloads as W
+from tests.helpers import oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_02894_amd import dirac
+    return dirac
+
+
+def gpu_run(D, spec, steps, precision=0, checkpoints=(), fields=None, psi0=None, **kw):
+    s = D.Solver.from_spec(spec, precision=precision, fields=fields, **kw)
+    s.set_initial_spinor(W.initial_spinor(spec) if psi0 is None else psi0)
+    out = {}
+    done = 0
+    for c in sorted(set(checkpoints) | {steps}):
+        s.step_n(c - done)
+        done = c
+        out[c] = s.get_spinor()
+    return s, out
+
+
+def oracle_run(spec, steps, checkpoints=(), fields=None, psi0=None):
+    T = O.build_tables(oracle_problem(spec, fields))
+    psi = W.initial_spinor(spec) if psi0 is None else psi0
+    out = {}
+    done = 0
+    for c in sorted(set(checkpoints) | {steps}):
+        psi = O.run(psi, T, c - done)
+        done = c
+        out[c] = psi
+    return T, out
+
+
+def test_flat_small_fp64_matches_oracle_and_exact_propagator(D):
+    spec = W.flat_small()
+    _, g = gpu_run(D, spec, 100, checkpoints=(1, 2, 37))
+    _, o = oracle_run(spec, 100, checkpoints=(1, 2, 37))
+    for k in (1, 2, 37, 100):
+        assert O.rel_l2(g[k], o[k]) < TOL64, k
+    ex = O.flat_exact_discrete(W.initial_spinor(spec), spec.n1, spec.n2, spec.a1, spec.a2, spec.m, spec.c,
+                               spec.dt, 100)
+    assert O.rel_l2(g[100], ex) < TOL64
+
+
+@pytest.mark.parametrize("m", [0.0, 1.0])
+def test_curved_bump_with_layer_fp64(D, m):
+    spec = W.curved_bump(n=64, steps=25, m=m)
+    _, g = gpu_run(D, spec, 25, checkpoints=(1, 5))
+    _, o = oracle_run(spec, 25, checkpoints=(1, 5))
+    for k in (1, 5, 25):
+        assert O.rel_l2(g[k], o[k]) < TOL64, k
+
+
+def test_paper_exp3_fp64(D):
+    spec = W.paper_exp3(n=128, steps=30)
+    _, g = gpu_run(D, spec, 30)
+    _, o = oracle_run(spec, 30)
+    assert O.rel_l2(g[30], o[30]) < TOL64
+
+
+@pytest.mark.parametrize("n1,n2,width", [(32, 128, 4), (256, 16, 3), (16, 16, 2), (1024, 32, 8)])
+def test_rectangular_and_small_grids(D, n1, n2, width):
+    spec = W.curved_bump(n=64, steps=6, m=0.7)
+    spec.n1, spec.n2, spec.pml_width = n1, n2, width
+    spec.a2 = 11.0
+    _, g = gpu_run(D, spec, 6)
+    _, o = oracle_run(spec, 6)
+    assert O.rel_l2(g[6], o[6]) < TOL64
+
+
+@pytest.mark.parametrize("ptype", [1, 2, 3, 4, 5, 6])
+def test_every_layer_type(D, ptype):
+    spec = W.curved_bump(n=64, steps=8, m=0.3)
+    spec.pml_type, spec.pml_sigma0, spec.pml_width = ptype, 0.4, 6
+    _, g = gpu_run(D, spec, 8)
+    _, o = oracle_run(spec, 8)
+    assert O.rel_l2(g[8], o[8]) < TOL64
+
+
+def smooth_fields(n1, n2, a1, a2, seed):
+    rng = np.random.default_rng(seed)
+    x = O.grid_points(n1, a1)
+    y = O.grid_points(n2, a2)
+    X, Y = np.meshgrid(x, y)
+    c1, c2, c3 = rng.uniform(0.05, 0.2, 3)
+    phi = -c1 * np.exp(-(X ** 2 + Y ** 2) / 20.0)
+    psi = c2 * np.exp(-((X - 1) ** 2 + Y ** 2) / 30.0) + c3 * 0.1
+    phx = phi * (-2 * X / 20.0)
+    phy = phi * (-2 * Y / 20.0)
+    psx = (psi - c3 * 0.1) * (-2 * (X - 1) / 30.0)
+    psy = (psi - c3 * 0.1) * (-2 * Y / 30.0)
+    return O.MetricFields(phi, psi, phx, phy, psx, psy)
+
+
+@pytest.mark.parametrize("spin", [0, 1, 2])
+def test_fields_metric(D, spin):
+    spec = W.flat_small(n=64, steps=10)
+    spec.metric, spec.spin, spec.m = W.METRIC_FIELDS, spin, 0.8
+    f = smooth_fields(64, 64, spec.a1, spec.a2, 3 + spin)
+    arr = (f.phi, f.psi, f.phi_x, f.phi_y, f.psi_x, f.psi_y)
+    _, g = gpu_run(D, spec, 10, fields=arr)
+    _, o = oracle_run(spec, 10, fields=f)
+    assert O.rel_l2(g[10], o[10]) < TOL64
+
+
+def test_curved_code_with_trivial_fields_equals_flat(D):
+    spec = W.flat_small(n=64, steps=20)
+    z = np.zeros((64, 64))
+    _, flat = gpu_run(D, spec, 20)
+    spec.metric = W.METRIC_FIELDS
+    _, curved = gpu_run(D, spec, 20, fields=(z, z, z, z, z, z))
+    assert O.rel_l2(curved[20], flat[20]) < 1e-14
+
+
+def test_observables_match_oracle(D):
+    spec = W.curved_bump(n=128, steps=15, m=1.0)
+    s, g = gpu_run(D, spec, 15)
+    T, o = oracle_run(spec, 15)
+    ob = s.observables()
+    ref = O.observables(o[15], T)
+    assert ob["step"] == 15 and abs(ob["t"] - 15 * spec.dt) < 1e-15
+    for k in ("norm_l2", "norm_w", "energy_re", "x_mean", "y_mean"):
+        assert abs(ob[k] - getattr(ref, k)) <= 1e-10 * max(1.0, abs(getattr(ref, k))), k
+    assert abs(ob["energy_im"] - ref.energy_im) <= 1e-10 * abs(ref.energy_re)
+    assert ob["finite"] == 1
+
+
+def test_observables_flat_exp3_and_nonfinite_flag(D):
+    import torch
+    spec = W.paper_exp3(n=64, steps=3)
+    s, g = gpu_run(D, spec, 3)
+    T, o = oracle_run(spec, 3)
+    ob, ref = s.observables(), O.observables(o[3], T)
+    for k in ("norm_l2", "norm_w", "energy_re", "energy_im", "x_mean", "y_mean"):
+        assert abs(ob[k] - getattr(ref, k)) <= 1e-10 * max(1.0, abs(ref.energy_re)), k
+    bad = W.initial_spinor(spec)
+    bad[5, 7, 1] = np.nan
+    with pytest.raises(D.DiracError) as ei:
+        s.set_initial_spinor(bad)
+    assert ei.value.status == -7
+    dev = torch.from_numpy(bad.view(np.float64).copy()).cuda()
+    s.set_initial_spinor_device(dev)
+    assert s.observables()["finite"] == 0
+
+
+def test_unstable_metric_is_rejected(D):
+    spec = W.flat_small(n=32, steps=1)
+    spec.metric = W.METRIC_FIELDS
+    z = np.zeros((32, 32))
+    phi = np.full((32, 32), 0.2)          # a = e^{Phi - Psi} > 1
+    with pytest.raises(D.DiracError) as ei:
+        D.Solver.from_spec(spec, fields=(phi, z, z, z, z, z))
+    assert ei.value.status == -3
+
+
+def test_step_splitting_graph_and_resume_are_bitwise(D):
+    spec = W.curved_bump(n=128, steps=70, m=0.5)
+    s1, a = gpu_run(D, spec, 70)
+    s2 = D.Solver.from_spec(spec)
+    s2.set_launch_mode(False)
+    s2.set_initial_spinor(W.initial_spinor(spec))
+    s2.step_n(33)
+    mid = s2.get_spinor()
+    s2.step_n(37)
+    assert np.array_equal(s2.get_spinor(), a[70])
+    s3 = D.Solver.from_spec(spec)
+    s3.set_launch_mode(True, 8)
+    s3.set_initial_spinor(mid)
+    s3.step_n(37)
+    assert np.array_equal(s3.get_spinor(), a[70])
+    s4, b = gpu_run(D, spec, 70)
+    assert np.array_equal(b[70], a[70])                      # run-to-run determinism
+    assert s4.observables() == s1.observables()
+
+
+def test_every_schedule_agrees(D):
+    spec = W.curved_bump(n=512, steps=3, m=1.0)
+    _, o = oracle_run(spec, 3)
+    results = {}
+    for d in (0, 1):
+        for (r, lines) in D.schedules(512, 0, d):
+            s = D.Solver.from_spec(spec)
+            s.set_schedule(d, r, lines)
+            s.set_initial_spinor(W.initial_spinor(spec))
+            s.step_n(3)
+            out = s.get_spinor()
+            assert O.rel_l2(out, o[3]) < TOL64, (d, r, lines)
+            results[(d, r, lines)] = out
+    # lines per workgroup never changes a bit
+    for (d, r, lines), out in results.items():
+        for (d2, r2, l2), out2 in results.items():
+            if d == d2 and r == r2:
+                assert np.array_equal(out, out2)
+
+
+def test_fp32_flat_against_exact_propagator(D):
+    spec = W.flat_small(n=256, steps=1000)
+    _, g = gpu_run(D, spec, 1000, precision=1, checkpoints=(100,))
+    psi0 = W.initial_spinor(spec)
+    for k, tol in ((100, 2e-5), (1000, 2e-4)):
+        ex = O.flat_exact_discrete(psi0, spec.n1, spec.n2, spec.a1, spec.a2, spec.m, spec.c, spec.dt, k)
+        assert O.rel_l2(g[k], ex) < tol, k
+
+
+def test_fp32_curved_against_oracle(D):
+    spec = W.curved_bump(n=128, steps=100, m=0.5)
+    _, g = gpu_run(D, spec, 100, precision=1)
+    _, o = oracle_run(spec, 100)
+    assert O.rel_l2(g[100], o[100]) < 2e-5
+
+
+def test_config2_full_size_short_and_long(D):
+    # 512^2 bump with the 32-point layer: element-wise parity for 20 steps, then
+    # properties over the full 2000 steps (finite, norm bounded, layer absorbs).
+    spec = W.curved_bump(n=512, steps=2000)
+    s, g = gpu_run(D, spec, 20)
+    _, o = oracle_run(spec, 20)
+    assert O.rel_l2(g[20], o[20]) < TOL64
+    ob0 = s.observables()
+    s.step_n(1980)
+    ob = s.observables()
+    assert ob["finite"] == 1 and ob["step"] == 2000
+    assert ob["norm_l2"] < ob0["norm_l2"] * 1.05
