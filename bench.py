@@ -1,0 +1,202 @@
+"""Throughput of the directional-split Dirac step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-variants] [--skip-cpu]
+
+Workload (the curved-graphene-shaped solve): 512 x 512 periodic grid on
+[-20,20)^2, static sheet over a Gaussian bump h = A exp(-r^2/s^2) with A, s
+drawn from seed 1909, absorbing layer of 32 points per side (type I, sigma0 = 1,
+theta = 0), massless, c = 1, dt = 0.01, Gaussian packet of width 2 at a seeded
+momentum; the state starts resident in HBM.  One "step" = Step 1 + x + y +
+Step 5 of the scheme over the whole grid.  The headline value is the FP64 path
+(complex128 state); the FP32 path (FP64-generated tables, FP64 reductions) and
+a large flat FP32 solve beyond the 256 MB Infinity Cache are reported beside it.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def bytes_per_point(kind: str, dir_: int, precision: int) -> int:
+    """Algorithmic HBM bytes per grid point of one direction-kernel launch in the
+    steady state (state read + written once; per-point tables read once; the
+    O(n) per-axis tables are not counted).  x: psi r/w + E + a; y: psi r/w + a."""
+    sz = 8 if precision == 0 else 4
+    state = 2 * 4 * sz
+    if kind == "flat":
+        return state
+    if kind == "flat_pml":
+        return state
+    return state + (4 * sz + sz if dir_ == 0 else sz)
+
+
+def kernel_sources_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1909_02894_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name: str):
+    """HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+    (profiles/traffic.json), or None when absent or taken on other kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_sources") != kernel_sources_digest():
+        return None
+    return d.get("kernels", {}).get(name)
+
+
+def time_solve(D, spec, precision, steps, warmup, timed_steps):
+    import torch
+    s = D.Solver.from_spec(spec, precision=precision)
+    from paper_1909_02894_amd import workloads as W
+    psi0 = torch.from_numpy(W.initial_spinor(spec).view(np.float64).copy()).cuda()
+    s.set_initial_spinor_device(psi0)
+    torch.cuda.synchronize()
+    s.step_n(warmup)
+    torch.cuda.synchronize()
+    st = s.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(st)
+    s.step_n(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    obs = s.observables()
+    # per-kernel durations (one launch per stage, HIP events around each launch)
+    kms, cnt = s.step_n_timed(timed_steps)
+    sched = (s.schedule(0), s.schedule(1))
+    s.close()
+    return dict(ms=ms, wall=wall, obs=obs, kernel_ms=kms, kernel_count=cnt, sched=sched)
+
+
+def roofline_for(spec, kind, precision, r):
+    N = spec.n1 * spec.n2
+    avg = [r["kernel_ms"][d] / max(1, r["kernel_count"][d]) for d in (0, 1)]
+    dom = 0 if r["kernel_ms"][0] >= r["kernel_ms"][1] else 1
+    byt = bytes_per_point(kind, dom, precision) * N
+    achieved = byt / (avg[dom] * 1e-3) / 1e9
+    name = f"{'x' if dom == 0 else 'y'}_stage_{'f64' if precision == 0 else 'f32'}_{spec.n1}x{spec.n2}_{kind}"
+    tr = load_traffic(name)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
+            "kernel": name, "avg_launch_us": round(avg[dom] * 1e3, 3),
+            "algorithmic_bytes_per_launch": byt,
+            "x_avg_us": round(avg[0] * 1e3, 3), "y_avg_us": round(avg[1] * 1e3, 3)}
+
+
+def cpu_baseline(spec, steps):
+    from oracle import dirac_oracle as O
+    from paper_1909_02894_amd import workloads as W
+    from tests.helpers import oracle_problem
+    T = O.build_tables(oracle_problem(spec))
+    psi = W.initial_spinor(spec)
+    t0 = time.perf_counter()
+    O.run(psi, T, steps)
+    dt = time.perf_counter() - t0
+    return {"value": spec.n1 * spec.n2 * steps / dt, "unit": "grid-point*steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of the same {spec.n1}x{spec.n2} curved solve (NumPy complex128, "
+                      f"single-threaded pocketfft); host has {os.cpu_count()} logical CPUs",
+            "seconds": round(dt, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--skip-variants", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=120)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB three times (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); a multi-GPU form of this solver is "
+              "not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1909_02894_amd import dirac as D
+    from paper_1909_02894_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": 1 << 30, "copies": 3}), flush=True)
+        return
+    spec = W.curved_bump(n=512, seed=1909, steps=args.steps)
+    K = args.steps
+    timed = min(K, 500)
+    r64 = time_solve(D, spec, D.FP64, K, args.warmup, timed)
+    N = spec.n1 * spec.n2
+    value = N * K / (r64["ms"] * 1e-3)
+    out = {
+        "metric": "grid-point*steps/s on 1 MI355X (FP32 vs FP64), % HBM peak; p50/p99 latency",
+        "value": value,
+        "unit": "grid-point*steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms"] / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "curved bump 512x512, seed 1909, 32-point type-I layer, m=0, dt=0.01, FP64",
+                   "grid": [spec.n1, spec.n2], "bump_A": round(spec.bump_A, 6), "bump_s": round(spec.bump_s, 6),
+                   "k0": [round(k, 6) for k in spec.k0], "schedule": {"x": r64["sched"][0], "y": r64["sched"][1]}},
+        "roofline": roofline_for(spec, "curved", D.FP64, r64),
+    }
+    variants = {}
+    if not args.skip_variants:
+        r32 = time_solve(D, spec, D.FP32, K, args.warmup, timed)
+        variants["fp32_same_workload"] = {
+            "value": N * K / (r32["ms"] * 1e-3), "ms_per_step": r32["ms"] / K, "dtype": "f32",
+            "roofline": roofline_for(spec, "curved", D.FP32, r32),
+            "schedule": {"x": r32["sched"][0], "y": r32["sched"][1]}}
+        big = W.flat_small(n=4096, steps=200)
+        rb = time_solve(D, big, D.FP32, 200, 10, 100)
+        variants["fp32_flat_4096"] = {
+            "value": big.n1 * big.n2 * 200 / (rb["ms"] * 1e-3), "ms_per_step": rb["ms"] / 200, "dtype": "f32",
+            "note": "flat 4096x4096 packet solve, 256 MiB state (beyond the Infinity Cache)",
+            "roofline": roofline_for(big, "flat", D.FP32, rb),
+            "schedule": {"x": rb["sched"][0], "y": rb["sched"][1]}}
+    out["variants"] = variants
+    if not args.skip_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
