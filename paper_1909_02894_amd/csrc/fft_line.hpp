@@ -125,7 +125,13 @@ struct LineFFT {
     static constexpr int REM = N / ipow(R, E);
     static constexpr int NPASS = E + (REM > 1 ? 1 : 0);
     static constexpr int NC = SPLIT ? 1 : 2;
-    static constexpr int LDS_ELEMS = (NPASS > 1) ? NC * N * L : 1;
+    // LDS layout, padded against bank conflicts: rows keep each (line, component)
+    // run contiguous with one pad element after every R elements (the first
+    // exchange writes with stride R); columns interleave the L lines of a position
+    // and add one pad element every 16.
+    static constexpr int ROW_STRIDE = N + N / R;
+    static constexpr int COL_RAW = NC * N * L;
+    static constexpr int LDS_ELEMS = (NPASS > 1) ? (COLS ? COL_RAW + COL_RAW / 16 : L * NC * ROW_STRIDE) : 1;
     static_assert(N % R == 0, "R must divide N");
     static_assert(NPASS == 1 ? N == R : E >= 2, "schedule needs radix-R first and last passes");
     static_assert(NT >= 1 && NT <= 1024, "workgroup size");
@@ -137,8 +143,12 @@ struct LineFFT {
         return ns;
     }
     __device__ static __forceinline__ int lidx(int l, int slot, int pos) {
-        if constexpr (COLS) return (slot * N + pos) * L + l;
-        else return (l * NC + slot) * N + pos;
+        if constexpr (COLS) {
+            const int a = (slot * N + pos) * L + l;
+            return a + a / 16;
+        } else {
+            return (l * NC + slot) * ROW_STRIDE + pos + pos / R;
+        }
     }
 
     // Exchange after pass PASS-1 and compute pass PASS (PASS >= 1).

@@ -14,7 +14,7 @@ struct KernelEntry {
     int lines;      // lines per workgroup
     int split;      // exchange one component at a time
     int nthreads;   // workgroup size
-    const void* stage_fn;
+    const void* stage_fn[3];   // by mode: 0 flat, 1 flat + layer, 2 curved
     const void* obs_fn;
 };
 
@@ -34,7 +34,9 @@ struct Registrar {
     static ::dirac::Registrar DIRAC_CAT(reg_, __LINE__)(::dirac::KernelEntry{                      \
         DIRAC_PREC, N, DIRAC_DIR, R, L, SPLIT,                                                      \
         ::dirac::LineFFT<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0)>::NT,                            \
-        reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0)>), \
+        {reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0), 0>), \
+         reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0), 1>), \
+         reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0), 2>)}, \
         OBS});
 // REG: a direction-kernel schedule.  REGO: the same plus the observable kernel
 // with that schedule (one per precision, n and direction).

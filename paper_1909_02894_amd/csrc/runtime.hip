@@ -190,7 +190,7 @@ Launch make_launch(const dirac_solver* s, int dir, int e_pre, int e_post) {
     Launch L{};
     const KernelEntry* e = s->sched[dir];
     const int nlines = dir == 0 ? s->g.n2 : s->g.n1;
-    L.fn = e->stage_fn;
+    L.fn = e->stage_fn[s->curved ? 2 : (s->pml ? 1 : 0)];
     L.grid = dim3((nlines + e->lines - 1) / e->lines);
     L.block = dim3(e->nthreads);
     if (s->prec == DIRAC_FP64) {

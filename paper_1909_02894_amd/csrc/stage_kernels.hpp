@@ -89,55 +89,96 @@ __device__ __forceinline__ void apply_Ediag(cpx<T>& u, cpx<T>& v, cpx<T> e0) {
     v = cmulc(v, e0);
 }
 
-template <typename T, int N, int R, int L, bool COLS, bool SPLIT>
+// Workgroup -> tile map that keeps neighbouring tiles on one XCD.  Workgroups
+// are dispatched round-robin over the 8 XCDs, each with its own L2; tiles that
+// share cache lines (adjacent column tiles, adjacent rows of the per-point
+// tables) are given to consecutive workgroups of the same XCD.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    const int x = b & 7, k = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Small twiddle tables are staged in LDS at kernel start (one coalesced read)
+// so the per-pass twiddle reads do not sit on the critical path.
+template <typename T, int N>
+struct TwStage {
+    static constexpr bool ON = N * sizeof(cpx<T>) <= 16384;
+    static constexpr int ELEMS = ON ? N : 1;
+};
+
+// MODE 0: flat, no absorbing layer (b = 1: psi <- Xi; E uniform diagonal)
+// MODE 1: flat with layer (b = 1/S along the line; E uniform diagonal)
+// MODE 2: curved (b = a(x) [/S]; E from the per-point table)
+template <typename T, int N, int R, int L, bool COLS, bool SPLIT, int MODE>
 __global__ void __launch_bounds__(N / R * L)
 stage_kernel(StageParams<T> p) {
     using F = LineFFT<T, N, R, L, COLS, SPLIT>;
+    using TS = TwStage<T, N>;
     constexpr int P = F::P;
+    constexpr bool BLEND = MODE != 0;
+    // prefetch symbols and blend weights before the transform when registers allow
+    constexpr bool PF = sizeof(T) * R <= 32;
     __shared__ cpx<T> lds[F::LDS_ELEMS];
+    __shared__ cpx<T> twl[TS::ELEMS];
     const int tid = threadIdx.x;
     const int l = COLS ? tid % L : tid / P;
     const int j = COLS ? tid / L : tid % P;
-    const int line = blockIdx.x * L + l;
+    const int line = xcd_tile(blockIdx.x, gridDim.x) * L + l;
     const bool valid = line < p.nlines;
+    const size_t n1 = (size_t)p.n1;
+    auto gidx = [&](int pos) -> size_t { return COLS ? (size_t)pos * n1 + line : (size_t)line * n1 + pos; };
 
     cpx<T> v[2][R];
-    size_t idx[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int pos = j + r * P;
-        idx[r] = COLS ? (size_t)pos * p.n1 + line : (size_t)line * p.n1 + pos;
-        if (valid) PointIO<T>::load(p.psi, idx[r], v[0][r], v[1][r]);
+        if (valid) PointIO<T>::load(p.psi, gidx(j + r * P), v[0][r], v[1][r]);
         else v[0][r] = v[1][r] = cpx<T>{0, 0};
     }
-    if (p.e_pre > 0 && valid) {
-        if (p.E) {
+    const cpx<T>* tw = p.tw;
+    if constexpr (TS::ON) {
+        for (int k = tid; k < N; k += F::NT) twl[k] = p.tw[k];
+        tw = twl;
+    }
+    cpx<T> kk[PF ? R : 1];
+    T bb[PF && BLEND ? R : 1];
+    if constexpr (PF) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) kk[s] = p.K[j + s * P];
+        if constexpr (BLEND) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
+                T b = T(1);
+                if constexpr (MODE == 2) b = valid ? p.a[gidx(j + r * P)] : T(0);
+                if (MODE == 1 || p.inv_s) b *= p.inv_s[j + r * P];
+                bb[r] = b;
+            }
+        }
+    }
+    if (p.e_pre > 0 && valid) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (MODE == 2) {
                 cpx<T> e0, e1;
-                PointIO<T>::load(p.E, idx[r], e0, e1);
+                PointIO<T>::load(p.E, gidx(j + r * P), e0, e1);
                 apply_E(v[0][r], v[1][r], e0, e1);
                 if (p.e_pre > 1) apply_E(v[0][r], v[1][r], e0, e1);
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
+            } else {
                 apply_Ediag(v[0][r], v[1][r], p.e0u);
                 if (p.e_pre > 1) apply_Ediag(v[0][r], v[1][r], p.e0u);
             }
         }
     }
-    const bool blend = (p.a != nullptr) || (p.inv_s != nullptr);
-    cpx<T> old[2][R];
-    if (blend) {
+    cpx<T> old[BLEND ? 2 : 1][BLEND ? R : 1];
+    if constexpr (BLEND) {
 #pragma unroll
         for (int r = 0; r < R; ++r) { old[0][r] = v[0][r]; old[1][r] = v[1][r]; }
     }
 
-    F::template fft<false>(v, lds, l, j, p.tw);
+    F::template fft<false>(v, lds, l, j, tw);
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-        const cpx<T> k = p.K[j + s * P];      // (cos, sin) / n
+        const cpx<T> k = PF ? kk[PF ? s : 0] : p.K[j + s * P];      // (cos, sin) / n
         const cpx<T> u = v[0][s], w = v[1][s];
         if constexpr (!COLS) {                // K_x = cos I - i sin sigma_x
             v[0][s] = scal(k.re, u) + mul_mi(scal(k.im, w));
@@ -147,29 +188,35 @@ stage_kernel(StageParams<T> p) {
             v[1][s] = scal(k.re, w) + scal(k.im, u);
         }
     }
-    F::template fft<true>(v, lds, l, j, p.tw);
+    F::template fft<true>(v, lds, l, j, tw);
 
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         cpx<T> u = v[0][r], w = v[1][r];
-        if (blend) {
-            T b = p.a ? p.a[idx[r]] : T(1);
-            if (p.inv_s) b *= p.inv_s[j + r * P];
+        if constexpr (BLEND) {
+            T b;
+            if constexpr (PF) {
+                b = bb[r];
+            } else {
+                b = T(1);
+                if constexpr (MODE == 2) b = p.a[gidx(j + r * P)];
+                if (MODE == 1 || p.inv_s) b *= p.inv_s[j + r * P];
+            }
             const T ob = T(1) - b;
             u = scal(b, u) + scal(ob, old[0][r]);
             w = scal(b, w) + scal(ob, old[1][r]);
         }
         if (p.e_post) {
-            if (p.E) {
+            if constexpr (MODE == 2) {
                 cpx<T> e0, e1;
-                PointIO<T>::load(p.E, idx[r], e0, e1);
+                PointIO<T>::load(p.E, gidx(j + r * P), e0, e1);
                 apply_E(u, w, e0, e1);
             } else {
                 apply_Ediag(u, w, p.e0u);
             }
         }
-        PointIO<T>::store(p.psi, idx[r], u, w);
+        PointIO<T>::store(p.psi, gidx(j + r * P), u, w);
     }
 }
 
@@ -221,7 +268,7 @@ obs_kernel(ObsParams p) {
     const int tid = threadIdx.x;
     const int l = COLS ? tid % L : tid / P;
     const int j = COLS ? tid / L : tid % P;
-    const int line = blockIdx.x * L + l;
+    const int line = xcd_tile(blockIdx.x, gridDim.x) * L + l;
     const bool valid = line < p.nlines;
     const T* psi = static_cast<const T*>(p.psi);
     const T* D = static_cast<const T*>(p.D);

@@ -8,12 +8,8 @@
 #define DIRAC_DIR 1
 REGO(512, 8, 8, 0)
 REG(512, 8, 4, 0)
-REG(512, 16, 8, 0)
-REG(512, 16, 16, 0)
 REGO(1024, 8, 4, 0)
 REG(1024, 8, 8, 0)
-REG(1024, 16, 4, 0)
-REG(1024, 16, 8, 0)
 REGO(2048, 8, 2, 0)
 REG(2048, 8, 4, 0)
 REG(2048, 16, 4, 0)

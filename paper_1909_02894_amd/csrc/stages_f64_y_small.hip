@@ -10,13 +10,11 @@ REGO(16, 4, 16, 0)
 REG(16, 4, 32, 0)
 REGO(32, 4, 8, 0)
 REG(32, 4, 16, 0)
-REGO(64, 8, 8, 0)
+REGO(64, 4, 8, 0)
+REG(64, 8, 8, 0)
 REG(64, 8, 16, 0)
-REG(64, 4, 8, 0)
-REGO(128, 8, 4, 0)
+REGO(128, 4, 4, 0)
+REG(128, 8, 4, 0)
 REG(128, 8, 8, 0)
-REG(128, 4, 4, 0)
 REGO(256, 8, 4, 0)
 REG(256, 8, 8, 0)
-REG(256, 16, 4, 0)
-REG(256, 16, 8, 0)
