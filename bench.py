@@ -110,6 +110,53 @@ def roofline_for(spec, kind, precision, r):
             "x_avg_us": round(avg[0] * 1e3, 3), "y_avg_us": round(avg[1] * 1e3, 3)}
 
 
+def bench_batch(D, W, count=256, steps=1000):
+    """Many independent curved solves of mixed size advanced by the batch engine:
+    one graph launch for the whole run (timed on its second, graph-reusing run)."""
+    import torch
+    specs = W.batch_mix(count, 4000, (128, 256, 512), steps)
+    b = D.Batch(precision=D.FP32, capacity=count)
+    solvers = []
+    for sp in specs:
+        s = D.Solver.from_spec(sp, precision=D.FP32, stream=b.stream)
+        s.set_initial_spinor(W.initial_spinor(sp))
+        b.add(s)
+        solvers.append(s)
+    b.run([steps] * count)          # builds and replays the graph
+    b.sync()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.run([steps] * count)          # the same run: graph reused
+    e1.record(b.stream)
+    b.sync()
+    ms = e0.elapsed_time(e1)
+    pts = sum(sp.n1 * sp.n2 for sp in specs)
+    fin = all(s.observables()["finite"] for s in solvers[:8])
+    algo = 88.0 * pts * steps
+    hist = {n: sum(1 for sp in specs if sp.n1 == n) for n in (128, 256, 512)}
+    b.close()
+    return {"value": pts * steps / (ms * 1e-3), "unit": "grid-point*steps/s", "dtype": "f32",
+            "solves": count, "steps": steps, "grid_sizes": hist, "ms": ms, "finite": fin,
+            "step_roofline": {"bound": "hbm", "achieved": round(algo / (ms * 1e-3) / 1e9, 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "bytes_per_point_step": 88,
+                              "state_bytes": pts * 16}}
+
+
+def bench_serve(count, rate, budget, quantum=64, seed=5000):
+    from paper_1909_02894_amd import serve as S
+    reqs = S.make_requests(count, rate, seed=seed)
+    srv = S.Server(precision=1, budget_bytes=budget, capacity=512, quantum=quantum)
+    st = srv.run(reqs)
+    srv.close()
+    return {"requests": st.requests, "rate_per_s": round(rate, 3), "budget_bytes": budget, "quantum": quantum,
+            "p50_s": round(st.p50_s, 4), "p99_s": round(st.p99_s, 4), "mean_s": round(st.mean_s, 4),
+            "throughput": st.throughput, "unit": "grid-point*steps/s", "wall_s": round(st.wall_s, 3),
+            "max_running": st.max_running, "quanta": st.quanta, "peak_arena_bytes": st.peak_arena_bytes}
+
+
 def cpu_baseline(spec, steps):
     from oracle import dirac_oracle as O
     from paper_1909_02894_amd import workloads as W
@@ -192,6 +239,15 @@ def main():
             "note": "flat 4096x4096 packet solve, 256 MiB state (beyond the Infinity Cache)",
             "roofline": roofline_for(big, "flat", D.FP32, rb),
             "schedule": {"x": rb["sched"][0], "y": rb["sched"][1]}}
+        bt = bench_batch(D, W)
+        variants["batch_256_mixed"] = bt
+        # serving at ~0.7x the measured batch capacity
+        mean_work = np.mean([n * n for n in (64, 128, 256, 512, 1024)]) * (200 + 5000) / 2.0
+        rate = 0.7 * bt["value"] / mean_work
+        variants["serve_poisson"] = bench_serve(100, rate, 288 << 30)
+        variants["serve_poisson_2GB"] = bench_serve(40, rate, 2 << 30, seed=5001)
+        out["latency"] = {"p50_s": variants["serve_poisson"]["p50_s"], "p99_s": variants["serve_poisson"]["p99_s"],
+                          "source": "serve_poisson"}
     out["variants"] = variants
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)

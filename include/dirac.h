@@ -204,6 +204,46 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps);
 dirac_status dirac_tune_cache_save(const char* path);
 dirac_status dirac_tune_cache_load(const char* path);
 
+/* --- batched solves ------------------------------------------------------------ */
+
+/* A batch advances many independent solves of mixed grid sizes together: every
+ * step of a run is two kernel launches (direction x, then y) that each cover all
+ * tiles of all solves still running, recorded once into a HIP graph and
+ * replayed.  Solves keep their own device buffers (created with
+ * dirac_create_metric, same precision as the batch, n1 and n2 <= 2048); the
+ * batch only holds descriptor tables in its own caller-given device buffer.
+ * Radix per grid size is fixed (4 for n <= 64, else 8), so a solve's result is
+ * bitwise the same alone in a batch, in any mix, and in the single-solve path
+ * with the same radix (dirac_set_schedule). */
+typedef struct dirac_batch dirac_batch;
+
+/* Device bytes for a batch of `capacity` solves. */
+size_t dirac_batch_footprint_bytes(int32_t capacity);
+
+dirac_status dirac_batch_create(int32_t precision, int32_t capacity, void* device_buffer, size_t bytes,
+                                void* hip_stream, dirac_batch** out);
+
+/* Put a solver (initial spinor already set) into a free slot; the batch then
+ * launches its work on the batch stream.  *slot_out receives the slot index. */
+dirac_status dirac_batch_add(dirac_batch* b, dirac_solver* s, int32_t* slot_out);
+
+/* Take a solver out of its slot (the solver itself stays valid). */
+dirac_status dirac_batch_remove(dirac_batch* b, int32_t slot);
+
+/* Advance slot i by steps[i] >= 0 steps (steps has `capacity` entries; free
+ * slots must have 0), asynchronously on the batch stream.  Each solve ends the
+ * run on a step boundary, so observables and get_spinor work between runs
+ * (after synchronising the batch stream, which dirac_batch_sync does). */
+dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps);
+
+/* Wait for everything enqueued on the batch stream. */
+dirac_status dirac_batch_sync(dirac_batch* b);
+
+/* 0 = one launch per phase, 1 = record each run into a HIP graph (default). */
+dirac_status dirac_batch_set_graph(dirac_batch* b, int32_t use_graph);
+
+dirac_status dirac_batch_destroy(dirac_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,301 @@
+// batch_runtime.hip -- host side of the batched multi-solve engine: slot table,
+// descriptor upload (pinned, double buffered), per-run phase schedule and its
+// HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/dirac.h"
+#include "batch_kernels.hpp"
+#include "batch_registry.hpp"
+#include "solver.hpp"
+
+namespace dirac {
+
+BatchKernel& batch_kernel(int prec, int dir) {
+    static BatchKernel k[2][2];
+    return k[prec][dir];
+}
+
+static size_t align256b(size_t x) { return (x + 255) & ~size_t(255); }
+
+static size_t batch_half_bytes(int capacity) {
+    return align256b((size_t)capacity * sizeof(BatchDesc<double>)) + align256b(2 * ((size_t)capacity + 1) * sizeof(int));
+}
+
+}  // namespace dirac
+
+using namespace dirac;
+
+struct dirac_batch {
+    int prec = 0;
+    int capacity = 0;
+    hipStream_t stream = nullptr;
+    char* base = nullptr;
+    size_t half = 0;
+    int which = 0;
+    std::vector<dirac_solver*> slots;
+    char* host_stage[2] = {nullptr, nullptr};
+    hipEvent_t stage_done[2] = {nullptr, nullptr};
+    bool use_graph = true;
+    // cached graph of the last run signature
+    std::vector<int64_t> sig;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t graph_done = nullptr;
+    int graph_half = -1;
+    uint64_t version = 0;
+    uint64_t graph_version = ~0ull;
+};
+
+static dirac_status bhip(hipError_t e, const char* what) {
+    return e == hipSuccess ? DIRAC_OK : fail(DIRAC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+#define BTRY(expr, what)                              \
+    do {                                              \
+        dirac_status st_ = bhip((expr), (what));      \
+        if (st_ != DIRAC_OK) return st_;              \
+    } while (0)
+
+static void batch_drop_graph(dirac_batch* b) {
+    if (b->gexec) {
+        if (b->graph_done) (void)hipEventSynchronize(b->graph_done);
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    b->sig.clear();
+}
+
+template <typename T>
+static void fill_desc(BatchDesc<T>& d, const dirac_solver* s, int steps) {
+    char* base = s->base;
+    d.psi = reinterpret_cast<T*>(base + s->lay.psi);
+    d.a = s->curved ? reinterpret_cast<const T*>(base + s->lay.a) : nullptr;
+    d.E = s->curved ? reinterpret_cast<const T*>(base + s->lay.E) : nullptr;
+    for (int ax = 0; ax < 2; ++ax) {
+        d.inv_s[ax] = s->pml ? reinterpret_cast<const T*>(base + s->lay.inv_s[ax]) : nullptr;
+        d.K[ax] = reinterpret_cast<const cpx<T>*>(base + s->lay.K[ax]);
+        d.tw[ax] = reinterpret_cast<const cpx<T>*>(base + s->lay.tw[ax]);
+    }
+    d.n1 = s->g.n1;
+    d.n2 = s->g.n2;
+    d.logn[0] = __builtin_ctz((unsigned)s->g.n1);
+    d.logn[1] = __builtin_ctz((unsigned)s->g.n2);
+    d.mode = s->curved ? 2 : (s->pml ? 1 : 0);
+    d.steps = steps;
+    d.e0u = cpx<T>{(T)s->e0u_re, (T)s->e0u_im};
+}
+
+static int tiles_of(int n_line, int n_lines) {
+    const int L = batch_lines(n_line);
+    return (n_lines + L - 1) / L;
+}
+
+extern "C" {
+
+size_t dirac_batch_footprint_bytes(int32_t capacity) {
+    if (capacity < 1 || capacity > (1 << 20)) return 0;
+    return 2 * batch_half_bytes(capacity) + 256;
+}
+
+dirac_status dirac_batch_create(int32_t prec, int32_t capacity, void* device_buffer, size_t bytes, void* hip_stream,
+                                dirac_batch** out) {
+    if (!out) return fail(DIRAC_E_ARG, "null output handle");
+    *out = nullptr;
+    if (prec != DIRAC_FP64 && prec != DIRAC_FP32) return fail(DIRAC_E_ARG, "precision must be 0 or 1");
+    if (capacity < 1 || capacity > (1 << 20)) return fail(DIRAC_E_ARG, "capacity must be in [1, 2^20]");
+    if (!device_buffer) return fail(DIRAC_E_ARG, "null device buffer");
+    if (bytes < dirac_batch_footprint_bytes(capacity))
+        return fail(DIRAC_E_SIZE, "batch buffer of %zu bytes < footprint %zu", bytes, dirac_batch_footprint_bytes(capacity));
+    for (int d = 0; d < 2; ++d)
+        if (!batch_kernel(prec, d).fn) return fail(DIRAC_E_DEVICE, "batch kernels not compiled");
+    dirac_batch* b = new (std::nothrow) dirac_batch();
+    if (!b) return fail(DIRAC_E_NOMEM, "host allocation failed");
+    b->prec = prec;
+    b->capacity = capacity;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    const uintptr_t raw = reinterpret_cast<uintptr_t>(device_buffer);
+    b->base = reinterpret_cast<char*>((raw + 255) & ~uintptr_t(255));
+    b->half = batch_half_bytes(capacity);
+    b->slots.assign(capacity, nullptr);
+    for (int h = 0; h < 2; ++h) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&b->host_stage[h]), b->half, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&b->stage_done[h], hipEventDisableTiming) != hipSuccess) {
+            dirac_batch_destroy(b);
+            return fail(DIRAC_E_DEVICE, "pinned staging allocation failed");
+        }
+    }
+    if (hipEventCreateWithFlags(&b->graph_done, hipEventDisableTiming) != hipSuccess) {
+        dirac_batch_destroy(b);
+        return fail(DIRAC_E_DEVICE, "event creation failed");
+    }
+    for (int d = 0; d < 2; ++d)
+        (void)hipFuncSetAttribute(batch_kernel(prec, d).fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    *out = b;
+    return DIRAC_OK;
+}
+
+dirac_status dirac_batch_add(dirac_batch* b, dirac_solver* s, int32_t* slot_out) {
+    if (!b || !s || !slot_out) return fail(DIRAC_E_ARG, "null argument");
+    if (s->prec != b->prec) return fail(DIRAC_E_ARG, "solver precision differs from the batch");
+    if (s->g.n1 > 2048 || s->g.n2 > 2048) return fail(DIRAC_E_SIZE, "batched solves need n1, n2 <= 2048");
+    if (!s->has_state) return fail(DIRAC_E_STATE, "set the solver's initial spinor first");
+    for (auto* t : b->slots)
+        if (t == s) return fail(DIRAC_E_ARG, "solver already in the batch");
+    for (int i = 0; i < b->capacity; ++i) {
+        if (!b->slots[i]) {
+            b->slots[i] = s;
+            *slot_out = i;
+            ++b->version;
+            return DIRAC_OK;
+        }
+    }
+    return fail(DIRAC_E_SIZE, "batch is full (capacity %d)", b->capacity);
+}
+
+dirac_status dirac_batch_remove(dirac_batch* b, int32_t slot) {
+    if (!b || slot < 0 || slot >= b->capacity || !b->slots[slot]) return fail(DIRAC_E_ARG, "bad slot");
+    b->slots[slot] = nullptr;
+    ++b->version;
+    return DIRAC_OK;
+}
+
+dirac_status dirac_batch_set_graph(dirac_batch* b, int32_t use_graph) {
+    if (!b) return fail(DIRAC_E_ARG, "null batch");
+    b->use_graph = use_graph != 0;
+    batch_drop_graph(b);
+    return DIRAC_OK;
+}
+
+dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
+    if (!b || !steps) return fail(DIRAC_E_ARG, "null argument");
+    std::vector<int> act;
+    for (int i = 0; i < b->capacity; ++i) {
+        if (steps[i] < 0) return fail(DIRAC_E_ARG, "negative step count for slot %d", i);
+        if (steps[i] > 0) {
+            if (!b->slots[i]) return fail(DIRAC_E_ARG, "steps for free slot %d", i);
+            if (steps[i] > (1ll << 30)) return fail(DIRAC_E_ARG, "step count too large for slot %d", i);
+            act.push_back(i);
+        }
+    }
+    if (act.empty()) return DIRAC_OK;
+    std::stable_sort(act.begin(), act.end(), [&](int x, int y) { return steps[x] > steps[y]; });
+    const int na = (int)act.size();
+    std::vector<int64_t> sig;
+    sig.reserve(2 * na + 1);
+    sig.push_back((int64_t)b->version);
+    for (int i : act) { sig.push_back(i); sig.push_back(steps[i]); }
+
+    const bool reuse = b->use_graph && b->gexec && sig == b->sig;
+    int h = reuse ? b->graph_half : b->which;
+    char* dev = b->base + (size_t)h * b->half;
+    const size_t desc_bytes = align256b((size_t)b->capacity * sizeof(BatchDesc<double>));
+    int* dprefix = reinterpret_cast<int*>(dev + desc_bytes);
+    std::vector<int> prefix[2];
+    size_t smem[2] = {0, 0};
+    for (int d = 0; d < 2; ++d) {
+        prefix[d].assign(na + 1, 0);
+        for (int q = 0; q < na; ++q) {
+            const dirac_solver* s = b->slots[act[q]];
+            const int nl = d == 0 ? s->g.n1 : s->g.n2;
+            const int lines = d == 0 ? s->g.n2 : s->g.n1;
+            prefix[d][q + 1] = prefix[d][q] + tiles_of(nl, lines);
+            smem[d] = std::max(smem[d], batch_kernel(b->prec, d).smem(__builtin_ctz((unsigned)nl)));
+        }
+    }
+    if (!reuse) {
+        batch_drop_graph(b);
+        // refill the staging half (wait until its previous upload has left the host buffer)
+        BTRY(hipEventSynchronize(b->stage_done[h]), "wait for staging buffer");
+        char* hs = b->host_stage[h];
+        for (int q = 0; q < na; ++q) {
+            const dirac_solver* s = b->slots[act[q]];
+            if (b->prec == DIRAC_FP64) fill_desc(reinterpret_cast<BatchDesc<double>*>(hs)[q], s, (int)steps[act[q]]);
+            else fill_desc(reinterpret_cast<BatchDesc<float>*>(hs)[q], s, (int)steps[act[q]]);
+        }
+        std::memcpy(hs + desc_bytes, prefix[0].data(), (na + 1) * sizeof(int));
+        std::memcpy(hs + desc_bytes + (b->capacity + 1) * sizeof(int), prefix[1].data(), (na + 1) * sizeof(int));
+        BTRY(hipMemcpyAsync(dev, hs, b->half, hipMemcpyHostToDevice, b->stream), "upload batch descriptors");
+        BTRY(hipEventRecord(b->stage_done[h], b->stream), "record staging event");
+        b->which ^= 1;
+    }
+
+    const int64_t qmax = steps[act[0]];
+    auto phase_params = [&](int d, int64_t k, BatchPhase<double>& ph) {
+        int nactive = na;
+        while (nactive > 0 && steps[act[nactive - 1]] <= k) --nactive;
+        ph.desc = reinterpret_cast<const BatchDesc<double>*>(dev);
+        ph.prefix = dprefix + (d == 0 ? 0 : b->capacity + 1);
+        ph.nactive = nactive;
+        ph.total_tiles = prefix[d][nactive];
+        ph.k = (int)k;
+    };
+    // BatchPhase<T> has the same layout for both T (pointers and ints only).
+    static_assert(sizeof(BatchPhase<double>) == sizeof(BatchPhase<float>), "phase layout");
+
+    if (!b->use_graph) {
+        for (int64_t k = 0; k < qmax; ++k) {
+            for (int d = 0; d < 2; ++d) {
+                BatchPhase<double> ph;
+                phase_params(d, k, ph);
+                void* args[] = {&ph};
+                BTRY(hipLaunchKernel(batch_kernel(b->prec, d).fn, dim3(ph.total_tiles), dim3(kBatchThreads), args,
+                                     smem[d], b->stream), "launch batch phase");
+            }
+        }
+    } else {
+        if (!reuse) {
+            BTRY(hipGraphCreate(&b->graph, 0), "hipGraphCreate");
+            hipGraphNode_t prev = nullptr;
+            for (int64_t k = 0; k < qmax; ++k) {
+                for (int d = 0; d < 2; ++d) {
+                    BatchPhase<double> ph;
+                    phase_params(d, k, ph);
+                    void* args[] = {&ph};
+                    hipKernelNodeParams kp{};
+                    kp.func = const_cast<void*>(batch_kernel(b->prec, d).fn);
+                    kp.gridDim = dim3(ph.total_tiles);
+                    kp.blockDim = dim3(kBatchThreads);
+                    kp.sharedMemBytes = (unsigned)smem[d];
+                    kp.kernelParams = args;
+                    hipGraphNode_t node;
+                    BTRY(hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp),
+                         "hipGraphAddKernelNode");
+                    prev = node;
+                }
+            }
+            BTRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            b->sig = sig;
+            b->graph_half = h;
+        }
+        BTRY(hipGraphLaunch(b->gexec, b->stream), "hipGraphLaunch");
+        BTRY(hipEventRecord(b->graph_done, b->stream), "record graph event");
+    }
+    for (int i : act) b->slots[i]->step += steps[i];
+    return DIRAC_OK;
+}
+
+dirac_status dirac_batch_sync(dirac_batch* b) {
+    if (!b) return fail(DIRAC_E_ARG, "null batch");
+    BTRY(hipStreamSynchronize(b->stream), "synchronise batch stream");
+    return DIRAC_OK;
+}
+
+dirac_status dirac_batch_destroy(dirac_batch* b) {
+    if (!b) return fail(DIRAC_E_ARG, "null batch");
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    for (int h = 0; h < 2; ++h) {
+        if (b->host_stage[h]) (void)hipHostFree(b->host_stage[h]);
+        if (b->stage_done[h]) (void)hipEventDestroy(b->stage_done[h]);
+    }
+    if (b->graph_done) (void)hipEventDestroy(b->graph_done);
+    delete b;
+    return DIRAC_OK;
+}
+
+}  // extern "C"

@@ -110,21 +110,21 @@ struct TwStage {
 // MODE 0: flat, no absorbing layer (b = 1: psi <- Xi; E uniform diagonal)
 // MODE 1: flat with layer (b = 1/S along the line; E uniform diagonal)
 // MODE 2: curved (b = a(x) [/S]; E from the per-point table)
+// One tile (L lines) of a direction stage, executed by F::NT threads.  lds and
+// twl are the workgroup's exchange buffer (F::LDS_ELEMS) and twiddle stage
+// (TwStage::ELEMS).  Every per-line operation depends on (T, N, R, MODE) only.
 template <typename T, int N, int R, int L, bool COLS, bool SPLIT, int MODE>
-__global__ void __launch_bounds__(N / R * L)
-stage_kernel(StageParams<T> p) {
+__device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cpx<T>* lds, cpx<T>* twl) {
     using F = LineFFT<T, N, R, L, COLS, SPLIT>;
     using TS = TwStage<T, N>;
     constexpr int P = F::P;
     constexpr bool BLEND = MODE != 0;
     // prefetch symbols and blend weights before the transform when registers allow
     constexpr bool PF = sizeof(T) * R <= 32;
-    __shared__ cpx<T> lds[F::LDS_ELEMS];
-    __shared__ cpx<T> twl[TS::ELEMS];
     const int tid = threadIdx.x;
     const int l = COLS ? tid % L : tid / P;
     const int j = COLS ? tid / L : tid % P;
-    const int line = xcd_tile(blockIdx.x, gridDim.x) * L + l;
+    const int line = tile * L + l;
     const bool valid = line < p.nlines;
     const size_t n1 = (size_t)p.n1;
     auto gidx = [&](int pos) -> size_t { return COLS ? (size_t)pos * n1 + line : (size_t)line * n1 + pos; };
@@ -218,6 +218,14 @@ stage_kernel(StageParams<T> p) {
         }
         PointIO<T>::store(p.psi, gidx(j + r * P), u, w);
     }
+}
+
+template <typename T, int N, int R, int L, bool COLS, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(N / R * L)
+stage_kernel(StageParams<T> p) {
+    __shared__ cpx<T> lds[LineFFT<T, N, R, L, COLS, SPLIT>::LDS_ELEMS];
+    __shared__ cpx<T> twl[TwStage<T, N>::ELEMS];
+    stage_tile<T, N, R, L, COLS, SPLIT, MODE>(p, xcd_tile(blockIdx.x, gridDim.x), lds, twl);
 }
 
 // Deterministic workgroup sum of NV doubles per thread into out[0..NV).

@@ -12,6 +12,7 @@ REGO(32, 4, 8, 0)
 REG(32, 4, 16, 0)
 REGO(64, 8, 8, 0)
 REG(64, 8, 16, 0)
+REG(64, 4, 8, 0)
 REGO(128, 4, 8, 0)
 REG(128, 8, 8, 0)
 REG(128, 8, 16, 0)

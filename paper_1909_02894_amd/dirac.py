@@ -86,6 +86,14 @@ SIGNATURES = {
     "dirac_autotune": (C.c_int32, [_vp, C.c_int32]),
     "dirac_tune_cache_save": (C.c_int32, [C.c_char_p]),
     "dirac_tune_cache_load": (C.c_int32, [C.c_char_p]),
+    "dirac_batch_footprint_bytes": (C.c_size_t, [C.c_int32]),
+    "dirac_batch_create": (C.c_int32, [C.c_int32, C.c_int32, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "dirac_batch_add": (C.c_int32, [_vp, _vp, C.POINTER(C.c_int32)]),
+    "dirac_batch_remove": (C.c_int32, [_vp, C.c_int32]),
+    "dirac_batch_run": (C.c_int32, [_vp, C.POINTER(C.c_int64)]),
+    "dirac_batch_sync": (C.c_int32, [_vp]),
+    "dirac_batch_set_graph": (C.c_int32, [_vp, C.c_int32]),
+    "dirac_batch_destroy": (C.c_int32, [_vp]),
 }
 
 
@@ -270,6 +278,60 @@ class Solver:
         if self.h is not None:
             destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many solves advanced together by the batch engine (one graph launch per run)."""
+
+    def __init__(self, precision=FP32, capacity=256, device=None, stream=None):
+        import torch
+        self.precision, self.capacity = precision, capacity
+        self.nbytes = int(lib.dirac_batch_footprint_bytes(capacity))
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream or torch.cuda.current_stream(device)
+        self.buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.h = _vp()
+        _check(lib.dirac_batch_create(precision, capacity, _vp(self.buffer.data_ptr()), self.nbytes,
+                                      _vp(self.stream.cuda_stream), C.byref(self.h)))
+        self.members = {}
+
+    def add(self, solver: "Solver") -> int:
+        slot = C.c_int32()
+        _check(lib.dirac_batch_add(self.h, solver.h, C.byref(slot)))
+        self.members[slot.value] = solver
+        return slot.value
+
+    def remove(self, slot: int):
+        _check(lib.dirac_batch_remove(self.h, slot))
+        self.members.pop(slot, None)
+
+    def run(self, steps):
+        """steps: dict slot -> n, or a sequence of capacity entries."""
+        arr = (C.c_int64 * self.capacity)()
+        if isinstance(steps, dict):
+            for k, v in steps.items():
+                arr[k] = int(v)
+        else:
+            for k, v in enumerate(steps):
+                arr[k] = int(v)
+        _check(lib.dirac_batch_run(self.h, arr))
+
+    def sync(self):
+        _check(lib.dirac_batch_sync(self.h))
+
+    def set_graph(self, use_graph: bool):
+        _check(lib.dirac_batch_set_graph(self.h, int(use_graph)))
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            _check(lib.dirac_batch_destroy(self.h))
+        self.h = None
 
     def __del__(self):
         try:

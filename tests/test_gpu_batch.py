@@ -1,0 +1,135 @@
+"""Batched multi-solve engine: every solve in a mixed batch equals, bit for bit,
+the same solve alone in a batch and the single-solve path with the batch radix;
+and matches the FP64 oracle within the parity tolerances."""
+import numpy as np
+import pytest
+
+from oracle import dirac_oracle as O
+from paper_1909_02894_amd import workloads as W
+from tests.helpers import oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_02894_amd import dirac
+    return dirac
+
+
+def batch_radix(n):
+    return 4 if n <= 64 else 8
+
+
+def mixed_specs():
+    specs = []
+    for i, n in enumerate((64, 128, 256, 128, 64, 512)):
+        s = W.curved_bump(n=n, seed=4000 + i, steps=0, m=0.5 * (i % 3))
+        specs.append(s)
+    f = W.flat_small(n=128)
+    specs.append(f)
+    fp = W.flat_small(n=64)
+    fp.pml_width = 6
+    specs.append(fp)
+    r = W.curved_bump(n=128, seed=77, steps=0)
+    r.n2, r.a2, r.pml_width = 32, 6.0, 4                 # rectangular
+    specs.append(r)
+    return specs
+
+
+def single_path(D, spec, prec, steps):
+    s = D.Solver.from_spec(spec, precision=prec)
+    for d, n in ((0, spec.n1), (1, spec.n2)):
+        r = batch_radix(n)
+        lines = [l for (rr, l) in D.schedules(n, prec, d) if rr == r][0]
+        s.set_schedule(d, r, lines)
+    s.set_initial_spinor(W.initial_spinor(spec))
+    s.step_n(steps)
+    return s.get_spinor()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mixed_batch_bitwise_and_oracle(D, prec):
+    specs = mixed_specs()
+    steps = [7, 12, 3, 12, 0, 5, 9, 12, 4]
+    b = D.Batch(precision=prec, capacity=16)
+    solvers, slots = [], []
+    for sp in specs:
+        s = D.Solver.from_spec(sp, precision=prec)
+        s.set_initial_spinor(W.initial_spinor(sp))
+        solvers.append(s)
+        slots.append(b.add(s))
+    b.run({sl: st for sl, st in zip(slots, steps)})
+    b.sync()
+    for sp, s, st in zip(specs, solvers, steps):
+        got = s.get_spinor()
+        assert s.observables()["step"] == st
+        assert np.array_equal(got, single_path(D, sp, prec, st)), (sp.n1, sp.n2, st)
+        ref = O.run(W.initial_spinor(sp), O.build_tables(oracle_problem(sp)), st)
+        tol = 1e-11 if prec == 0 else 2e-5
+        if st:
+            assert O.rel_l2(got, ref) < tol, (sp.n1, sp.n2, st)
+    # alone in a batch == in the mix
+    alone = D.Batch(precision=prec, capacity=1)
+    sp = specs[1]
+    s = D.Solver.from_spec(sp, precision=prec)
+    s.set_initial_spinor(W.initial_spinor(sp))
+    alone.add(s)
+    alone.run([steps[1]])
+    alone.sync()
+    assert np.array_equal(s.get_spinor(), solvers[1].get_spinor())
+
+
+def test_graph_reuse_direct_mode_and_slot_changes(D):
+    specs = mixed_specs()[:4]
+    outs = {}
+    for use_graph in (True, False):
+        b = D.Batch(precision=1, capacity=8)
+        b.set_graph(use_graph)
+        sv = []
+        for sp in specs:
+            s = D.Solver.from_spec(sp, precision=1)
+            s.set_initial_spinor(W.initial_spinor(sp))
+            sv.append((b.add(s), s))
+        for _ in range(3):                       # the same run three times: graph reused
+            b.run({sl: 4 for sl, _ in sv})
+        b.remove(sv[2][0])                       # drop one, add a fresh solve into its slot
+        sp = specs[2]
+        s_new = D.Solver.from_spec(sp, precision=1)
+        s_new.set_initial_spinor(W.initial_spinor(sp))
+        sl = b.add(s_new)
+        b.run({sv[0][0]: 2, sv[1][0]: 5, sl: 6, sv[3][0]: 1})
+        b.sync()
+        outs[use_graph] = [sv[0][1].get_spinor(), sv[1][1].get_spinor(), s_new.get_spinor(), sv[3][1].get_spinor(),
+                           sv[2][1].get_spinor()]
+        assert sv[0][1].observables()["step"] == 14 and s_new.observables()["step"] == 6
+    for a, c in zip(outs[True], outs[False]):
+        assert np.array_equal(a, c)
+    # segmented runs equal one long single-solve run
+    assert np.array_equal(outs[True][1], single_path(D, specs[1], 1, 17))
+    assert np.array_equal(outs[True][2], single_path(D, specs[2], 1, 6))
+
+
+def test_batch_rejects_bad_input(D):
+    b = D.Batch(precision=0, capacity=2)
+    sp = W.curved_bump(n=64, steps=0)
+    s32 = D.Solver.from_spec(sp, precision=1)
+    s32.set_initial_spinor(W.initial_spinor(sp))
+    with pytest.raises(D.DiracError):
+        b.add(s32)                                # precision mismatch
+    s = D.Solver.from_spec(sp, precision=0)
+    with pytest.raises(D.DiracError) as ei:
+        b.add(s)                                  # no initial state
+    assert ei.value.status == -6
+    s.set_initial_spinor(W.initial_spinor(sp))
+    sl = b.add(s)
+    with pytest.raises(D.DiracError):
+        b.run([0, 3])                             # steps for a free slot
+    with pytest.raises(D.DiracError):
+        b.run([-1, 0])
+    b.run([2, 0])
+    b.sync()
+    assert s.observables()["step"] == 2
