@@ -74,6 +74,7 @@ def time_solve(D, spec, precision, steps, warmup, timed_steps):
     psi0 = torch.from_numpy(W.initial_spinor(spec).view(np.float64).copy()).cuda()
     s.set_initial_spinor_device(psi0)
     torch.cuda.synchronize()
+    s.autotune(20)                   # warm-up part 1: pick the fastest compiled schedules
     s.step_n(warmup)
     torch.cuda.synchronize()
     st = s.stream

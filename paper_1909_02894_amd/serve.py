@@ -29,15 +29,19 @@ from . import workloads as W
 
 
 class Arena:
-    """First-fit allocator over one device buffer (256-byte granules)."""
+    """First-fit allocator over one device buffer (256-byte granules).
+
+    With reserve=False the arena only does the bookkeeping of a budget (for
+    budgets near the whole device, which cannot be reserved as one buffer); the
+    caller then backs each granted block with its own allocation."""
 
     GRAN = 256
 
-    def __init__(self, nbytes: int, device):
+    def __init__(self, nbytes: int, device, reserve: bool = True):
         import torch
         self.nbytes = (nbytes // self.GRAN) * self.GRAN
-        self.buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
-        self.base = self.buffer.data_ptr()
+        self.buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=device) if reserve else None
+        self.base = self.buffer.data_ptr() if reserve else None
         self.free = [(0, self.nbytes)]          # sorted (offset, size)
         self.used = 0
 
@@ -90,14 +94,19 @@ class _Running:
 
 
 class _ArenaSolver(D.Solver):
-    """A Solver whose device buffer is a slice of the arena."""
+    """A Solver whose device buffer is a slice of the arena (ptr), or a buffer of
+    its own when the arena only accounts (ptr None)."""
 
     def __init__(self, spec, precision, ptr, nbytes, stream):
+        import torch
         self.n1, self.n2, self.precision = spec.n1, spec.n2, precision
         self.grid, self.metric, self.pml, keep = D.spec_structs(spec)
         self.nbytes = nbytes
         self.stream = stream
         self.buffer = None
+        if ptr is None:
+            self.buffer = torch.empty(nbytes, dtype=torch.uint8, device=stream.device)
+            ptr = self.buffer.data_ptr()
         self.h = None
         self.h = D.create_metric(self.grid, self.metric, self.pml, precision, ptr, nbytes, stream.cuda_stream)
         del keep
@@ -125,13 +134,19 @@ class Server:
         import torch
         self.precision = precision
         self.device = device or torch.device("cuda", torch.cuda.current_device())
-        self.arena = Arena(budget_bytes, self.device)
+        # budgets beyond 64 GiB are accounted, not reserved: each admitted solve then
+        # gets its own buffer from torch's caching allocator
+        self.reserve = budget_bytes <= (64 << 30)
+        self.arena = Arena(budget_bytes, self.device, reserve=self.reserve)
         self.batch_stream = torch.cuda.Stream(self.device)
         self.setup_stream = torch.cuda.Stream(self.device)
         self.batch = D.Batch(precision=precision, capacity=capacity, device=self.device, stream=self.batch_stream)
         self.capacity = capacity
         self.quantum = quantum
         self.keep_results = keep_results
+
+    def _ptr(self, off):
+        return None if self.arena.base is None else self.arena.base + off
 
     def _footprint(self, spec):
         g, m, p, _ = D.spec_structs(spec)
@@ -161,7 +176,7 @@ class Server:
                 if got is None:
                     break
                 off, size = got
-                s = _ArenaSolver(r.spec, self.precision, self.arena.base + off, size, self.setup_stream)
+                s = _ArenaSolver(r.spec, self.precision, self._ptr(off), size, self.setup_stream)
                 s.set_initial_spinor(W.initial_spinor(r.spec))
                 slot = self.batch.add(s)
                 r.admitted = now()
@@ -188,7 +203,7 @@ class Server:
                 if got is None:
                     break
                 off, size = got
-                s = _ArenaSolver(r.spec, self.precision, self.arena.base + off, size, self.setup_stream)
+                s = _ArenaSolver(r.spec, self.precision, self._ptr(off), size, self.setup_stream)
                 s.set_initial_spinor(W.initial_spinor(r.spec))
                 slot = self.batch.add(s)
                 r.admitted = now()
