@@ -60,6 +60,8 @@ dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pm
     if (prec != DIRAC_FP64 && prec != DIRAC_FP32) return fail(DIRAC_E_ARG, "precision must be 0 (FP64) or 1 (FP32)");
     if (!is_pow2_in_range(g->n1) || !is_pow2_in_range(g->n2))
         return fail(DIRAC_E_SIZE, "n1 = %d, n2 = %d: each must be a power of two in [16, 8192]", g->n1, g->n2);
+    if ((size_t)g->n1 * g->n2 * 4 * (prec == DIRAC_FP32 ? 4 : 8) >= (size_t(1) << 31))
+        return fail(DIRAC_E_SIZE, "state of %d x %d points does not fit 2 GiB of 32-bit offsets", g->n1, g->n2);
     if (!(g->a1 > 0) || !(g->a2 > 0) || !std::isfinite(g->a1) || !std::isfinite(g->a2))
         return fail(DIRAC_E_ARG, "half-widths a1, a2 must be finite and > 0");
     if (!(g->dt > 0) || !std::isfinite(g->dt)) return fail(DIRAC_E_ARG, "dt must be finite and > 0");

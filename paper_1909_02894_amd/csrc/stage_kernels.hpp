@@ -49,28 +49,34 @@ struct ObsParams {
     double a1, a2, h1, h2;
 };
 
+// Point access with 32-bit byte offsets (every supported state is < 2 GiB), so
+// addresses are formed as a scalar base plus a 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ const T* at(const T* base, uint32_t elem) {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + elem * (uint32_t)sizeof(T));
+}
 template <typename T> struct PointIO;
 template <> struct PointIO<double> {
-    static __device__ __forceinline__ void load(const double* p, size_t idx, cpx<double>& u, cpx<double>& v) {
-        const double2* q = reinterpret_cast<const double2*>(p) + 2 * idx;
+    static __device__ __forceinline__ void load(const double* p, uint32_t idx, cpx<double>& u, cpx<double>& v) {
+        const double2* q = reinterpret_cast<const double2*>(reinterpret_cast<const char*>(p) + idx * 32u);
         const double2 A = q[0], B = q[1];
         u = {A.x, A.y};
         v = {B.x, B.y};
     }
-    static __device__ __forceinline__ void store(double* p, size_t idx, cpx<double> u, cpx<double> v) {
-        double2* q = reinterpret_cast<double2*>(p) + 2 * idx;
+    static __device__ __forceinline__ void store(double* p, uint32_t idx, cpx<double> u, cpx<double> v) {
+        double2* q = reinterpret_cast<double2*>(reinterpret_cast<char*>(p) + idx * 32u);
         q[0] = make_double2(u.re, u.im);
         q[1] = make_double2(v.re, v.im);
     }
 };
 template <> struct PointIO<float> {
-    static __device__ __forceinline__ void load(const float* p, size_t idx, cpx<float>& u, cpx<float>& v) {
-        const float4 A = reinterpret_cast<const float4*>(p)[idx];
+    static __device__ __forceinline__ void load(const float* p, uint32_t idx, cpx<float>& u, cpx<float>& v) {
+        const float4 A = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(p) + idx * 16u);
         u = {A.x, A.y};
         v = {A.z, A.w};
     }
-    static __device__ __forceinline__ void store(float* p, size_t idx, cpx<float> u, cpx<float> v) {
-        reinterpret_cast<float4*>(p)[idx] = make_float4(u.re, u.im, v.re, v.im);
+    static __device__ __forceinline__ void store(float* p, uint32_t idx, cpx<float> u, cpx<float> v) {
+        *reinterpret_cast<float4*>(reinterpret_cast<char*>(p) + idx * 16u) = make_float4(u.re, u.im, v.re, v.im);
     }
 };
 
@@ -126,8 +132,8 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     const int j = COLS ? tid / L : tid % P;
     const int line = tile * L + l;
     const bool valid = line < p.nlines;
-    const size_t n1 = (size_t)p.n1;
-    auto gidx = [&](int pos) -> size_t { return COLS ? (size_t)pos * n1 + line : (size_t)line * n1 + pos; };
+    const uint32_t n1 = (uint32_t)p.n1;
+    auto gidx = [&](int pos) -> uint32_t { return COLS ? (uint32_t)pos * n1 + line : (uint32_t)line * n1 + pos; };
 
     cpx<T> v[2][R];
 #pragma unroll
@@ -149,7 +155,7 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 T b = T(1);
-                if constexpr (MODE == 2) b = valid ? p.a[gidx(j + r * P)] : T(0);
+                if constexpr (MODE == 2) b = valid ? *at(p.a, gidx(j + r * P)) : T(0);
                 if (MODE == 1 || p.inv_s) b *= p.inv_s[j + r * P];
                 bb[r] = b;
             }
@@ -200,7 +206,7 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
                 b = bb[r];
             } else {
                 b = T(1);
-                if constexpr (MODE == 2) b = p.a[gidx(j + r * P)];
+                if constexpr (MODE == 2) b = *at(p.a, gidx(j + r * P));
                 if (MODE == 1 || p.inv_s) b *= p.inv_s[j + r * P];
             }
             const T ob = T(1) - b;
@@ -283,11 +289,11 @@ obs_kernel(ObsParams p) {
     const cpx<T>* tw = static_cast<const cpx<T>*>(p.tw);
 
     cpx<T> v[2][R], old[2][R];
-    size_t idx[R];
+    uint32_t idx[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int pos = j + r * P;
-        idx[r] = COLS ? (size_t)pos * p.n1 + line : (size_t)line * p.n1 + pos;
+        idx[r] = COLS ? (uint32_t)pos * (uint32_t)p.n1 + line : (uint32_t)line * (uint32_t)p.n1 + pos;
         if (valid) PointIO<T>::load(psi, idx[r], v[0][r], v[1][r]);
         else v[0][r] = v[1][r] = cpx<T>{0, 0};
         old[0][r] = v[0][r];
@@ -306,7 +312,7 @@ obs_kernel(ObsParams p) {
     if (valid) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const size_t q = idx[r];
+            const uint32_t q = idx[r];
             const double p0r = old[0][r].re, p0i = old[0][r].im, p1r = old[1][r].re, p1i = old[1][r].im;
             const double d0r = v[0][r].re, d0i = v[0][r].im, d1r = v[1][r].re, d1i = v[1][r].im;
             const double w = p.w[q], ca = p.ca[q];

@@ -246,3 +246,27 @@ def test_config2_full_size_short_and_long(D):
     ob = s.observables()
     assert ob["finite"] == 1 and ob["step"] == 2000
     assert ob["norm_l2"] < ob0["norm_l2"] * 1.05
+
+
+def test_precision_report_flat_2048(D, capsys):
+    # 2048^2 flat packet solve for 5000 steps in FP32 and FP64 against the exact
+    # discrete propagator U(xi)^n of the scheme (computed in FP64 without a time loop).
+    spec = W.flat_small(n=2048, steps=5000)
+    psi0 = W.initial_spinor(spec)
+    checks = (100, 1000, 5000)
+    _, g32 = gpu_run(D, spec, 5000, precision=1, checkpoints=checks)
+    _, g64 = gpu_run(D, spec, 5000, precision=0, checkpoints=checks)
+    tol32 = {100: 2e-5, 1000: 2e-4, 5000: 1e-3}
+    rows = []
+    for k in checks:
+        ex = O.flat_exact_discrete(psi0, spec.n1, spec.n2, spec.a1, spec.a2, spec.m, spec.c, spec.dt, k)
+        mx = np.abs(ex).max()
+        r32, r64 = O.rel_l2(g32[k], ex), O.rel_l2(g64[k], ex)
+        m32, m64 = np.abs(g32[k] - ex).max() / mx, np.abs(g64[k] - ex).max() / mx
+        rows.append((k, r32, m32, r64, m64))
+        assert r32 < tol32[k] and m32 < 2 * tol32[k], (k, r32, m32)
+        assert r64 < 1e-10 and m64 < 2e-10, (k, r64, m64)
+    with capsys.disabled():
+        print("\nprecision 2048^2 flat: step, fp32 rel_l2, fp32 maxabs/max, fp64 rel_l2, fp64 maxabs/max")
+        for r in rows:
+            print("  %5d  %.3e  %.3e  %.3e  %.3e" % r)
