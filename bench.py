@@ -16,7 +16,6 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -43,15 +42,6 @@ def bytes_per_point(kind: str, dir_: int, precision: int) -> int:
     return state + (4 * sz + sz if dir_ == 0 else sz)
 
 
-def kernel_sources_digest() -> str:
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_1909_02894_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(d, f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(name: str):
     """HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
     (profiles/traffic.json), or None when absent or taken on other kernel sources."""
@@ -62,6 +52,7 @@ def load_traffic(name: str):
         d = json.load(open(p))
     except Exception:
         return None
+    from paper_1909_02894_amd.profiling import kernel_sources_digest
     if d.get("kernel_sources") != kernel_sources_digest():
         return None
     return d.get("kernels", {}).get(name)

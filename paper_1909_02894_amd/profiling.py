@@ -1,0 +1,118 @@
+"""Summaries of rocprofv3 output for the direction kernels.
+
+    python -m paper_1909_02894_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
+    python -m paper_1909_02894_amd.profiling traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
+        <copy_write.csv> <grid> <out.json> "<command>"
+
+`stats` turns a ``--kernel-trace --stats`` kernel table into a short markdown
+summary.  `traffic` takes two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
+counter-collection CSVs (KiB per dispatch) of a solve, and the same two
+counters for a plain 1 GiB device copy, scales each counter by
+(bytes the copy moves) / (what the counter reads for the copy), and writes the
+median HBM bytes per launch for every direction kernel, keyed by the names
+bench.py uses (e.g. ``y_stage_f64_512x512_curved``), plus a digest of the
+kernel sources so that stale numbers are not reported.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import re
+import statistics
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+MODE_NAMES = {0: "flat", 1: "flat_pml", 2: "curved"}
+COPY_BYTES = 1 << 30
+
+
+def kernel_sources_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1909_02894_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+_STAGE = re.compile(r"stage_kernel<(double|float), (\d+), (\d+), (\d+), (true|false), (true|false), (\d)>")
+
+
+def bench_name(kernel: str, grid: str):
+    """Map a stage-kernel instantiation to bench.py's name, e.g.
+    'void dirac::stage_kernel<double, 512, 8, 2, true, false, 2>(...)' ->
+    'y_stage_f64_512x512_curved'."""
+    m = _STAGE.search(kernel)
+    if not m:
+        return None
+    t, n, r, lines, cols, split, mode = m.groups()
+    return f"{'y' if cols == 'true' else 'x'}_stage_{'f64' if t == 'double' else 'f32'}_{grid}_{MODE_NAMES[int(mode)]}"
+
+
+def short_name(kernel: str) -> str:
+    k = kernel.replace("void dirac::", "").replace("dirac::", "")
+    return k.split("(")[0]
+
+
+def stats(csv_path: str, out_md: str, command: str, top: int = 14):
+    rows = list(csv.DictReader(open(csv_path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 kernel statistics", "", "Command (run from the repository root):", "", "```",
+             command, "```", "",
+             "| kernel | calls | avg (us) | min (us) | max (us) | share |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.1f}% |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def _per_kernel(path, counter):
+    d = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            d[r["Kernel_Name"]].append(float(r["Counter_Value"]) * 1024.0)   # KiB -> bytes
+    return d
+
+
+def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, grid, out_json, command):
+    cf = _per_kernel(copy_fetch_csv, "FETCH_SIZE")
+    cw = _per_kernel(copy_write_csv, "WRITE_SIZE")
+    copy_k = [k for k in cf if "copyBuffer" in k or "copy" in k.lower()]
+    if not copy_k:
+        raise SystemExit("no copy kernel in the calibration runs")
+    k0 = max(copy_k, key=lambda k: statistics.median(cf[k]))
+    f_scale = COPY_BYTES / statistics.median(cf[k0])
+    w_scale = COPY_BYTES / statistics.median(cw[k0])
+    fe = _per_kernel(fetch_csv, "FETCH_SIZE")
+    wr = _per_kernel(write_csv, "WRITE_SIZE")
+    out = {"kernel_sources": kernel_sources_digest(), "command": command,
+           "calibration": {"copy_kernel": short_name(k0), "copy_bytes_each_way": COPY_BYTES,
+                           "fetch_scale": f_scale, "write_scale": w_scale},
+           "kernels": {}}
+    # several instantiations can map to one name (the autotuner tries them all);
+    # keep the one dispatched most often, i.e. the schedule the timed run used
+    best = {}
+    for k in fe:
+        name = bench_name(k, grid)
+        if name and k in wr and (name not in best or len(fe[k]) > len(fe[best[name]])):
+            best[name] = k
+    for name, k in best.items():
+        fb = statistics.median(fe[k]) * f_scale
+        wb = statistics.median(wr[k]) * w_scale
+        out["kernels"][name] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "bytes": round(fb + wb),
+                                "dispatches": len(fe[k]), "instantiation": short_name(k)}
+    json.dump(out, open(out_json, "w"), indent=1)
+    return out
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic(*sys.argv[2:9])
+    else:
+        raise SystemExit(__doc__)
