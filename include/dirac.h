@@ -188,7 +188,8 @@ dirac_status dirac_set_schedule(dirac_solver* s, int32_t direction, const dirac_
 dirac_status dirac_set_launch_mode(dirac_solver* s, int32_t use_graph, int32_t graph_chunk);
 
 /* Advance nsteps like dirac_step_n with one kernel launch per stage and a HIP
- * event pair around every launch on the solver's stream, then synchronise.
+ * event recorded on the solver's stream before the first launch and after every
+ * launch (so the intervals tile the timed region), then synchronise.
  * ms_out[0] / ms_out[1] = summed duration of the x / y stage kernels in
  * milliseconds, counts_out[0..1] = number of launches of each. */
 dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,

@@ -557,34 +557,31 @@ dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
     ms_out[0] = ms_out[1] = 0.0;
     counts_out[0] = counts_out[1] = 0;
     if (nsteps == 0) return DIRAC_OK;
+    // one event before the first launch and one after every launch: launch i
+    // spans events i .. i+1, so the intervals tile the whole timed region
     const size_t nl = (size_t)nsteps * 2;
-    while (s->events.size() < 2 * nl) {
+    while (s->events.size() < nl + 1) {
         hipEvent_t ev;
         HIP_TRY(hipEventCreate(&ev), "hipEventCreate");
         s->events.push_back(ev);
     }
     hipStream_t st = s->stream;
+    HIP_TRY(hipEventRecord(s->events[0], st), "hipEventRecord");
     size_t k = 0;
-    std::vector<int> kind;
-    kind.reserve(nl);
     for (int64_t n = 0; n < nsteps; ++n) {
         Launch lx = make_launch(s, 0, n == 0 ? 1 : 2, 0);
         Launch ly = make_launch(s, 1, 0, n == nsteps - 1 ? 1 : 0);
-        HIP_TRY(hipEventRecord(s->events[2 * k], st), "hipEventRecord");
         HIP_TRY(do_launch(lx, st), "launch x stage");
-        HIP_TRY(hipEventRecord(s->events[2 * k + 1], st), "hipEventRecord");
-        kind.push_back(0); ++k;
-        HIP_TRY(hipEventRecord(s->events[2 * k], st), "hipEventRecord");
+        HIP_TRY(hipEventRecord(s->events[++k], st), "hipEventRecord");
         HIP_TRY(do_launch(ly, st), "launch y stage");
-        HIP_TRY(hipEventRecord(s->events[2 * k + 1], st), "hipEventRecord");
-        kind.push_back(1); ++k;
+        HIP_TRY(hipEventRecord(s->events[++k], st), "hipEventRecord");
     }
     HIP_TRY(hipStreamSynchronize(st), "synchronise");
     for (size_t i = 0; i < k; ++i) {
         float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, s->events[2 * i], s->events[2 * i + 1]), "hipEventElapsedTime");
-        ms_out[kind[i]] += ms;
-        counts_out[kind[i]] += 1;
+        HIP_TRY(hipEventElapsedTime(&ms, s->events[i], s->events[i + 1]), "hipEventElapsedTime");
+        ms_out[i & 1] += ms;
+        counts_out[i & 1] += 1;
     }
     s->step += nsteps;
     return DIRAC_OK;

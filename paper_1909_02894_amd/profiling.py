@@ -30,10 +30,11 @@ COPY_BYTES = 1 << 30
 
 
 def kernel_sources_digest() -> str:
+    """Digest of the direction-kernel sources (the code the counters measure)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1909_02894_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
+        if f in ("fft_line.hpp", "stage_kernels.hpp") or (f.startswith("stages_") and f.endswith(".hip")):
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
