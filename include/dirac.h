@@ -211,7 +211,7 @@ dirac_status dirac_tune_cache_load(const char* path);
  * step of a run is two kernel launches (direction x, then y) that each cover all
  * tiles of all solves still running, recorded once into a HIP graph and
  * replayed.  Solves keep their own device buffers (created with
- * dirac_create_metric, same precision as the batch, n1 and n2 <= 2048); the
+ * dirac_create_metric, same precision as the batch, n1 and n2 <= 1024); the
  * batch only holds descriptor tables in its own caller-given device buffer.
  * Radix per grid size is fixed (4 for n <= 64, else 8), so a solve's result is
  * bitwise the same alone in a batch, in any mix, and in the single-solve path

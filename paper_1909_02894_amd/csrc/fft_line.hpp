@@ -9,11 +9,12 @@
 // inputs at jj + r n/Rp, multiplies input r by W_n^{r (jj mod Ns) n/(Ns Rp)},
 // takes a radix-Rp DFT and writes output s at (jj / Ns) Ns Rp + jj mod Ns + s Ns.
 //
-// Thread layout.  A line of n points is handled by P = n / R threads; thread j
-// keeps R values per component in registers.  The first and the last pass
-// have radix R, so on entry thread j holds positions j + r P and on exit it
-// holds modes j + s P: the symbol multiply and the blend with the untouched
-// input happen in registers, and only the interior passes go through LDS.
+// Thread layout.  A line of n points is handled by P = n / R logical threads
+// per spinor component; logical thread j keeps R values in registers.  The
+// first and the last pass have radix R, so on entry thread j holds positions
+// j + r P and on exit it holds modes j + s P: the symbol multiply and the
+// blend with the untouched input happen in registers, and only the interior
+// passes go through LDS.
 // Radix schedule: n = R^e * rem (rem < R), passes [R, rem, R, ..., R].
 #pragma once
 #include <hip/hip_runtime.h>
@@ -113,28 +114,53 @@ __host__ __device__ constexpr int ilog(int n, int r) {  // largest e with r^e | 
 }
 __host__ __device__ constexpr int ipow(int r, int e) { int v = 1; for (int i = 0; i < e; ++i) v *= r; return v; }
 
-// One line geometry: N-point transform, R values per thread per component,
-// L lines per workgroup, COLS = lines are columns (line index fastest among
-// threads, for coalesced row segments), SPLIT = exchange one spinor component
-// at a time through LDS (half the LDS, twice the barriers).
-template <typename T, int N, int R, int L, bool COLS, bool SPLIT>
+// Exchange of a 32-bit value with the partner lane (lane xor 32) of the same
+// wave, with gfx950's v_permlane32_swap (upper half of the first operand <->
+// lower half of the second): lanes 0..31 find the partner's value in the second
+// result, lanes 32..63 in the first.
+__device__ __forceinline__ uint32_t partner_u32(uint32_t x) {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (threadIdx.x & 32) ? r[0] : r[1];
+}
+__device__ __forceinline__ float partner(float x) {
+    return __uint_as_float(partner_u32(__float_as_uint(x)));
+}
+__device__ __forceinline__ double partner(double x) {
+    const uint64_t b = __double_as_longlong(x);
+    const uint32_t lo = partner_u32((uint32_t)b), hi = partner_u32((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> partner(cpx<T> v) { return {partner(v.re), partner(v.im)}; }
+
+// One line geometry: N-point transform, R values per thread, L lines per
+// workgroup, COLS = lines are columns (line index fastest among threads, for
+// coalesced row segments).
+//
+// Each thread carries ONE spinor component: in every wave, lanes 0..31 hold
+// component 0 and lanes 32..63 component 1 of the same 32 logical threads, so
+// the two components of a point sit in partner lanes (lane xor 32) and the
+// 2x2 mixes (half-step exponential, directional symbol) exchange them with one
+// permlane swap.  A line of N points is held by P = N / R logical threads;
+// a workgroup has NTL = P L logical and NT = 2 NTL physical threads.
+template <typename T, int N, int R, int L, bool COLS>
 struct LineFFT {
     static constexpr int P = N / R;
-    static constexpr int NT = P * L;
+    static constexpr int NTL = P * L;
+    static constexpr int NT = 2 * NTL;
     static constexpr int E = ilog(N, R);
     static constexpr int REM = N / ipow(R, E);
     static constexpr int NPASS = E + (REM > 1 ? 1 : 0);
-    static constexpr int NC = SPLIT ? 1 : 2;
     // LDS layout, padded against bank conflicts: rows keep each (line, component)
     // run contiguous with one pad element after every R elements (the first
     // exchange writes with stride R); columns interleave the L lines of a position
     // and add one pad element every 16.
     static constexpr int ROW_STRIDE = N + N / R;
-    static constexpr int COL_RAW = NC * N * L;
-    static constexpr int LDS_ELEMS = (NPASS > 1) ? (COLS ? COL_RAW + COL_RAW / 16 : L * NC * ROW_STRIDE) : 1;
+    static constexpr int COL_RAW = 2 * N * L;
+    static constexpr int LDS_ELEMS = (NPASS > 1) ? (COLS ? COL_RAW + COL_RAW / 16 : L * 2 * ROW_STRIDE) : 1;
     static_assert(N % R == 0, "R must divide N");
     static_assert(NPASS == 1 ? N == R : E >= 2, "schedule needs radix-R first and last passes");
-    static_assert(NT >= 1 && NT <= 1024, "workgroup size");
+    static_assert(NTL % 32 == 0 && NT <= 1024, "32 logical threads per wave, at most 1024 threads");
 
     __host__ __device__ static constexpr int radix_of(int p) { return (p == 1 && REM > 1) ? REM : R; }
     __host__ __device__ static constexpr int ns_of(int p) {
@@ -142,72 +168,66 @@ struct LineFFT {
         for (int q = 0; q < p; ++q) ns *= radix_of(q);
         return ns;
     }
-    __device__ static __forceinline__ int lidx(int l, int slot, int pos) {
+    __device__ static __forceinline__ int lidx(int l, int comp, int pos) {
         if constexpr (COLS) {
-            const int a = (slot * N + pos) * L + l;
+            const int a = (comp * N + pos) * L + l;
             return a + a / 16;
         } else {
-            return (l * NC + slot) * ROW_STRIDE + pos + pos / R;
+            return (l * 2 + comp) * ROW_STRIDE + pos + pos / R;
         }
+    }
+    // Coordinates of physical thread t: component, line within the tile, and
+    // logical thread index j within the line.
+    struct Coord { int comp, l, j; };
+    __device__ static __forceinline__ Coord coord(int t) {
+        const int comp = (t >> 5) & 1;
+        const int u = ((t >> 6) << 5) | (t & 31);
+        return Coord{comp, COLS ? u % L : u / P, COLS ? u / L : u % P};
     }
 
     // Exchange after pass PASS-1 and compute pass PASS (PASS >= 1).
     template <bool INV, int PASS>
-    __device__ static __forceinline__ void pass(cpx<T> (&v)[2][R], cpx<T>* lds, int l, int j,
+    __device__ static __forceinline__ void pass(cpx<T> (&v)[R], cpx<T>* lds, const Coord& c,
                                                 const cpx<T>* __restrict__ tw) {
         constexpr int Rq = radix_of(PASS - 1), Nq = ns_of(PASS - 1);
         constexpr int Rp = radix_of(PASS), Ns = ns_of(PASS);
 #pragma unroll
-        for (int cg = 0; cg < 2 / NC; ++cg) {
+        for (int t = 0; t < R / Rq; ++t) {
+            const int jj = c.j + t * P;
+            const int base = (jj / Nq) * Nq * Rq + (jj % Nq);
 #pragma unroll
-            for (int cc = 0; cc < NC; ++cc) {
-                const int comp = cg * NC + cc;
-#pragma unroll
-                for (int t = 0; t < R / Rq; ++t) {
-                    const int jj = j + t * P;
-                    const int base = (jj / Nq) * Nq * Rq + (jj % Nq);
-#pragma unroll
-                    for (int s = 0; s < Rq; ++s) lds[lidx(l, cc, base + s * Nq)] = v[comp][t * Rq + s];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int cc = 0; cc < NC; ++cc) {
-                const int comp = cg * NC + cc;
-#pragma unroll
-                for (int t = 0; t < R / Rp; ++t) {
-                    const int jj = j + t * P;
-#pragma unroll
-                    for (int r = 0; r < Rp; ++r) v[comp][t * Rp + r] = lds[lidx(l, cc, jj + r * (N / Rp))];
-                }
-            }
-            __syncthreads();
+            for (int s = 0; s < Rq; ++s) lds[lidx(c.l, c.comp, base + s * Nq)] = v[t * Rq + s];
         }
+        __syncthreads();
 #pragma unroll
         for (int t = 0; t < R / Rp; ++t) {
-            const int jj = j + t * P;
+            const int jj = c.j + t * P;
+#pragma unroll
+            for (int r = 0; r < Rp; ++r) v[t * Rp + r] = lds[lidx(c.l, c.comp, jj + r * (N / Rp))];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < R / Rp; ++t) {
+            const int jj = c.j + t * P;
             const int k = jj % Ns;
 #pragma unroll
             for (int r = 1; r < Rp; ++r) {
                 const cpx<T> w = tw[r * k * (N / (Ns * Rp))];
-                v[0][t * Rp + r] = INV ? cmulc(v[0][t * Rp + r], w) : cmul(v[0][t * Rp + r], w);
-                v[1][t * Rp + r] = INV ? cmulc(v[1][t * Rp + r], w) : cmul(v[1][t * Rp + r], w);
+                v[t * Rp + r] = INV ? cmulc(v[t * Rp + r], w) : cmul(v[t * Rp + r], w);
             }
-            dft<T, Rp, INV>(&v[0][t * Rp]);
-            dft<T, Rp, INV>(&v[1][t * Rp]);
+            dft<T, Rp, INV>(&v[t * Rp]);
         }
-        if constexpr (PASS + 1 < NPASS) pass<INV, PASS + 1>(v, lds, l, j, tw);
+        if constexpr (PASS + 1 < NPASS) pass<INV, PASS + 1>(v, lds, c, tw);
     }
 
-    // Transform both components of the line.  Entry: v[c][r] = position j + r P.
-    // Exit: v[c][s] = mode (forward) / position (inverse) j + s P.  tw[k] =
-    // exp(-2 pi i k / N); the inverse uses conjugates and is unnormalised.
+    // Transform this thread's component of the line.  Entry: v[r] = position
+    // j + r P.  Exit: v[s] = mode (forward) / position (inverse) j + s P.
+    // tw[k] = exp(-2 pi i k / N); the inverse uses conjugates and is unnormalised.
     template <bool INV>
-    __device__ static __forceinline__ void fft(cpx<T> (&v)[2][R], cpx<T>* lds, int l, int j,
+    __device__ static __forceinline__ void fft(cpx<T> (&v)[R], cpx<T>* lds, const Coord& c,
                                                const cpx<T>* __restrict__ tw) {
-        dft<T, R, INV>(v[0]);
-        dft<T, R, INV>(v[1]);
-        if constexpr (NPASS > 1) pass<INV, 1>(v, lds, l, j, tw);
+        dft<T, R, INV>(v);
+        if constexpr (NPASS > 1) pass<INV, 1>(v, lds, c, tw);
     }
 };
 

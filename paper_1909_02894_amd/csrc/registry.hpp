@@ -12,7 +12,6 @@ struct KernelEntry {
     int dir;        // 0 = x (rows), 1 = y (columns)
     int radix;      // values per thread per component
     int lines;      // lines per workgroup
-    int split;      // exchange one component at a time
     int nthreads;   // workgroup size
     const void* stage_fn[3];   // by mode: 0 flat, 1 flat + layer, 2 curved
     const void* obs_fn;
@@ -26,20 +25,20 @@ struct Registrar {
 
 }  // namespace dirac
 
-// REG(N, R, L, SPLIT) inside a translation unit that defines DIRAC_T (double /
-// float), DIRAC_PREC (0/1), DIRAC_COLS (false/true), DIRAC_DIR (0/1).
+// REG(N, R, L) inside a translation unit that defines DIRAC_T (double / float),
+// DIRAC_PREC (0/1), DIRAC_COLS (false/true), DIRAC_DIR (0/1).
 #define DIRAC_CAT2(a, b) a##b
 #define DIRAC_CAT(a, b) DIRAC_CAT2(a, b)
-#define DIRAC_REG_IMPL(N, R, L, SPLIT, OBS)                                                          \
+#define DIRAC_REG_IMPL(N, R, L, OBS)                                                                 \
     static ::dirac::Registrar DIRAC_CAT(reg_, __LINE__)(::dirac::KernelEntry{                      \
-        DIRAC_PREC, N, DIRAC_DIR, R, L, SPLIT,                                                      \
-        ::dirac::LineFFT<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0)>::NT,                            \
-        {reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0), 0>), \
-         reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0), 1>), \
-         reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0), 2>)}, \
+        DIRAC_PREC, N, DIRAC_DIR, R, L,                                                             \
+        ::dirac::LineFFT<DIRAC_T, N, R, L, DIRAC_COLS>::NT,                                          \
+        {reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, 0>),   \
+         reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, 1>),   \
+         reinterpret_cast<const void*>(&::dirac::stage_kernel<DIRAC_T, N, R, L, DIRAC_COLS, 2>)},  \
         OBS});
 // REG: a direction-kernel schedule.  REGO: the same plus the observable kernel
 // with that schedule (one per precision, n and direction).
-#define REG(N, R, L, SPLIT) DIRAC_REG_IMPL(N, R, L, SPLIT, nullptr)
-#define REGO(N, R, L, SPLIT) \
-    DIRAC_REG_IMPL(N, R, L, SPLIT, reinterpret_cast<const void*>(&::dirac::obs_kernel<DIRAC_T, N, R, L, DIRAC_COLS, (SPLIT != 0)>))
+#define REG(N, R, L) DIRAC_REG_IMPL(N, R, L, nullptr)
+#define REGO(N, R, L) \
+    DIRAC_REG_IMPL(N, R, L, reinterpret_cast<const void*>(&::dirac::obs_kernel<DIRAC_T, N, R, L, DIRAC_COLS>))

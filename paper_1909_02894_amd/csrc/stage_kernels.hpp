@@ -55,44 +55,34 @@ template <typename T>
 __device__ __forceinline__ const T* at(const T* base, uint32_t elem) {
     return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + elem * (uint32_t)sizeof(T));
 }
-template <typename T> struct PointIO;
-template <> struct PointIO<double> {
-    static __device__ __forceinline__ void load(const double* p, uint32_t idx, cpx<double>& u, cpx<double>& v) {
-        const double2* q = reinterpret_cast<const double2*>(reinterpret_cast<const char*>(p) + idx * 32u);
-        const double2 A = q[0], B = q[1];
-        u = {A.x, A.y};
-        v = {B.x, B.y};
-    }
-    static __device__ __forceinline__ void store(double* p, uint32_t idx, cpx<double> u, cpx<double> v) {
-        double2* q = reinterpret_cast<double2*>(reinterpret_cast<char*>(p) + idx * 32u);
-        q[0] = make_double2(u.re, u.im);
-        q[1] = make_double2(v.re, v.im);
-    }
-};
-template <> struct PointIO<float> {
-    static __device__ __forceinline__ void load(const float* p, uint32_t idx, cpx<float>& u, cpx<float>& v) {
-        const float4 A = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(p) + idx * 16u);
-        u = {A.x, A.y};
-        v = {A.z, A.w};
-    }
-    static __device__ __forceinline__ void store(float* p, uint32_t idx, cpx<float> u, cpx<float> v) {
-        *reinterpret_cast<float4*>(reinterpret_cast<char*>(p) + idx * 16u) = make_float4(u.re, u.im, v.re, v.im);
-    }
-};
 
-// [u; v] <- [[e0, e1], [conj e1, conj e0]] [u; v]
+// One spinor component of a point (component c at byte offset c * 2 sizeof(T)).
 template <typename T>
-__device__ __forceinline__ void apply_E(cpx<T>& u, cpx<T>& v, cpx<T> e0, cpx<T> e1) {
-    const cpx<T> nu = cmul(e0, u) + cmul(e1, v);
-    const cpx<T> nv = cmulc(u, e1) + cmulc(v, e0);
-    u = nu;
-    v = nv;
+__device__ __forceinline__ cpx<T> load_comp(const T* p, uint32_t idx, int c) {
+    const char* b = reinterpret_cast<const char*>(p) + idx * (uint32_t)(4 * sizeof(T)) + c * (uint32_t)(2 * sizeof(T));
+    if constexpr (sizeof(T) == 8) {
+        const double2 a = *reinterpret_cast<const double2*>(b);
+        return {(T)a.x, (T)a.y};
+    } else {
+        const float2 a = *reinterpret_cast<const float2*>(b);
+        return {(T)a.x, (T)a.y};
+    }
 }
-// flat: E = diag(e0, conj e0)
 template <typename T>
-__device__ __forceinline__ void apply_Ediag(cpx<T>& u, cpx<T>& v, cpx<T> e0) {
-    u = cmul(e0, u);
-    v = cmulc(v, e0);
+__device__ __forceinline__ void store_comp(T* p, uint32_t idx, int c, cpx<T> v) {
+    char* b = reinterpret_cast<char*>(p) + idx * (uint32_t)(4 * sizeof(T)) + c * (uint32_t)(2 * sizeof(T));
+    if constexpr (sizeof(T) == 8) *reinterpret_cast<double2*>(b) = make_double2(v.re, v.im);
+    else *reinterpret_cast<float2*>(b) = make_float2(v.re, v.im);
+}
+
+// Row c of E = [[e0, e1], [conj e1, conj e0]] applied to the point: the thread
+// holding component c gets A own + B other with A = e0, B = e1 (c = 0) or their
+// conjugates (c = 1); `other` is the partner lane's component.
+template <typename T>
+__device__ __forceinline__ cpx<T> apply_E_row(cpx<T> own, cpx<T> e0, cpx<T> e1, T sgn) {
+    const cpx<T> other = partner(own);
+    const cpx<T> A{e0.re, sgn * e0.im}, B{e1.re, sgn * e1.im};
+    return cmul(A, own) + cmul(B, other);
 }
 
 // Workgroup -> tile map that keeps neighbouring tiles on one XCD.  Workgroups
@@ -116,122 +106,125 @@ struct TwStage {
 // MODE 0: flat, no absorbing layer (b = 1: psi <- Xi; E uniform diagonal)
 // MODE 1: flat with layer (b = 1/S along the line; E uniform diagonal)
 // MODE 2: curved (b = a(x) [/S]; E from the per-point table)
-// One tile (L lines) of a direction stage, executed by F::NT threads.  lds and
-// twl are the workgroup's exchange buffer (F::LDS_ELEMS) and twiddle stage
-// (TwStage::ELEMS).  Every per-line operation depends on (T, N, R, MODE) only.
-template <typename T, int N, int R, int L, bool COLS, bool SPLIT, int MODE>
+// One tile (L lines) of a direction stage, executed by F::NT threads (one
+// spinor component per thread).  lds and twl are the workgroup's exchange
+// buffer (F::LDS_ELEMS) and twiddle stage (TwStage::ELEMS).  Every per-line
+// operation depends on (T, N, R, MODE) only.
+template <typename T, int N, int R, int L, bool COLS, int MODE>
 __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cpx<T>* lds, cpx<T>* twl) {
-    using F = LineFFT<T, N, R, L, COLS, SPLIT>;
+    using F = LineFFT<T, N, R, L, COLS>;
     using TS = TwStage<T, N>;
     constexpr int P = F::P;
     constexpr bool BLEND = MODE != 0;
     // prefetch symbols and blend weights before the transform when registers allow
-    constexpr bool PF = sizeof(T) * R <= 32;
-    const int tid = threadIdx.x;
-    const int l = COLS ? tid % L : tid / P;
-    const int j = COLS ? tid / L : tid % P;
-    const int line = tile * L + l;
+    constexpr bool PF = sizeof(T) * R <= 64 && F::NT <= 512;
+    const typename F::Coord c = F::coord(threadIdx.x);
+    const int line = tile * L + c.l;
     const bool valid = line < p.nlines;
     const uint32_t n1 = (uint32_t)p.n1;
+    const T sgn = c.comp ? T(-1) : T(1);
     auto gidx = [&](int pos) -> uint32_t { return COLS ? (uint32_t)pos * n1 + line : (uint32_t)line * n1 + pos; };
 
-    cpx<T> v[2][R];
+    cpx<T> v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (valid) PointIO<T>::load(p.psi, gidx(j + r * P), v[0][r], v[1][r]);
-        else v[0][r] = v[1][r] = cpx<T>{0, 0};
-    }
+    for (int r = 0; r < R; ++r) v[r] = valid ? load_comp(p.psi, gidx(c.j + r * P), c.comp) : cpx<T>{0, 0};
     const cpx<T>* tw = p.tw;
     if constexpr (TS::ON) {
-        for (int k = tid; k < N; k += F::NT) twl[k] = p.tw[k];
+        for (int k = threadIdx.x; k < N; k += F::NT) twl[k] = p.tw[k];
         tw = twl;
     }
     cpx<T> kk[PF ? R : 1];
     T bb[PF && BLEND ? R : 1];
     if constexpr (PF) {
 #pragma unroll
-        for (int s = 0; s < R; ++s) kk[s] = p.K[j + s * P];
+        for (int s = 0; s < R; ++s) kk[s] = p.K[c.j + s * P];
         if constexpr (BLEND) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 T b = T(1);
-                if constexpr (MODE == 2) b = valid ? *at(p.a, gidx(j + r * P)) : T(0);
-                if (MODE == 1 || p.inv_s) b *= p.inv_s[j + r * P];
+                if constexpr (MODE == 2) b = valid ? *at(p.a, gidx(c.j + r * P)) : T(0);
+                if (MODE == 1 || p.inv_s) b *= p.inv_s[c.j + r * P];
                 bb[r] = b;
             }
         }
     }
-    if (p.e_pre > 0 && valid) {
+    if (p.e_pre > 0) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if constexpr (MODE == 2) {
-                cpx<T> e0, e1;
-                PointIO<T>::load(p.E, gidx(j + r * P), e0, e1);
-                apply_E(v[0][r], v[1][r], e0, e1);
-                if (p.e_pre > 1) apply_E(v[0][r], v[1][r], e0, e1);
+                cpx<T> e0{0, 0}, e1{0, 0};
+                if (valid) {
+                    const uint32_t q = gidx(c.j + r * P);
+                    e0 = load_comp(p.E, q, 0);
+                    e1 = load_comp(p.E, q, 1);
+                }
+                v[r] = apply_E_row(v[r], e0, e1, sgn);
+                if (p.e_pre > 1) v[r] = apply_E_row(v[r], e0, e1, sgn);
             } else {
-                apply_Ediag(v[0][r], v[1][r], p.e0u);
-                if (p.e_pre > 1) apply_Ediag(v[0][r], v[1][r], p.e0u);
+                const cpx<T> e{p.e0u.re, sgn * p.e0u.im};
+                v[r] = cmul(e, v[r]);
+                if (p.e_pre > 1) v[r] = cmul(e, v[r]);
             }
         }
     }
-    cpx<T> old[BLEND ? 2 : 1][BLEND ? R : 1];
+    cpx<T> old[BLEND ? R : 1];
     if constexpr (BLEND) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) { old[0][r] = v[0][r]; old[1][r] = v[1][r]; }
+        for (int r = 0; r < R; ++r) old[r] = v[r];
     }
 
-    F::template fft<false>(v, lds, l, j, tw);
+    F::template fft<false>(v, lds, c, tw);
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-        const cpx<T> k = PF ? kk[PF ? s : 0] : p.K[j + s * P];      // (cos, sin) / n
-        const cpx<T> u = v[0][s], w = v[1][s];
-        if constexpr (!COLS) {                // K_x = cos I - i sin sigma_x
-            v[0][s] = scal(k.re, u) + mul_mi(scal(k.im, w));
-            v[1][s] = scal(k.re, w) + mul_mi(scal(k.im, u));
-        } else {                              // K_y = [[cos, -sin], [sin, cos]]
-            v[0][s] = scal(k.re, u) - scal(k.im, w);
-            v[1][s] = scal(k.re, w) + scal(k.im, u);
+        cpx<T> k;
+        if constexpr (PF) k = kk[s];
+        else k = p.K[c.j + s * P];                 // (cos, sin) / n
+        const cpx<T> other = partner(v[s]);
+        if constexpr (!COLS) {                     // K_x = cos I - i sin sigma_x
+            v[s] = scal(k.re, v[s]) + mul_mi(scal(k.im, other));
+        } else {                                   // K_y = [[cos, -sin], [sin, cos]]
+            v[s] = scal(k.re, v[s]) - scal(sgn * k.im, other);
         }
     }
-    F::template fft<true>(v, lds, l, j, tw);
+    F::template fft<true>(v, lds, c, tw);
 
-    if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        cpx<T> u = v[0][r], w = v[1][r];
+        cpx<T> u = v[r];
         if constexpr (BLEND) {
             T b;
             if constexpr (PF) {
                 b = bb[r];
             } else {
                 b = T(1);
-                if constexpr (MODE == 2) b = *at(p.a, gidx(j + r * P));
-                if (MODE == 1 || p.inv_s) b *= p.inv_s[j + r * P];
+                if constexpr (MODE == 2) b = valid ? *at(p.a, gidx(c.j + r * P)) : T(0);
+                if (MODE == 1 || p.inv_s) b *= p.inv_s[c.j + r * P];
             }
-            const T ob = T(1) - b;
-            u = scal(b, u) + scal(ob, old[0][r]);
-            w = scal(b, w) + scal(ob, old[1][r]);
+            u = scal(b, u) + scal(T(1) - b, old[r]);
         }
         if (p.e_post) {
             if constexpr (MODE == 2) {
-                cpx<T> e0, e1;
-                PointIO<T>::load(p.E, gidx(j + r * P), e0, e1);
-                apply_E(u, w, e0, e1);
+                cpx<T> e0{0, 0}, e1{0, 0};
+                if (valid) {
+                    const uint32_t q = gidx(c.j + r * P);
+                    e0 = load_comp(p.E, q, 0);
+                    e1 = load_comp(p.E, q, 1);
+                }
+                u = apply_E_row(u, e0, e1, sgn);
             } else {
-                apply_Ediag(u, w, p.e0u);
+                u = cmul(cpx<T>{p.e0u.re, sgn * p.e0u.im}, u);
             }
         }
-        PointIO<T>::store(p.psi, gidx(j + r * P), u, w);
+        if (valid) store_comp(p.psi, gidx(c.j + r * P), c.comp, u);
     }
 }
 
-template <typename T, int N, int R, int L, bool COLS, bool SPLIT, int MODE>
-__global__ void __launch_bounds__(N / R * L)
+template <typename T, int N, int R, int L, bool COLS, int MODE>
+__global__ void __launch_bounds__(2 * (N / R) * L)
 stage_kernel(StageParams<T> p) {
-    __shared__ cpx<T> lds[LineFFT<T, N, R, L, COLS, SPLIT>::LDS_ELEMS];
+    __shared__ cpx<T> lds[LineFFT<T, N, R, L, COLS>::LDS_ELEMS];
     __shared__ cpx<T> twl[TwStage<T, N>::ELEMS];
-    stage_tile<T, N, R, L, COLS, SPLIT, MODE>(p, xcd_tile(blockIdx.x, gridDim.x), lds, twl);
+    stage_tile<T, N, R, L, COLS, MODE>(p, xcd_tile(blockIdx.x, gridDim.x), lds, twl);
 }
 
 // Deterministic workgroup sum of NV doubles per thread into out[0..NV).
@@ -272,88 +265,78 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV], double* out) {
 // accumulates the density moments and the pointwise Hamiltonian terms.
 // partial layout: [sum|psi|^2, sum w|psi|^2, sum x|psi|^2, sum y|psi|^2,
 //                  energy re, energy im, non-finite count, 0]
-template <typename T, int N, int R, int L, bool COLS, bool SPLIT>
-__global__ void __launch_bounds__(N / R * L)
+template <typename T, int N, int R, int L, bool COLS>
+__global__ void __launch_bounds__(2 * (N / R) * L)
 obs_kernel(ObsParams p) {
-    using F = LineFFT<T, N, R, L, COLS, SPLIT>;
-    static_assert(F::NT % 64 == 0, "observable kernels reduce whole waves");
+    using F = LineFFT<T, N, R, L, COLS>;
     constexpr int P = F::P;
     __shared__ cpx<T> lds[F::LDS_ELEMS];
-    const int tid = threadIdx.x;
-    const int l = COLS ? tid % L : tid / P;
-    const int j = COLS ? tid / L : tid % P;
-    const int line = xcd_tile(blockIdx.x, gridDim.x) * L + l;
+    const typename F::Coord c = F::coord(threadIdx.x);
+    const int line = xcd_tile(blockIdx.x, gridDim.x) * L + c.l;
     const bool valid = line < p.nlines;
     const T* psi = static_cast<const T*>(p.psi);
     const T* D = static_cast<const T*>(p.D);
     const cpx<T>* tw = static_cast<const cpx<T>*>(p.tw);
+    const double sgn = c.comp ? -1.0 : 1.0;
 
-    cpx<T> v[2][R], old[2][R];
+    cpx<T> v[R], old[R];
     uint32_t idx[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int pos = j + r * P;
+        const int pos = c.j + r * P;
         idx[r] = COLS ? (uint32_t)pos * (uint32_t)p.n1 + line : (uint32_t)line * (uint32_t)p.n1 + pos;
-        if (valid) PointIO<T>::load(psi, idx[r], v[0][r], v[1][r]);
-        else v[0][r] = v[1][r] = cpx<T>{0, 0};
-        old[0][r] = v[0][r];
-        old[1][r] = v[1][r];
+        v[r] = valid ? load_comp(psi, idx[r], c.comp) : cpx<T>{0, 0};
+        old[r] = v[r];
     }
-    F::template fft<false>(v, lds, l, j, tw);
+    F::template fft<false>(v, lds, c, tw);
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-        const T d = D[j + s * P];
-        v[0][s] = mul_i(scal(d, v[0][s]));
-        v[1][s] = mul_i(scal(d, v[1][s]));
-    }
-    F::template fft<true>(v, lds, l, j, tw);
+    for (int s = 0; s < R; ++s) v[s] = mul_i(scal(D[c.j + s * P], v[s]));
+    F::template fft<true>(v, lds, c, tw);
 
+    // Each thread adds its component's share of the sums; the partner lane
+    // supplies the other component where the Hamiltonian mixes them.
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (valid) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint32_t q = idx[r];
-            const double p0r = old[0][r].re, p0i = old[0][r].im, p1r = old[1][r].re, p1i = old[1][r].im;
-            const double d0r = v[0][r].re, d0i = v[0][r].im, d1r = v[1][r].re, d1i = v[1][r].im;
-            const double w = p.w[q], ca = p.ca[q];
-            double er, ei;
-            if constexpr (!COLS) {
-                // psi^dag (-i ca sigma_x Dpsi) = -i ca (conj(p0) d1 + conj(p1) d0)
-                const double sr = p0r * d1r + p0i * d1i + p1r * d0r + p1i * d0i;
-                const double si = p0r * d1i - p0i * d1r + p1r * d0i - p1i * d0r;
-                er = ca * si;
-                ei = -ca * sr;
-                // psi^dag [-i (gx sx + gy sy) + V sz] psi
-                //  = conj(p0)[-i(gx - i gy) p1 + V p0] + conj(p1)[-i(gx + i gy) p0 - V p1]
-                const double gx = p.gx[q], gy = p.gy[q], V = p.V[q];
-                const double ar = -gy, ai = -gx;     // -i (gx - i gy)
-                const double br = gy, bi = -gx;      // -i (gx + i gy)
-                const double t1r = ar * p1r - ai * p1i, t1i = ar * p1i + ai * p1r;   // (..) p1
-                const double t2r = br * p0r - bi * p0i, t2i = br * p0i + bi * p0r;   // (..) p0
-                er += p0r * t1r + p0i * t1i + p1r * t2r + p1i * t2i;
-                ei += p0r * t1i - p0i * t1r + p1r * t2i - p1i * t2r;
-                const double dens0 = p0r * p0r + p0i * p0i, dens1 = p1r * p1r + p1i * p1i;
-                er += V * (dens0 - dens1);
-                const double dens = dens0 + dens1;
-                const int ix = COLS ? line : j + r * P;
-                const int iy = COLS ? j + r * P : line;
-                const double x = -p.a1 + ix * p.h1, y = -p.a2 + iy * p.h2;
-                acc[0] += dens;
-                acc[1] += w * dens;
-                acc[2] += x * dens;
-                acc[3] += y * dens;
-                const bool fin = isfinite(p0r) && isfinite(p0i) && isfinite(p1r) && isfinite(p1i);
-                acc[6] += fin ? 0.0 : 1.0;
-            } else {
-                // psi^dag (-i ca sigma_y Dpsi) = ca (-conj(p0) d1 + conj(p1) d0)
-                const double sr = -(p0r * d1r + p0i * d1i) + (p1r * d0r + p1i * d0i);
-                const double si = -(p0r * d1i - p0i * d1r) + (p1r * d0i - p1i * d0r);
-                er = ca * sr;
-                ei = ca * si;
-            }
-            acc[4] += w * er;
-            acc[5] += w * ei;
+    for (int r = 0; r < R; ++r) {
+        const cpx<T> dother = partner(v[r]);
+        const cpx<T> pother = partner(old[r]);
+        if (!valid) continue;
+        const uint32_t q = idx[r];
+        const double pr = old[r].re, pi = old[r].im;          // own component
+        const double orr = pother.re, oi = pother.im;         // other component
+        const double dr = dother.re, di = dother.im;          // derivative of the other component
+        const double w = p.w[q], ca = p.ca[q];
+        // conj(own) * D(other)
+        const double sr = pr * dr + pi * di, si = pr * di - pi * dr;
+        double er, ei;
+        if constexpr (!COLS) {
+            // -i ca (conj(p0) d1 + conj(p1) d0): this thread's term -i ca conj(own) D(other)
+            er = ca * si;
+            ei = -ca * sr;
+            // conj(own) [coef other] with coef = -i (gx - i gy) for component 0 and
+            // -i (gx + i gy) for component 1, plus +-V |own|^2
+            const double gx = p.gx[q], gy = p.gy[q], V = p.V[q];
+            const double ar = -sgn * gy, ai = -gx;
+            const double tr = ar * orr - ai * oi, ti = ar * oi + ai * orr;
+            er += pr * tr + pi * ti;
+            ei += pr * ti - pi * tr;
+            const double dens = pr * pr + pi * pi;
+            er += sgn * V * dens;
+            const int ix = COLS ? line : c.j + r * P;
+            const int iy = COLS ? c.j + r * P : line;
+            const double x = -p.a1 + ix * p.h1, y = -p.a2 + iy * p.h2;
+            acc[0] += dens;
+            acc[1] += w * dens;
+            acc[2] += x * dens;
+            acc[3] += y * dens;
+            acc[6] += (isfinite(pr) && isfinite(pi)) ? 0.0 : 1.0;
+        } else {
+            // ca (-conj(p0) d1 + conj(p1) d0): this thread's term -sgn ca conj(own) D(other)
+            er = -sgn * ca * sr;
+            ei = -sgn * ca * si;
         }
+        acc[4] += w * er;
+        acc[5] += w * ei;
     }
     block_sum<F::NT, 8>(acc, p.partials + 8 * (size_t)blockIdx.x);
 }

@@ -6,15 +6,17 @@
 #define DIRAC_PREC 1
 #define DIRAC_COLS false
 #define DIRAC_DIR 0
-REGO(512, 8, 1, 0)
-REG(512, 8, 2, 0)
-REGO(1024, 8, 1, 0)
-REG(1024, 8, 2, 0)
-REGO(2048, 8, 1, 0)
-REG(2048, 16, 1, 0)
-REG(2048, 16, 2, 0)
-REGO(4096, 8, 1, 0)
-REG(4096, 16, 1, 0)
-REG(4096, 16, 2, 0)
-REGO(8192, 16, 1, 0)
-REG(8192, 8, 1, 0)
+REGO(512, 8, 1)
+REG(512, 8, 2)
+REG(512, 16, 1)
+REG(512, 4, 1)
+REGO(1024, 8, 1)
+REG(1024, 16, 1)
+REG(1024, 8, 2)
+REGO(2048, 8, 1)
+REG(2048, 16, 1)
+REG(2048, 16, 2)
+REGO(4096, 16, 1)
+REG(4096, 8, 1)
+REG(4096, 16, 2)
+REGO(8192, 16, 1)

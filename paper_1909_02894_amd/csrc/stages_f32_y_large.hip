@@ -6,14 +6,16 @@
 #define DIRAC_PREC 1
 #define DIRAC_COLS true
 #define DIRAC_DIR 1
-REGO(512, 8, 8, 0)
-REG(512, 8, 4, 0)
-REGO(1024, 8, 4, 0)
-REG(1024, 8, 8, 0)
-REGO(2048, 8, 2, 0)
-REG(2048, 8, 4, 0)
-REG(2048, 16, 4, 0)
-REGO(4096, 16, 2, 0)
-REG(4096, 8, 2, 0)
-REGO(8192, 16, 1, 0)
-REG(8192, 8, 1, 0)
+REGO(512, 8, 4)
+REG(512, 8, 8)
+REG(512, 16, 8)
+REG(512, 16, 16)
+REGO(1024, 8, 4)
+REG(1024, 16, 4)
+REG(1024, 16, 8)
+REGO(2048, 8, 2)
+REG(2048, 16, 4)
+REG(2048, 16, 2)
+REGO(4096, 16, 2)
+REG(4096, 8, 1)
+REGO(8192, 16, 1)

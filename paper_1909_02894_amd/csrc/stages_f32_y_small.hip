@@ -6,14 +6,17 @@
 #define DIRAC_PREC 1
 #define DIRAC_COLS true
 #define DIRAC_DIR 1
-REGO(16, 4, 16, 0)
-REG(16, 4, 32, 0)
-REGO(32, 4, 8, 0)
-REG(32, 4, 16, 0)
-REGO(64, 8, 8, 0)
-REG(64, 8, 16, 0)
-REG(64, 4, 8, 0)
-REGO(128, 4, 8, 0)
-REG(128, 8, 8, 0)
-REG(128, 8, 16, 0)
-REGO(256, 8, 8, 0)
+REGO(16, 4, 16)
+REG(16, 4, 8)
+REGO(32, 4, 8)
+REG(32, 4, 4)
+REGO(64, 8, 8)
+REG(64, 4, 8)
+REG(64, 8, 16)
+REGO(128, 4, 8)
+REG(128, 8, 8)
+REG(128, 8, 16)
+REGO(256, 8, 8)
+REG(256, 8, 4)
+REG(256, 16, 8)
+REG(256, 16, 16)

@@ -6,11 +6,12 @@
 #define DIRAC_PREC 0
 #define DIRAC_COLS false
 #define DIRAC_DIR 0
-REGO(512, 4, 1, 0)
-REG(512, 8, 1, 0)
-REG(512, 8, 2, 0)
-REG(512, 8, 4, 0)
-REGO(1024, 8, 1, 0)
-REG(1024, 8, 2, 0)
-REGO(2048, 8, 1, 0)
-REGO(4096, 8, 1, 0)
+REGO(512, 4, 1)
+REG(512, 8, 1)
+REG(512, 8, 2)
+REGO(1024, 8, 1)
+REG(1024, 4, 1)
+REG(1024, 8, 2)
+REGO(2048, 8, 1)
+REG(2048, 4, 1)
+REGO(4096, 8, 1)

@@ -6,16 +6,17 @@
 #define DIRAC_PREC 0
 #define DIRAC_COLS false
 #define DIRAC_DIR 0
-REGO(16, 4, 16, 0)
-REG(16, 4, 32, 0)
-REGO(32, 4, 8, 0)
-REG(32, 4, 16, 0)
-REGO(64, 4, 4, 0)
-REG(64, 8, 8, 0)
-REG(64, 8, 16, 0)
-REGO(128, 4, 2, 0)
-REG(128, 8, 4, 0)
-REG(128, 8, 8, 0)
-REGO(256, 4, 1, 0)
-REG(256, 8, 2, 0)
-REG(256, 8, 4, 0)
+REGO(16, 4, 16)
+REG(16, 4, 8)
+REGO(32, 4, 8)
+REG(32, 4, 4)
+REGO(64, 4, 4)
+REG(64, 4, 2)
+REG(64, 8, 4)
+REGO(128, 4, 2)
+REG(128, 4, 1)
+REG(128, 8, 2)
+REG(128, 8, 4)
+REGO(256, 4, 1)
+REG(256, 8, 1)
+REG(256, 8, 2)

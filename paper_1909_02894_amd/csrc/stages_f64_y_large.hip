@@ -6,11 +6,11 @@
 #define DIRAC_PREC 0
 #define DIRAC_COLS true
 #define DIRAC_DIR 1
-REGO(512, 8, 2, 0)
-REG(512, 8, 4, 0)
-REG(512, 4, 2, 0)
-REGO(1024, 8, 4, 0)
-REG(1024, 8, 2, 0)
-REGO(2048, 8, 2, 0)
-REG(2048, 8, 1, 0)
-REGO(4096, 8, 1, 0)
+REGO(512, 8, 2)
+REG(512, 8, 4)
+REG(512, 4, 2)
+REGO(1024, 8, 4)
+REG(1024, 8, 2)
+REGO(2048, 8, 2)
+REG(2048, 8, 1)
+REGO(4096, 8, 1)

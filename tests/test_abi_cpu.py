@@ -85,4 +85,5 @@ def test_every_size_and_precision_has_kernels():
                 sch = D.schedules(n, prec, d)
                 assert sch, (prec, d, n)
                 for r, lines in sch:
-                    assert n % r == 0 and (n // r) * lines <= 1024
+                    # one spinor component per thread: 2 (n / r) lines threads per workgroup
+                    assert n % r == 0 and 2 * (n // r) * lines <= 1024 and (n // r) * lines % 32 == 0
