@@ -165,12 +165,15 @@ const char* dirac_last_error(void);
 
 /* --- schedules, timing and tuning ---------------------------------------------- */
 
-/* FFT schedule of one direction: register radix (2, 4, 8 or 16) and lines
- * (rows or columns) per workgroup.  Every per-line operation, and so every
- * result bit, depends on (n, precision, radix) only, never on lines_per_wg. */
+/* FFT schedule of one direction: register radix (4, 8 or 16), lines (rows or
+ * columns) per workgroup, and spinor components per thread (2: a thread holds
+ * both components of its points; 1: the two components sit in partner lanes of
+ * a wave).  Every per-line operation, and so every result bit, depends on
+ * (n, precision, radix) only, never on lines_per_wg or components_per_thread. */
 typedef struct {
     int32_t radix;
     int32_t lines_per_wg;
+    int32_t components_per_thread;
 } dirac_schedule;
 
 /* Number of compiled schedules for (n, precision, direction 0 = x / 1 = y) and
@@ -211,7 +214,7 @@ dirac_status dirac_tune_cache_load(const char* path);
  * step of a run is two kernel launches (direction x, then y) that each cover all
  * tiles of all solves still running, recorded once into a HIP graph and
  * replayed.  Solves keep their own device buffers (created with
- * dirac_create_metric, same precision as the batch, n1 and n2 <= 1024); the
+ * dirac_create_metric, same precision as the batch, n1 and n2 <= 2048); the
  * batch only holds descriptor tables in its own caller-given device buffer.
  * Radix per grid size is fixed (4 for n <= 64, else 8), so a solve's result is
  * bitwise the same alone in a batch, in any mix, and in the single-solve path

@@ -5,9 +5,9 @@
 // is still active at step k; the workgroup -> (solve, tile) map is a binary
 // search in the per-direction tile prefix of the solves, which are ordered by
 // their step counts (longest first), so the active solves are always a prefix.
-// All batch schedules use 256-thread workgroups (one spinor component per
-// thread): radix R = 4 for n <= 64, else 8, and L = 128 / (n / R) lines per
-// tile, for n up to 1024.  The per-line arithmetic is that of the
+// All batch schedules use 256-thread workgroups with both spinor components in
+// a thread: radix R = 4 for n <= 64, else 8, and L = 256 / (n / R) lines per
+// tile, for n up to 2048.  The per-line arithmetic is that of the
 // single-solve direction kernel with the same radix, so a solve's result is the
 // same bit for bit alone or in any mix.
 #pragma once
@@ -40,19 +40,20 @@ struct BatchPhase {
 };
 
 __host__ __device__ constexpr int batch_radix(int n) { return n <= 64 ? 4 : 8; }
-__host__ __device__ constexpr int batch_lines(int n) { return 128 / (n / batch_radix(n)); }
+__host__ __device__ constexpr int batch_lines(int n) { return 256 / (n / batch_radix(n)); }
+constexpr int kBatchCPT = 2;
 constexpr int kBatchThreads = 256;
 
 template <typename T, bool COLS, int N>
 __host__ __device__ constexpr size_t batch_smem_bytes() {
-    return (LineFFT<T, N, batch_radix(N), batch_lines(N), COLS>::LDS_ELEMS + TwStage<T, N>::ELEMS) *
+    return (LineFFT<T, N, batch_radix(N), batch_lines(N), COLS, kBatchCPT>::LDS_ELEMS + TwStage<T, N>::ELEMS) *
            sizeof(cpx<T>);
 }
 
 template <typename T, bool COLS, int N>
 __device__ __forceinline__ void batch_tile(const BatchDesc<T>& d, int tile, int k, char* smem) {
     constexpr int R = batch_radix(N), L = batch_lines(N);
-    using F = LineFFT<T, N, R, L, COLS>;
+    using F = LineFFT<T, N, R, L, COLS, kBatchCPT>;
     static_assert(F::NT == kBatchThreads, "batch schedules use 256-thread workgroups");
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
     cpx<T>* twl = lds + F::LDS_ELEMS;
@@ -69,9 +70,9 @@ __device__ __forceinline__ void batch_tile(const BatchDesc<T>& d, int tile, int 
     p.e_pre = COLS ? 0 : (k == 0 ? 1 : 2);
     p.e_post = COLS ? (k == d.steps - 1 ? 1 : 0) : 0;
     p.e0u = d.e0u;
-    if (d.mode == 0) stage_tile<T, N, R, L, COLS, 0>(p, tile, lds, twl);
-    else if (d.mode == 1) stage_tile<T, N, R, L, COLS, 1>(p, tile, lds, twl);
-    else stage_tile<T, N, R, L, COLS, 2>(p, tile, lds, twl);
+    if (d.mode == 0) stage_tile<T, N, R, L, COLS, 0, kBatchCPT>(p, tile, lds, twl);
+    else if (d.mode == 1) stage_tile<T, N, R, L, COLS, 1, kBatchCPT>(p, tile, lds, twl);
+    else stage_tile<T, N, R, L, COLS, 2, kBatchCPT>(p, tile, lds, twl);
 }
 
 template <typename T, bool COLS>
@@ -93,7 +94,8 @@ __global__ void __launch_bounds__(kBatchThreads) batch_stage_kernel(BatchPhase<T
         case 7: batch_tile<T, COLS, 128>(d, tile, ph.k, smem); break;
         case 8: batch_tile<T, COLS, 256>(d, tile, ph.k, smem); break;
         case 9: batch_tile<T, COLS, 512>(d, tile, ph.k, smem); break;
-        default: batch_tile<T, COLS, 1024>(d, tile, ph.k, smem); break;
+        case 10: batch_tile<T, COLS, 1024>(d, tile, ph.k, smem); break;
+        default: batch_tile<T, COLS, 2048>(d, tile, ph.k, smem); break;
     }
 }
 
@@ -102,7 +104,7 @@ constexpr size_t batch_smem_for_logn(int logn) {
     return logn == 4 ? batch_smem_bytes<T, COLS, 16>() : logn == 5 ? batch_smem_bytes<T, COLS, 32>()
          : logn == 6 ? batch_smem_bytes<T, COLS, 64>() : logn == 7 ? batch_smem_bytes<T, COLS, 128>()
          : logn == 8 ? batch_smem_bytes<T, COLS, 256>() : logn == 9 ? batch_smem_bytes<T, COLS, 512>()
-         : batch_smem_bytes<T, COLS, 1024>();
+         : logn == 10 ? batch_smem_bytes<T, COLS, 1024>() : batch_smem_bytes<T, COLS, 2048>();
 }
 
 }  // namespace dirac

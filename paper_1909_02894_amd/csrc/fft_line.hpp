@@ -133,21 +133,22 @@ __device__ __forceinline__ double partner(double x) {
 template <typename T>
 __device__ __forceinline__ cpx<T> partner(cpx<T> v) { return {partner(v.re), partner(v.im)}; }
 
-// One line geometry: N-point transform, R values per thread, L lines per
-// workgroup, COLS = lines are columns (line index fastest among threads, for
-// coalesced row segments).
+// One line geometry: N-point transform, R values per thread per component,
+// L lines per workgroup, COLS = lines are columns (line index fastest among
+// threads, for coalesced row segments), CPT = spinor components per thread.
 //
-// Each thread carries ONE spinor component: in every wave, lanes 0..31 hold
+// CPT = 2: a thread carries both components of its R points (NT = P L threads).
+// CPT = 1: a thread carries ONE component: in every wave, lanes 0..31 hold
 // component 0 and lanes 32..63 component 1 of the same 32 logical threads, so
 // the two components of a point sit in partner lanes (lane xor 32) and the
 // 2x2 mixes (half-step exponential, directional symbol) exchange them with one
-// permlane swap.  A line of N points is held by P = N / R logical threads;
-// a workgroup has NTL = P L logical and NT = 2 NTL physical threads.
-template <typename T, int N, int R, int L, bool COLS>
+// permlane swap (NT = 2 P L threads, half the registers per thread).
+// A line of N points is held by P = N / R logical threads.
+template <typename T, int N, int R, int L, bool COLS, int CPT>
 struct LineFFT {
     static constexpr int P = N / R;
     static constexpr int NTL = P * L;
-    static constexpr int NT = 2 * NTL;
+    static constexpr int NT = (CPT == 1 ? 2 : 1) * NTL;
     static constexpr int E = ilog(N, R);
     static constexpr int REM = N / ipow(R, E);
     static constexpr int NPASS = E + (REM > 1 ? 1 : 0);
@@ -158,9 +159,10 @@ struct LineFFT {
     static constexpr int ROW_STRIDE = N + N / R;
     static constexpr int COL_RAW = 2 * N * L;
     static constexpr int LDS_ELEMS = (NPASS > 1) ? (COLS ? COL_RAW + COL_RAW / 16 : L * 2 * ROW_STRIDE) : 1;
+    static_assert(CPT == 1 || CPT == 2, "components per thread");
     static_assert(N % R == 0, "R must divide N");
     static_assert(NPASS == 1 ? N == R : E >= 2, "schedule needs radix-R first and last passes");
-    static_assert(NTL % 32 == 0 && NT <= 1024, "32 logical threads per wave, at most 1024 threads");
+    static_assert((CPT == 2 || NTL % 32 == 0) && NT <= 1024, "32 logical threads per wave, <= 1024 threads");
 
     __host__ __device__ static constexpr int radix_of(int p) { return (p == 1 && REM > 1) ? REM : R; }
     __host__ __device__ static constexpr int ns_of(int p) {
@@ -176,34 +178,45 @@ struct LineFFT {
             return (l * 2 + comp) * ROW_STRIDE + pos + pos / R;
         }
     }
-    // Coordinates of physical thread t: component, line within the tile, and
-    // logical thread index j within the line.
+    // Coordinates of physical thread t: component (CPT = 1), line within the
+    // tile, and logical thread index j within the line.
     struct Coord { int comp, l, j; };
     __device__ static __forceinline__ Coord coord(int t) {
-        const int comp = (t >> 5) & 1;
-        const int u = ((t >> 6) << 5) | (t & 31);
-        return Coord{comp, COLS ? u % L : u / P, COLS ? u / L : u % P};
+        if constexpr (CPT == 1) {
+            const int comp = (t >> 5) & 1;
+            const int u = ((t >> 6) << 5) | (t & 31);
+            return Coord{comp, COLS ? u % L : u / P, COLS ? u / L : u % P};
+        } else {
+            return Coord{0, COLS ? t % L : t / P, COLS ? t / L : t % P};
+        }
     }
+    __device__ static __forceinline__ int slot(const Coord& c, int cc) { return CPT == 1 ? c.comp : cc; }
 
     // Exchange after pass PASS-1 and compute pass PASS (PASS >= 1).
     template <bool INV, int PASS>
-    __device__ static __forceinline__ void pass(cpx<T> (&v)[R], cpx<T>* lds, const Coord& c,
+    __device__ static __forceinline__ void pass(cpx<T> (&v)[CPT][R], cpx<T>* lds, const Coord& c,
                                                 const cpx<T>* __restrict__ tw) {
         constexpr int Rq = radix_of(PASS - 1), Nq = ns_of(PASS - 1);
         constexpr int Rp = radix_of(PASS), Ns = ns_of(PASS);
 #pragma unroll
-        for (int t = 0; t < R / Rq; ++t) {
-            const int jj = c.j + t * P;
-            const int base = (jj / Nq) * Nq * Rq + (jj % Nq);
+        for (int cc = 0; cc < CPT; ++cc) {
 #pragma unroll
-            for (int s = 0; s < Rq; ++s) lds[lidx(c.l, c.comp, base + s * Nq)] = v[t * Rq + s];
+            for (int t = 0; t < R / Rq; ++t) {
+                const int jj = c.j + t * P;
+                const int base = (jj / Nq) * Nq * Rq + (jj % Nq);
+#pragma unroll
+                for (int s = 0; s < Rq; ++s) lds[lidx(c.l, slot(c, cc), base + s * Nq)] = v[cc][t * Rq + s];
+            }
         }
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < R / Rp; ++t) {
-            const int jj = c.j + t * P;
+        for (int cc = 0; cc < CPT; ++cc) {
 #pragma unroll
-            for (int r = 0; r < Rp; ++r) v[t * Rp + r] = lds[lidx(c.l, c.comp, jj + r * (N / Rp))];
+            for (int t = 0; t < R / Rp; ++t) {
+                const int jj = c.j + t * P;
+#pragma unroll
+                for (int r = 0; r < Rp; ++r) v[cc][t * Rp + r] = lds[lidx(c.l, slot(c, cc), jj + r * (N / Rp))];
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -213,20 +226,24 @@ struct LineFFT {
 #pragma unroll
             for (int r = 1; r < Rp; ++r) {
                 const cpx<T> w = tw[r * k * (N / (Ns * Rp))];
-                v[t * Rp + r] = INV ? cmulc(v[t * Rp + r], w) : cmul(v[t * Rp + r], w);
+#pragma unroll
+                for (int cc = 0; cc < CPT; ++cc)
+                    v[cc][t * Rp + r] = INV ? cmulc(v[cc][t * Rp + r], w) : cmul(v[cc][t * Rp + r], w);
             }
-            dft<T, Rp, INV>(&v[t * Rp]);
+#pragma unroll
+            for (int cc = 0; cc < CPT; ++cc) dft<T, Rp, INV>(&v[cc][t * Rp]);
         }
         if constexpr (PASS + 1 < NPASS) pass<INV, PASS + 1>(v, lds, c, tw);
     }
 
-    // Transform this thread's component of the line.  Entry: v[r] = position
-    // j + r P.  Exit: v[s] = mode (forward) / position (inverse) j + s P.
+    // Transform the components this thread carries.  Entry: v[cc][r] = position
+    // j + r P.  Exit: v[cc][s] = mode (forward) / position (inverse) j + s P.
     // tw[k] = exp(-2 pi i k / N); the inverse uses conjugates and is unnormalised.
     template <bool INV>
-    __device__ static __forceinline__ void fft(cpx<T> (&v)[R], cpx<T>* lds, const Coord& c,
+    __device__ static __forceinline__ void fft(cpx<T> (&v)[CPT][R], cpx<T>* lds, const Coord& c,
                                                const cpx<T>* __restrict__ tw) {
-        dft<T, R, INV>(v);
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) dft<T, R, INV>(v[cc]);
         if constexpr (NPASS > 1) pass<INV, 1>(v, lds, c, tw);
     }
 };

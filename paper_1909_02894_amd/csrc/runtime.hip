@@ -121,7 +121,8 @@ Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* 
 
 const KernelEntry* find_entry(int prec, int n, int dir, const dirac_schedule& s) {
     for (const auto& e : kernel_registry())
-        if (e.prec == prec && e.n == n && e.dir == dir && e.radix == s.radix && e.lines == s.lines_per_wg)
+        if (e.prec == prec && e.n == n && e.dir == dir && e.radix == s.radix && e.lines == s.lines_per_wg &&
+            e.cpt == s.components_per_thread)
             return &e;
     return nullptr;
 }
@@ -142,7 +143,7 @@ struct TuneKey {
         return std::tie(prec, n, dir, other, mode) < std::tie(o.prec, o.n, o.dir, o.other, o.mode);
     }
 };
-struct TuneVal { int radix, lines; double ms; };
+struct TuneVal { int radix, lines, cpt; double ms; };
 static std::map<TuneKey, TuneVal>& tune_cache() { static std::map<TuneKey, TuneVal> c; return c; }
 static std::mutex& tune_mutex() { static std::mutex m; return m; }
 
@@ -153,7 +154,7 @@ const KernelEntry* pick_entry(int prec, int n, int dir, int other, int mode) {
         std::lock_guard<std::mutex> lk(tune_mutex());
         auto it = tune_cache().find(TuneKey{prec, n, dir, other, mode});
         if (it != tune_cache().end()) {
-            dirac_schedule sc{it->second.radix, it->second.lines};
+            dirac_schedule sc{it->second.radix, it->second.lines, it->second.cpt};
             if (const KernelEntry* e = find_entry(prec, n, dir, sc)) return e;
         }
     }
@@ -519,7 +520,12 @@ dirac_status dirac_schedule_get(int32_t n, int32_t prec, int32_t dir, int32_t i,
     int c = 0;
     for (const auto& e : kernel_registry()) {
         if (e.prec == prec && e.n == n && e.dir == dir) {
-            if (c == i) { out->radix = e.radix; out->lines_per_wg = e.lines; return DIRAC_OK; }
+            if (c == i) {
+                out->radix = e.radix;
+                out->lines_per_wg = e.lines;
+                out->components_per_thread = e.cpt;
+                return DIRAC_OK;
+            }
             ++c;
         }
     }
@@ -530,13 +536,16 @@ dirac_status dirac_get_schedule(const dirac_solver* s, int32_t dir, dirac_schedu
     if (!s || !out || dir < 0 || dir > 1) return fail(DIRAC_E_ARG, "bad arguments");
     out->radix = s->sched[dir]->radix;
     out->lines_per_wg = s->sched[dir]->lines;
+    out->components_per_thread = s->sched[dir]->cpt;
     return DIRAC_OK;
 }
 
 dirac_status dirac_set_schedule(dirac_solver* s, int32_t dir, const dirac_schedule* sch) {
     if (!s || !sch || dir < 0 || dir > 1) return fail(DIRAC_E_ARG, "bad arguments");
     const KernelEntry* e = find_entry(s->prec, dir == 0 ? s->g.n1 : s->g.n2, dir, *sch);
-    if (!e) return fail(DIRAC_E_ARG, "schedule radix %d lines %d not compiled", sch->radix, sch->lines_per_wg);
+    if (!e)
+        return fail(DIRAC_E_ARG, "schedule radix %d lines %d components %d not compiled", sch->radix,
+                    sch->lines_per_wg, sch->components_per_thread);
     s->sched[dir] = e;
     drop_graph(s);
     return DIRAC_OK;
@@ -620,7 +629,7 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
         }
         s->sched[dir] = best;
         std::lock_guard<std::mutex> lk(tune_mutex());
-        tune_cache()[TuneKey{s->prec, n, dir, other, mode}] = TuneVal{best->radix, best->lines, best_ms / reps};
+        tune_cache()[TuneKey{s->prec, n, dir, other, mode}] = TuneVal{best->radix, best->lines, best->cpt, best_ms / reps};
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -636,10 +645,10 @@ dirac_status dirac_tune_cache_save(const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return fail(DIRAC_E_ARG, "cannot open %s", path);
     std::lock_guard<std::mutex> lk(tune_mutex());
-    std::fprintf(f, "# prec n dir other mode radix lines ms_per_step\n");
+    std::fprintf(f, "# prec n dir other mode radix lines components ms_per_step\n");
     for (const auto& kv : tune_cache())
-        std::fprintf(f, "%d %d %d %d %d %d %d %.6g\n", kv.first.prec, kv.first.n, kv.first.dir, kv.first.other,
-                     kv.first.mode, kv.second.radix, kv.second.lines, kv.second.ms);
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %.6g\n", kv.first.prec, kv.first.n, kv.first.dir, kv.first.other,
+                     kv.first.mode, kv.second.radix, kv.second.lines, kv.second.cpt, kv.second.ms);
     std::fclose(f);
     return DIRAC_OK;
 }
@@ -654,8 +663,8 @@ dirac_status dirac_tune_cache_load(const char* path) {
         if (line[0] == '#') continue;
         TuneKey k{};
         TuneVal v{};
-        if (std::sscanf(line, "%d %d %d %d %d %d %d %lf", &k.prec, &k.n, &k.dir, &k.other, &k.mode, &v.radix,
-                        &v.lines, &v.ms) == 8)
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %d %lf", &k.prec, &k.n, &k.dir, &k.other, &k.mode, &v.radix,
+                        &v.lines, &v.cpt, &v.ms) == 9)
             tune_cache()[k] = v;
     }
     std::fclose(f);

@@ -75,16 +75,6 @@ __device__ __forceinline__ void store_comp(T* p, uint32_t idx, int c, cpx<T> v) 
     else *reinterpret_cast<float2*>(b) = make_float2(v.re, v.im);
 }
 
-// Row c of E = [[e0, e1], [conj e1, conj e0]] applied to the point: the thread
-// holding component c gets A own + B other with A = e0, B = e1 (c = 0) or their
-// conjugates (c = 1); `other` is the partner lane's component.
-template <typename T>
-__device__ __forceinline__ cpx<T> apply_E_row(cpx<T> own, cpx<T> e0, cpx<T> e1, T sgn) {
-    const cpx<T> other = partner(own);
-    const cpx<T> A{e0.re, sgn * e0.im}, B{e1.re, sgn * e1.im};
-    return cmul(A, own) + cmul(B, other);
-}
-
 // Workgroup -> tile map that keeps neighbouring tiles on one XCD.  Workgroups
 // are dispatched round-robin over the 8 XCDs, each with its own L2; tiles that
 // share cache lines (adjacent column tiles, adjacent rows of the per-point
@@ -106,28 +96,48 @@ struct TwStage {
 // MODE 0: flat, no absorbing layer (b = 1: psi <- Xi; E uniform diagonal)
 // MODE 1: flat with layer (b = 1/S along the line; E uniform diagonal)
 // MODE 2: curved (b = a(x) [/S]; E from the per-point table)
-// One tile (L lines) of a direction stage, executed by F::NT threads (one
-// spinor component per thread).  lds and twl are the workgroup's exchange
-// buffer (F::LDS_ELEMS) and twiddle stage (TwStage::ELEMS).  Every per-line
-// operation depends on (T, N, R, MODE) only.
-template <typename T, int N, int R, int L, bool COLS, int MODE>
+// One tile (L lines) of a direction stage, executed by F::NT threads.  lds and
+// twl are the workgroup's exchange buffer (F::LDS_ELEMS) and twiddle stage
+// (TwStage::ELEMS).  Every per-line operation depends on (T, N, R, MODE) only:
+// the 2x2 mixes are written per output component as (own, other) expressions
+// that are the same whether the other component sits in the same thread
+// (CPT = 2) or in the partner lane (CPT = 1), so results do not depend on L or CPT.
+template <typename T, int N, int R, int L, bool COLS, int MODE, int CPT>
 __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cpx<T>* lds, cpx<T>* twl) {
-    using F = LineFFT<T, N, R, L, COLS>;
+    using F = LineFFT<T, N, R, L, COLS, CPT>;
     using TS = TwStage<T, N>;
     constexpr int P = F::P;
     constexpr bool BLEND = MODE != 0;
     // prefetch symbols and blend weights before the transform when registers allow
-    constexpr bool PF = sizeof(T) * R <= 64 && F::NT <= 512;
+    constexpr bool PF = sizeof(T) * R * CPT <= 64 && F::NT <= 512;
     const typename F::Coord c = F::coord(threadIdx.x);
     const int line = tile * L + c.l;
     const bool valid = line < p.nlines;
     const uint32_t n1 = (uint32_t)p.n1;
-    const T sgn = c.comp ? T(-1) : T(1);
     auto gidx = [&](int pos) -> uint32_t { return COLS ? (uint32_t)pos * n1 + line : (uint32_t)line * n1 + pos; };
-
-    cpx<T> v[R];
+    auto comp_of = [&](int cc) { return CPT == 1 ? c.comp : cc; };
+    // v[cc][r] <- f(own, other, component, r) for every carried component
+    auto mix = [&](cpx<T> (&a)[CPT][R], auto&& f) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = valid ? load_comp(p.psi, gidx(c.j + r * P), c.comp) : cpx<T>{0, 0};
+        for (int r = 0; r < R; ++r) {
+            if constexpr (CPT == 1) {
+                const cpx<T> o = a[0][r];
+                a[0][r] = f(o, partner(o), c.comp, r);
+            } else {
+                const cpx<T> a0 = a[0][r], a1 = a[1][r];
+                a[0][r] = f(a0, a1, 0, r);
+                a[1][r] = f(a1, a0, 1, r);
+            }
+        }
+    };
+
+    cpx<T> v[CPT][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t q = gidx(c.j + r * P);
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) v[cc][r] = valid ? load_comp(p.psi, q, comp_of(cc)) : cpx<T>{0, 0};
+    }
     const cpx<T>* tw = p.tw;
     if constexpr (TS::ON) {
         for (int k = threadIdx.x; k < N; k += F::NT) twl[k] = p.tw[k];
@@ -135,96 +145,95 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     }
     cpx<T> kk[PF ? R : 1];
     T bb[PF && BLEND ? R : 1];
+    auto blend_weight = [&](int r) -> T {
+        T b = T(1);
+        if constexpr (MODE == 2) b = valid ? *at(p.a, gidx(c.j + r * P)) : T(0);
+        if (MODE == 1 || p.inv_s) b *= p.inv_s[c.j + r * P];
+        return b;
+    };
     if constexpr (PF) {
 #pragma unroll
         for (int s = 0; s < R; ++s) kk[s] = p.K[c.j + s * P];
         if constexpr (BLEND) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                T b = T(1);
-                if constexpr (MODE == 2) b = valid ? *at(p.a, gidx(c.j + r * P)) : T(0);
-                if (MODE == 1 || p.inv_s) b *= p.inv_s[c.j + r * P];
-                bb[r] = b;
-            }
+            for (int r = 0; r < R; ++r) bb[r] = blend_weight(r);
         }
     }
-    if (p.e_pre > 0) {
+    // Step 1 (and Step 5 of the previous step): row `comp` of
+    // E = [[e0, e1], [conj e1, conj e0]]: A own + B other with A = e0, B = e1 for
+    // component 0 and their conjugates for component 1.
+    auto applyE = [&](int times) {
+        if constexpr (MODE == 2) {
+            cpx<T> e0[R], e1[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if constexpr (MODE == 2) {
-                cpx<T> e0{0, 0}, e1{0, 0};
+            for (int r = 0; r < R; ++r) {
+                e0[r] = e1[r] = cpx<T>{0, 0};
                 if (valid) {
                     const uint32_t q = gidx(c.j + r * P);
-                    e0 = load_comp(p.E, q, 0);
-                    e1 = load_comp(p.E, q, 1);
+                    e0[r] = load_comp(p.E, q, 0);
+                    e1[r] = load_comp(p.E, q, 1);
                 }
-                v[r] = apply_E_row(v[r], e0, e1, sgn);
-                if (p.e_pre > 1) v[r] = apply_E_row(v[r], e0, e1, sgn);
-            } else {
-                const cpx<T> e{p.e0u.re, sgn * p.e0u.im};
-                v[r] = cmul(e, v[r]);
-                if (p.e_pre > 1) v[r] = cmul(e, v[r]);
             }
+            for (int t = 0; t < times; ++t)
+                mix(v, [&](cpx<T> own, cpx<T> other, int comp, int r) {
+                    const T sg = comp ? T(-1) : T(1);
+                    return cmul(cpx<T>{e0[r].re, sg * e0[r].im}, own) + cmul(cpx<T>{e1[r].re, sg * e1[r].im}, other);
+                });
+        } else {
+            for (int t = 0; t < times; ++t)
+                mix(v, [&](cpx<T> own, cpx<T>, int comp, int) {
+                    return cmul(cpx<T>{p.e0u.re, comp ? -p.e0u.im : p.e0u.im}, own);
+                });
         }
-    }
-    cpx<T> old[BLEND ? R : 1];
+    };
+    if (p.e_pre > 0) applyE(p.e_pre);
+    cpx<T> old[BLEND ? CPT : 1][BLEND ? R : 1];
     if constexpr (BLEND) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) old[r] = v[r];
+        for (int cc = 0; cc < CPT; ++cc)
+#pragma unroll
+            for (int r = 0; r < R; ++r) old[cc][r] = v[cc][r];
     }
 
     F::template fft<false>(v, lds, c, tw);
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
+    mix(v, [&](cpx<T> own, cpx<T> other, int comp, int s) {
         cpx<T> k;
         if constexpr (PF) k = kk[s];
-        else k = p.K[c.j + s * P];                 // (cos, sin) / n
-        const cpx<T> other = partner(v[s]);
-        if constexpr (!COLS) {                     // K_x = cos I - i sin sigma_x
-            v[s] = scal(k.re, v[s]) + mul_mi(scal(k.im, other));
-        } else {                                   // K_y = [[cos, -sin], [sin, cos]]
-            v[s] = scal(k.re, v[s]) - scal(sgn * k.im, other);
+        else k = p.K[c.j + s * P];                     // (cos, sin) / n
+        if constexpr (!COLS) {                         // K_x = cos I - i sin sigma_x
+            return scal(k.re, own) + mul_mi(scal(k.im, other));
+        } else {                                       // K_y = [[cos, -sin], [sin, cos]]
+            return scal(k.re, own) - scal(comp ? -k.im : k.im, other);
         }
-    }
+    });
     F::template fft<true>(v, lds, c, tw);
 
+    if constexpr (BLEND) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            T b;
+            if constexpr (PF) b = bb[r];
+            else b = blend_weight(r);
+#pragma unroll
+            for (int cc = 0; cc < CPT; ++cc) v[cc][r] = scal(b, v[cc][r]) + scal(T(1) - b, old[cc][r]);
+        }
+    }
+    if (p.e_post) applyE(1);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        cpx<T> u = v[r];
-        if constexpr (BLEND) {
-            T b;
-            if constexpr (PF) {
-                b = bb[r];
-            } else {
-                b = T(1);
-                if constexpr (MODE == 2) b = valid ? *at(p.a, gidx(c.j + r * P)) : T(0);
-                if (MODE == 1 || p.inv_s) b *= p.inv_s[c.j + r * P];
-            }
-            u = scal(b, u) + scal(T(1) - b, old[r]);
-        }
-        if (p.e_post) {
-            if constexpr (MODE == 2) {
-                cpx<T> e0{0, 0}, e1{0, 0};
-                if (valid) {
-                    const uint32_t q = gidx(c.j + r * P);
-                    e0 = load_comp(p.E, q, 0);
-                    e1 = load_comp(p.E, q, 1);
-                }
-                u = apply_E_row(u, e0, e1, sgn);
-            } else {
-                u = cmul(cpx<T>{p.e0u.re, sgn * p.e0u.im}, u);
-            }
-        }
-        if (valid) store_comp(p.psi, gidx(c.j + r * P), c.comp, u);
+        if (!valid) break;
+        const uint32_t q = gidx(c.j + r * P);
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) store_comp(p.psi, q, comp_of(cc), v[cc][r]);
     }
 }
 
-template <typename T, int N, int R, int L, bool COLS, int MODE>
-__global__ void __launch_bounds__(2 * (N / R) * L)
+template <typename T, int N, int R, int L, bool COLS, int MODE, int CPT>
+__global__ void __launch_bounds__((CPT == 1 ? 2 : 1) * (N / R) * L)
 stage_kernel(StageParams<T> p) {
-    __shared__ cpx<T> lds[LineFFT<T, N, R, L, COLS>::LDS_ELEMS];
+    __shared__ cpx<T> lds[LineFFT<T, N, R, L, COLS, CPT>::LDS_ELEMS];
     __shared__ cpx<T> twl[TwStage<T, N>::ELEMS];
-    stage_tile<T, N, R, L, COLS, MODE>(p, xcd_tile(blockIdx.x, gridDim.x), lds, twl);
+    stage_tile<T, N, R, L, COLS, MODE, CPT>(p, xcd_tile(blockIdx.x, gridDim.x), lds, twl);
 }
 
 // Deterministic workgroup sum of NV doubles per thread into out[0..NV).
@@ -265,10 +274,11 @@ __device__ __forceinline__ void block_sum(double (&acc)[NV], double* out) {
 // accumulates the density moments and the pointwise Hamiltonian terms.
 // partial layout: [sum|psi|^2, sum w|psi|^2, sum x|psi|^2, sum y|psi|^2,
 //                  energy re, energy im, non-finite count, 0]
-template <typename T, int N, int R, int L, bool COLS>
-__global__ void __launch_bounds__(2 * (N / R) * L)
+template <typename T, int N, int R, int L, bool COLS, int CPT>
+__global__ void __launch_bounds__((CPT == 1 ? 2 : 1) * (N / R) * L)
 obs_kernel(ObsParams p) {
-    using F = LineFFT<T, N, R, L, COLS>;
+    using F = LineFFT<T, N, R, L, COLS, CPT>;
+    static_assert(F::NT % 64 == 0, "observable kernels reduce whole waves");
     constexpr int P = F::P;
     __shared__ cpx<T> lds[F::LDS_ELEMS];
     const typename F::Coord c = F::coord(threadIdx.x);
@@ -277,66 +287,81 @@ obs_kernel(ObsParams p) {
     const T* psi = static_cast<const T*>(p.psi);
     const T* D = static_cast<const T*>(p.D);
     const cpx<T>* tw = static_cast<const cpx<T>*>(p.tw);
-    const double sgn = c.comp ? -1.0 : 1.0;
 
-    cpx<T> v[R], old[R];
+    cpx<T> v[CPT][R], old[CPT][R];
     uint32_t idx[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int pos = c.j + r * P;
         idx[r] = COLS ? (uint32_t)pos * (uint32_t)p.n1 + line : (uint32_t)line * (uint32_t)p.n1 + pos;
-        v[r] = valid ? load_comp(psi, idx[r], c.comp) : cpx<T>{0, 0};
-        old[r] = v[r];
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+            v[cc][r] = valid ? load_comp(psi, idx[r], CPT == 1 ? c.comp : cc) : cpx<T>{0, 0};
+            old[cc][r] = v[cc][r];
+        }
     }
     F::template fft<false>(v, lds, c, tw);
 #pragma unroll
-    for (int s = 0; s < R; ++s) v[s] = mul_i(scal(D[c.j + s * P], v[s]));
+    for (int s = 0; s < R; ++s)
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) v[cc][s] = mul_i(scal(D[c.j + s * P], v[cc][s]));
     F::template fft<true>(v, lds, c, tw);
 
-    // Each thread adds its component's share of the sums; the partner lane
-    // supplies the other component where the Hamiltonian mixes them.
+    // Each carried component adds its share of the sums; the other component
+    // (same thread, or the partner lane) enters where the Hamiltonian mixes them.
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const cpx<T> dother = partner(v[r]);
-        const cpx<T> pother = partner(old[r]);
-        if (!valid) continue;
-        const uint32_t q = idx[r];
-        const double pr = old[r].re, pi = old[r].im;          // own component
-        const double orr = pother.re, oi = pother.im;         // other component
-        const double dr = dother.re, di = dother.im;          // derivative of the other component
-        const double w = p.w[q], ca = p.ca[q];
-        // conj(own) * D(other)
-        const double sr = pr * dr + pi * di, si = pr * di - pi * dr;
-        double er, ei;
-        if constexpr (!COLS) {
-            // -i ca (conj(p0) d1 + conj(p1) d0): this thread's term -i ca conj(own) D(other)
-            er = ca * si;
-            ei = -ca * sr;
-            // conj(own) [coef other] with coef = -i (gx - i gy) for component 0 and
-            // -i (gx + i gy) for component 1, plus +-V |own|^2
-            const double gx = p.gx[q], gy = p.gy[q], V = p.V[q];
-            const double ar = -sgn * gy, ai = -gx;
-            const double tr = ar * orr - ai * oi, ti = ar * oi + ai * orr;
-            er += pr * tr + pi * ti;
-            ei += pr * ti - pi * tr;
-            const double dens = pr * pr + pi * pi;
-            er += sgn * V * dens;
-            const int ix = COLS ? line : c.j + r * P;
-            const int iy = COLS ? c.j + r * P : line;
-            const double x = -p.a1 + ix * p.h1, y = -p.a2 + iy * p.h2;
-            acc[0] += dens;
-            acc[1] += w * dens;
-            acc[2] += x * dens;
-            acc[3] += y * dens;
-            acc[6] += (isfinite(pr) && isfinite(pi)) ? 0.0 : 1.0;
-        } else {
-            // ca (-conj(p0) d1 + conj(p1) d0): this thread's term -sgn ca conj(own) D(other)
-            er = -sgn * ca * sr;
-            ei = -sgn * ca * si;
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+            cpx<T> dother, pother;
+            if constexpr (CPT == 1) {
+                dother = partner(v[0][r]);
+                pother = partner(old[0][r]);
+            } else {
+                dother = v[1 - cc][r];
+                pother = old[1 - cc][r];
+            }
+            const int comp = CPT == 1 ? c.comp : cc;
+            if (!valid) continue;
+            const double sgn = comp ? -1.0 : 1.0;
+            const uint32_t q = idx[r];
+            const double pr = old[cc][r].re, pi = old[cc][r].im;   // own component
+            const double orr = pother.re, oi = pother.im;          // other component
+            const double dr = dother.re, di = dother.im;           // derivative of the other component
+            const double w = p.w[q], ca = p.ca[q];
+            // conj(own) * D(other)
+            const double sr = pr * dr + pi * di, si = pr * di - pi * dr;
+            double er, ei;
+            if constexpr (!COLS) {
+                // -i ca (conj(p0) d1 + conj(p1) d0): this component's term -i ca conj(own) D(other)
+                er = ca * si;
+                ei = -ca * sr;
+                // conj(own) [coef other] with coef = -i (gx - i gy) for component 0 and
+                // -i (gx + i gy) for component 1, plus +-V |own|^2
+                const double gx = p.gx[q], gy = p.gy[q], V = p.V[q];
+                const double ar = -sgn * gy, ai = -gx;
+                const double tr = ar * orr - ai * oi, ti = ar * oi + ai * orr;
+                er += pr * tr + pi * ti;
+                ei += pr * ti - pi * tr;
+                const double dens = pr * pr + pi * pi;
+                er += sgn * V * dens;
+                const int ix = COLS ? line : c.j + r * P;
+                const int iy = COLS ? c.j + r * P : line;
+                const double x = -p.a1 + ix * p.h1, y = -p.a2 + iy * p.h2;
+                acc[0] += dens;
+                acc[1] += w * dens;
+                acc[2] += x * dens;
+                acc[3] += y * dens;
+                acc[6] += (isfinite(pr) && isfinite(pi)) ? 0.0 : 1.0;
+            } else {
+                // ca (-conj(p0) d1 + conj(p1) d0): this component's term -sgn ca conj(own) D(other)
+                er = -sgn * ca * sr;
+                ei = -sgn * ca * si;
+            }
+            acc[4] += w * er;
+            acc[5] += w * ei;
         }
-        acc[4] += w * er;
-        acc[5] += w * ei;
     }
     block_sum<F::NT, 8>(acc, p.partials + 8 * (size_t)blockIdx.x);
 }

@@ -1,22 +1,26 @@
-// Direction-x (rows) kernel schedules, FP32, n = 512..8192.  The first entry per n
-// is the default schedule and also carries the observable kernel.
+// Direction-x (rows) kernel schedules, FP32, n = 512..8192: REG(n, radix,
+// lines per workgroup, spinor components per thread).  The first entry per n is
+// the default schedule and also carries the observable kernel.
 #include "stage_kernels.hpp"
 #include "registry.hpp"
 #define DIRAC_T float
 #define DIRAC_PREC 1
 #define DIRAC_COLS false
 #define DIRAC_DIR 0
-REGO(512, 8, 1)
-REG(512, 8, 2)
-REG(512, 16, 1)
-REG(512, 4, 1)
-REGO(1024, 8, 1)
-REG(1024, 16, 1)
-REG(1024, 8, 2)
-REGO(2048, 8, 1)
-REG(2048, 16, 1)
-REG(2048, 16, 2)
-REGO(4096, 16, 1)
-REG(4096, 8, 1)
-REG(4096, 16, 2)
-REGO(8192, 16, 1)
+REGO(512, 4, 1, 1)
+REG(512, 8, 1, 2)
+REG(512, 8, 1, 1)
+REG(512, 8, 2, 2)
+REGO(1024, 8, 2, 2)
+REG(1024, 8, 1, 1)
+REG(1024, 8, 1, 2)
+REG(1024, 16, 1, 2)
+REGO(2048, 8, 1, 2)
+REG(2048, 16, 1, 2)
+REG(2048, 8, 1, 1)
+REG(2048, 16, 1, 1)
+REGO(4096, 16, 1, 2)
+REG(4096, 8, 1, 2)
+REG(4096, 16, 2, 1)
+REGO(8192, 16, 1, 2)
+REG(8192, 16, 1, 1)

@@ -55,7 +55,7 @@ class Obs(C.Structure):
 
 
 class Schedule(C.Structure):
-    _fields_ = [("radix", C.c_int32), ("lines_per_wg", C.c_int32)]
+    _fields_ = [("radix", C.c_int32), ("lines_per_wg", C.c_int32), ("components_per_thread", C.c_int32)]
 
 
 class DiracError(RuntimeError):
@@ -195,7 +195,7 @@ def schedules(n: int, precision: int, direction: int):
     for i in range(lib.dirac_schedule_count(n, precision, direction)):
         s = Schedule()
         _check(lib.dirac_schedule_get(n, precision, direction, i, C.byref(s)))
-        out.append((s.radix, s.lines_per_wg))
+        out.append((s.radix, s.lines_per_wg, s.components_per_thread))
     return out
 
 
@@ -256,10 +256,10 @@ class Solver:
     def schedule(self, direction):
         s = Schedule()
         _check(lib.dirac_get_schedule(self.h, direction, C.byref(s)))
-        return (s.radix, s.lines_per_wg)
+        return (s.radix, s.lines_per_wg, s.components_per_thread)
 
-    def set_schedule(self, direction, radix, lines):
-        s = Schedule(radix, lines)
+    def set_schedule(self, direction, radix, lines, components=2):
+        s = Schedule(radix, lines, components)
         _check(lib.dirac_set_schedule(self.h, direction, C.byref(s)))
 
     def set_launch_mode(self, use_graph: bool, chunk: int = 32):

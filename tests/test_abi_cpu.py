@@ -84,6 +84,7 @@ def test_every_size_and_precision_has_kernels():
                     continue
                 sch = D.schedules(n, prec, d)
                 assert sch, (prec, d, n)
-                for r, lines in sch:
-                    # one spinor component per thread: 2 (n / r) lines threads per workgroup
-                    assert n % r == 0 and 2 * (n // r) * lines <= 1024 and (n // r) * lines % 32 == 0
+                for r, lines, cpt in sch:
+                    # cpt = 1: 2 (n / r) lines threads, 32 logical threads per wave
+                    nt = (n // r) * lines * (2 if cpt == 1 else 1)
+                    assert n % r == 0 and nt <= 1024 and (cpt == 2 or (n // r) * lines % 32 == 0)

@@ -44,8 +44,8 @@ def single_path(D, spec, prec, steps):
     s = D.Solver.from_spec(spec, precision=prec)
     for d, n in ((0, spec.n1), (1, spec.n2)):
         r = batch_radix(n)
-        lines = [l for (rr, l) in D.schedules(n, prec, d) if rr == r][0]
-        s.set_schedule(d, r, lines)
+        lines, cpt = [(l, c) for (rr, l, c) in D.schedules(n, prec, d) if rr == r][0]
+        s.set_schedule(d, r, lines, cpt)
     s.set_initial_spinor(W.initial_spinor(spec))
     s.step_n(steps)
     return s.get_spinor()

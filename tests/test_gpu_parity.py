@@ -203,17 +203,17 @@ def test_every_schedule_agrees(D):
     _, o = oracle_run(spec, 3)
     results = {}
     for d in (0, 1):
-        for (r, lines) in D.schedules(512, 0, d):
+        for (r, lines, cpt) in D.schedules(512, 0, d):
             s = D.Solver.from_spec(spec)
-            s.set_schedule(d, r, lines)
+            s.set_schedule(d, r, lines, cpt)
             s.set_initial_spinor(W.initial_spinor(spec))
             s.step_n(3)
             out = s.get_spinor()
             assert O.rel_l2(out, o[3]) < TOL64, (d, r, lines)
-            results[(d, r, lines)] = out
-    # lines per workgroup never changes a bit
-    for (d, r, lines), out in results.items():
-        for (d2, r2, l2), out2 in results.items():
+            results[(d, r, lines, cpt)] = out
+    # neither lines per workgroup nor components per thread changes a bit
+    for (d, r, lines, cpt), out in results.items():
+        for (d2, r2, l2, c2), out2 in results.items():
             if d == d2 and r == r2:
                 assert np.array_equal(out, out2)
 
