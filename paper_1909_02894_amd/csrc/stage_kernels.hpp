@@ -68,6 +68,30 @@ __device__ __forceinline__ cpx<T> load_comp(const T* p, uint32_t idx, int c) {
         return {(T)a.x, (T)a.y};
     }
 }
+// Both components of a point in one access (16 B for FP32) or two (FP64).
+template <typename T>
+__device__ __forceinline__ void load_point(const T* p, uint32_t idx, cpx<T>& u, cpx<T>& v) {
+    const char* b = reinterpret_cast<const char*>(p) + idx * (uint32_t)(4 * sizeof(T));
+    if constexpr (sizeof(T) == 8) {
+        const double2 A = reinterpret_cast<const double2*>(b)[0], B = reinterpret_cast<const double2*>(b)[1];
+        u = {(T)A.x, (T)A.y};
+        v = {(T)B.x, (T)B.y};
+    } else {
+        const float4 A = *reinterpret_cast<const float4*>(b);
+        u = {(T)A.x, (T)A.y};
+        v = {(T)A.z, (T)A.w};
+    }
+}
+template <typename T>
+__device__ __forceinline__ void store_point(T* p, uint32_t idx, cpx<T> u, cpx<T> v) {
+    char* b = reinterpret_cast<char*>(p) + idx * (uint32_t)(4 * sizeof(T));
+    if constexpr (sizeof(T) == 8) {
+        reinterpret_cast<double2*>(b)[0] = make_double2(u.re, u.im);
+        reinterpret_cast<double2*>(b)[1] = make_double2(v.re, v.im);
+    } else {
+        *reinterpret_cast<float4*>(b) = make_float4(u.re, u.im, v.re, v.im);
+    }
+}
 template <typename T>
 __device__ __forceinline__ void store_comp(T* p, uint32_t idx, int c, cpx<T> v) {
     char* b = reinterpret_cast<char*>(p) + idx * (uint32_t)(4 * sizeof(T)) + c * (uint32_t)(2 * sizeof(T));
@@ -115,7 +139,6 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     const bool valid = line < p.nlines;
     const uint32_t n1 = (uint32_t)p.n1;
     auto gidx = [&](int pos) -> uint32_t { return COLS ? (uint32_t)pos * n1 + line : (uint32_t)line * n1 + pos; };
-    auto comp_of = [&](int cc) { return CPT == 1 ? c.comp : cc; };
     // v[cc][r] <- f(own, other, component, r) for every carried component
     auto mix = [&](cpx<T> (&a)[CPT][R], auto&& f) {
 #pragma unroll
@@ -135,8 +158,12 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t q = gidx(c.j + r * P);
-#pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) v[cc][r] = valid ? load_comp(p.psi, q, comp_of(cc)) : cpx<T>{0, 0};
+        if constexpr (CPT == 1) {
+            v[0][r] = valid ? load_comp(p.psi, q, c.comp) : cpx<T>{0, 0};
+        } else {
+            v[0][r] = v[1][r] = cpx<T>{0, 0};
+            if (valid) load_point(p.psi, q, v[0][r], v[1][r]);
+        }
     }
     const cpx<T>* tw = p.tw;
     if constexpr (TS::ON) {
@@ -168,11 +195,7 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 e0[r] = e1[r] = cpx<T>{0, 0};
-                if (valid) {
-                    const uint32_t q = gidx(c.j + r * P);
-                    e0[r] = load_comp(p.E, q, 0);
-                    e1[r] = load_comp(p.E, q, 1);
-                }
+                if (valid) load_point(p.E, gidx(c.j + r * P), e0[r], e1[r]);
             }
             for (int t = 0; t < times; ++t)
                 mix(v, [&](cpx<T> own, cpx<T> other, int comp, int r) {
@@ -223,8 +246,8 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     for (int r = 0; r < R; ++r) {
         if (!valid) break;
         const uint32_t q = gidx(c.j + r * P);
-#pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) store_comp(p.psi, q, comp_of(cc), v[cc][r]);
+        if constexpr (CPT == 1) store_comp(p.psi, q, c.comp, v[0][r]);
+        else store_point(p.psi, q, v[0][r], v[1][r]);
     }
 }
 
@@ -294,11 +317,14 @@ obs_kernel(ObsParams p) {
     for (int r = 0; r < R; ++r) {
         const int pos = c.j + r * P;
         idx[r] = COLS ? (uint32_t)pos * (uint32_t)p.n1 + line : (uint32_t)line * (uint32_t)p.n1 + pos;
-#pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) {
-            v[cc][r] = valid ? load_comp(psi, idx[r], CPT == 1 ? c.comp : cc) : cpx<T>{0, 0};
-            old[cc][r] = v[cc][r];
+        if constexpr (CPT == 1) {
+            v[0][r] = valid ? load_comp(psi, idx[r], c.comp) : cpx<T>{0, 0};
+        } else {
+            v[0][r] = v[1][r] = cpx<T>{0, 0};
+            if (valid) load_point(psi, idx[r], v[0][r], v[1][r]);
         }
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) old[cc][r] = v[cc][r];
     }
     F::template fft<false>(v, lds, c, tw);
 #pragma unroll
