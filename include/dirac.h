@@ -49,7 +49,8 @@ enum {
     DIRAC_E_NOMEM = -4,      /* host allocation failed                          */
     DIRAC_E_DEVICE = -5,     /* a HIP call failed                               */
     DIRAC_E_STATE = -6,      /* call out of order (e.g. step before set_initial)*/
-    DIRAC_E_NONFINITE = -7   /* non-finite values in an input array              */
+    DIRAC_E_NONFINITE = -7,  /* non-finite values in an input array              */
+    DIRAC_E_NOCONV = -8      /* the Scheme I linear solve did not converge       */
 };
 
 /* Arithmetic of the state, FFTs and pointwise stages.  DIRAC_FP32 keeps the
@@ -117,6 +118,25 @@ typedef struct {
 
 typedef struct dirac_solver dirac_solver;
 
+/* Time integrator.
+ *  DIRAC_SCHEME_EXP_SPLIT (default): Numerical Scheme II, the exponential
+ *    directional step of Sec. 5.2 (eq. (second_scheme)); needs real blend
+ *    coefficients b = a/S in [0, 1].
+ *  DIRAC_SCHEME_CN_GMRES: Numerical Scheme I of Sec. 5.1 (eq. (cn)): Step 1, the
+ *    Crank-Nicolson transport step G psi* = G~ psi with
+ *    G = I + (dt/2) alpha(x).T, G~ = I - (dt/2) alpha(x).T (spectral derivative of
+ *    eq. (trick), alpha(x).T = c (b_x sigma_x d_x + b_y sigma_y d_y)), solved by
+ *    restarted GMRES on the device, then Step 3.  Unconditionally stable for any
+ *    real b (so b > 1 is accepted); FP64 only, n1, n2 <= 2048. */
+enum { DIRAC_SCHEME_EXP_SPLIT = 0, DIRAC_SCHEME_CN_GMRES = 1 };
+typedef struct {
+    int32_t scheme;          /* DIRAC_SCHEME_*                                         */
+    int32_t gmres_restart;   /* Krylov vectors per cycle, 2..63 (0 = 20)                */
+    int32_t gmres_max_iter;  /* total iterations per step before DIRAC_E_NOCONV (0 = 400) */
+    int32_t reserved;
+    double gmres_rtol;       /* stop at ||G x - b|| <= rtol ||b|| (0 = 1e-13)           */
+} dirac_scheme;
+
 /* Bytes of device memory a solver needs (including 256-byte alignment slack).
  * Returns 0 for invalid arguments. */
 size_t dirac_footprint_bytes(const dirac_grid* grid, const dirac_metric* metric,
@@ -134,6 +154,18 @@ dirac_status dirac_create_metric(const dirac_grid* grid, const dirac_metric* met
                                  const dirac_pml* pml, int32_t precision,
                                  void* device_buffer, size_t bytes, void* hip_stream,
                                  dirac_solver** out);
+
+/* Footprint and creation with an explicit time integrator (scheme NULL = the
+ * default Scheme II); dirac_create_metric(...) = dirac_create_solver(..., NULL, ...). */
+size_t dirac_footprint_bytes_scheme(const dirac_grid* grid, const dirac_metric* metric, const dirac_pml* pml,
+                                    int32_t precision, const dirac_scheme* scheme);
+dirac_status dirac_create_solver(const dirac_grid* grid, const dirac_metric* metric, const dirac_pml* pml,
+                                 int32_t precision, const dirac_scheme* scheme, void* device_buffer,
+                                 size_t bytes, void* hip_stream, dirac_solver** out);
+
+/* Scheme I statistics since creation: total GMRES iterations, and the relative
+ * residual reached by the last solve. */
+dirac_status dirac_cn_stats(const dirac_solver* s, int64_t* iterations, double* last_rel_residual);
 
 /* Upload the initial spinor (host [n2][n1][2] complex128, not normalised) and
  * reset the step counter and time to 0.  Synchronises the stream. */

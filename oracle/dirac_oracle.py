@@ -512,3 +512,75 @@ def flat_discrete_frequency(xi_x: float, xi_y: float, m: float, c: float, dt: fl
 
 def rel_l2(a: np.ndarray, ref: np.ndarray) -> float:
     return float(np.linalg.norm((a - ref).ravel()) / np.linalg.norm(ref.ravel()))
+
+
+# ---------------------------------------------------------------------------
+# Numerical Scheme I (Sec. 5.1): Crank-Nicolson transport step solved by GMRES
+# ---------------------------------------------------------------------------
+
+def transport_operator(psi: np.ndarray, T: Tables) -> np.ndarray:
+    """alpha(x) . T psi of eq. (hamiltonian_pml) for the 2-D equation: the
+    transport part c a(x) (sigma_x [[d_x]] / S^1 + sigma_y [[d_y]] / S^2) psi with the
+    spectral derivative of eq. (trick); the blend coefficients b_i = a / S^i carry
+    the layer (Appendix A: a / S_x, a / S_y)."""
+    c = T.prob.c
+    dx = spectral_derivative(psi, 1, T.xi1)
+    dy = spectral_derivative(psi, 0, T.xi2)
+    sx = np.stack([dx[..., 1], dx[..., 0]], axis=-1)                  # sigma_x dx
+    sy = np.stack([-1j * dy[..., 1], 1j * dy[..., 0]], axis=-1)       # sigma_y dy
+    return c * (T.bx[..., None] * sx + T.by[..., None] * sy)
+
+
+def cn_operators(T: Tables):
+    """G = I + (dt/2) alpha . T and G~ = I - (dt/2) alpha . T (Sec. 5.1, eq. (cn))."""
+    h = T.prob.dt / 2.0
+    G = lambda v: v + h * transport_operator(v, T)
+    Gt = lambda v: v - h * transport_operator(v, T)
+    return G, Gt
+
+
+def cn_solve(rhs: np.ndarray, T: Tables, x0: np.ndarray | None = None, rtol: float = 1e-14,
+             restart: int = 30, maxiter: int = 200) -> np.ndarray:
+    """Solve G x = rhs with GMRES (the Krylov solver the paper names, through
+    scipy's implementation)."""
+    import scipy.sparse.linalg as spla
+    shape = rhs.shape
+    n = rhs.size
+    G, _ = cn_operators(T)
+    A = spla.LinearOperator((n, n), matvec=lambda v: G(v.reshape(shape)).ravel(), dtype=np.complex128)
+    x, info = spla.gmres(A, rhs.ravel(), x0=None if x0 is None else x0.ravel(), rtol=rtol, atol=0.0,
+                         restart=restart, maxiter=maxiter)
+    if info != 0:
+        raise RuntimeError(f"GMRES did not converge (info={info})")
+    return x.reshape(shape)
+
+
+def cn_step(psi: np.ndarray, T: Tables, rtol: float = 1e-14) -> np.ndarray:
+    """One step of Scheme I, eq. (cn): Step 1 (E), G psi* = G~ psi^{n+1/2}, Step 3 (E)."""
+    half = apply_pointwise(T.E, psi)
+    _, Gt = cn_operators(T)
+    star = cn_solve(Gt(half), T, x0=half, rtol=rtol)
+    return apply_pointwise(T.E, star)
+
+
+def cn_run(psi0: np.ndarray, T: Tables, nsteps: int, rtol: float = 1e-14) -> np.ndarray:
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    for _ in range(nsteps):
+        psi = cn_step(psi, T, rtol)
+    return psi
+
+
+def cn_flat_exact(psi0: np.ndarray, n1: int, n2: int, a1: float, a2: float, m: float, c: float, dt: float,
+                  nsteps: int) -> np.ndarray:
+    """Flat Scheme I per Fourier mode: (A C A)^n with the Cayley factor
+    C = (I + (dt/2) c i sigma.xi)^{-1} (I - (dt/2) c i sigma.xi)."""
+    xi1 = wavenumbers(n1, a1)
+    xi2 = wavenumbers(n2, a2)
+    XI, YI = np.meshgrid(xi1, xi2)
+    mu = dt * m * c * c / 2.0
+    A = np.diag([np.exp(-1j * mu), np.exp(1j * mu)])
+    S = 1j * (dt / 2.0) * c * (XI[..., None, None] * SIGMA_X + YI[..., None, None] * SIGMA_Y)
+    Cay = np.linalg.solve(ID2 + S, ID2 - S)
+    U = A @ Cay @ A
+    P = np.fft.fft2(psi0, axes=(0, 1))
+    return np.fft.ifft2(apply_pointwise(np.linalg.matrix_power(U, nsteps), P), axes=(0, 1))

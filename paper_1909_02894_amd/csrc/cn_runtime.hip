@@ -1,0 +1,210 @@
+// cn_runtime.hip -- host driver of Numerical Scheme I (Sec. 5.1, eq. (cn)):
+//   psi^{n+1/2} = E psi^n                                  (Step 1)
+//   G psi* = G~ psi^{n+1/2}, solved by restarted GMRES      (Step 2, Crank-Nicolson)
+//   psi^{n+1} = E psi*                                      (Step 3)
+// with G = I + (dt/2) alpha.T and G~ = I - (dt/2) alpha.T.  Every vector operation
+// runs on the device; the host holds only the small Hessenberg least-squares
+// problem of each GMRES cycle (Givens rotations, back substitution), and reads
+// one column of it per Arnoldi iteration.
+//
+// GMRES(m): Arnoldi with classical Gram-Schmidt applied twice (CGS2), started
+// from x0 = psi^{n+1/2}; a cycle ends when the rotated residual estimate falls
+// below rtol ||G~ psi||, and the next cycle's explicit residual b - G x decides
+// convergence, so the reported residual is always a true one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "../../include/dirac.h"
+#include "cn_kernels.hpp"
+#include "solver.hpp"
+
+namespace dirac {
+
+namespace {
+
+using zd = std::complex<double>;
+
+struct CnCtx {
+    dirac_solver* s;
+    hipStream_t st;
+    size_t npts, ncplx, vstride;      // vstride in doubles
+    double* psi;
+    double* rhs;
+    double* work;
+    double* V;                        // Krylov basis, m + 1 vectors
+    double* part;
+    double* coef;                     // [4][64] complex: h pass 1, h pass 2, norm, update
+    double h;                         // (dt / 2) c
+
+    double* vec(int k) const { return V + (size_t)k * vstride; }
+    double* coef_row(int r) const { return coef + (size_t)r * 128; }
+};
+
+#define CN_TRY(expr, what)                                                                              \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail(DIRAC_E_DEVICE, "%s: %s", (what), hipGetErrorString(e_));    \
+    } while (0)
+
+// out = in + sign (dt/2) alpha.T in: the x pass writes out, the y pass accumulates.
+hipError_t apply_G(const CnCtx& c, const double* in, double* out, double sign) {
+    dirac_solver* s = c.s;
+    char* b = s->base;
+    for (int dir = 0; dir < 2; ++dir) {
+        CnApplyParams p{};
+        p.in = in;
+        p.out = out;
+        p.a = s->curved ? reinterpret_cast<const double*>(b + s->lay.a) : nullptr;
+        p.inv_s = s->pml ? reinterpret_cast<const double*>(b + s->lay.inv_s[dir]) : nullptr;
+        p.D = reinterpret_cast<const double*>(b + s->lay.D[dir]);
+        p.tw = reinterpret_cast<const cpx<double>*>(b + s->lay.tw[dir]);
+        p.n1 = s->g.n1;
+        p.nlines = dir == 0 ? s->g.n2 : s->g.n1;
+        p.scale = sign * c.h;
+        hipError_t e = launch_cn_apply(dir, dir == 0 ? s->g.n1 : s->g.n2, p.nlines, p, c.st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ||v||^2 into coef row `row`, slot 0 (device), fixed-order reduction.
+hipError_t norm2_dev(const CnCtx& c, const double* v, int row) {
+    return launch_cn_dots(v, 0, 1, v, c.ncplx, c.part, kCnDotBlocks, 64, c.coef_row(row), c.st);
+}
+
+dirac_status read_coef(const CnCtx& c, double* host, size_t doubles) {
+    CN_TRY(hipMemcpyAsync(host, c.coef, doubles * sizeof(double), hipMemcpyDeviceToHost, c.st), "read GMRES coefficients");
+    CN_TRY(hipStreamSynchronize(c.st), "synchronise GMRES");
+    return DIRAC_OK;
+}
+
+// Solve G x = rhs in place (x = psi on entry is the initial guess).
+dirac_status gmres(CnCtx& c, double bnorm, int64_t& iters, double& rel_res) {
+    dirac_solver* s = c.s;
+    const int m = s->scheme.gmres_restart;
+    const double tol = s->scheme.gmres_rtol * bnorm;
+    std::vector<zd> H((size_t)(m + 1) * m), g(m + 1), sn(m), y(m);
+    std::vector<double> cs(m), host(3 * 128);
+    std::vector<double>& upload = s->cn_host;            // outlives the async upload
+    upload.assign(128, 0.0);
+    auto Hat = [&](int i, int j) -> zd& { return H[(size_t)i * m + j]; };
+    int64_t used = 0;
+    for (;;) {
+        // explicit residual r = rhs - G x
+        CN_TRY(apply_G(c, c.psi, c.work, +1.0), "apply G");
+        CN_TRY(launch_cn_sub(c.rhs, c.work, 4 * c.npts, c.st), "residual");
+        CN_TRY(norm2_dev(c, c.work, 2), "residual norm");
+        dirac_status r = read_coef(c, host.data(), 3 * 128);
+        if (r != DIRAC_OK) return r;
+        const double beta = std::sqrt(host[256]);
+        if (!std::isfinite(beta)) return fail(DIRAC_E_NONFINITE, "GMRES residual is not finite");
+        rel_res = bnorm > 0 ? beta / bnorm : 0.0;
+        if (beta <= tol) break;
+        if (used >= s->scheme.gmres_max_iter)
+            return fail(DIRAC_E_NOCONV, "GMRES stopped after %lld iterations at relative residual %.3g",
+                        (long long)used, rel_res);
+        CN_TRY(launch_cn_scale(c.work, c.vec(0), 4 * c.npts, 1.0 / beta, c.st), "normalise");
+        std::fill(g.begin(), g.end(), zd(0));
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            CN_TRY(apply_G(c, c.vec(j), c.work, +1.0), "apply G");
+            for (int pass = 0; pass < 2; ++pass) {        // CGS2
+                CN_TRY(launch_cn_dots(c.V, c.vstride, j + 1, c.work, c.ncplx, c.part, kCnDotBlocks, 64,
+                                      c.coef_row(pass), c.st), "Gram-Schmidt dots");
+                CN_TRY(launch_cn_axpy(c.V, c.vstride, j + 1, c.coef_row(pass), c.work, c.ncplx, 1.0, c.st),
+                       "Gram-Schmidt update");
+            }
+            CN_TRY(norm2_dev(c, c.work, 2), "Arnoldi norm");
+            r = read_coef(c, host.data(), 3 * 128);
+            if (r != DIRAC_OK) return r;
+            ++used;
+            for (int i = 0; i <= j; ++i)
+                Hat(i, j) = zd(host[2 * i] + host[128 + 2 * i], host[2 * i + 1] + host[128 + 2 * i + 1]);
+            const double hn = std::sqrt(host[256]);
+            if (!std::isfinite(hn)) return fail(DIRAC_E_NONFINITE, "Arnoldi vector is not finite");
+            // previous rotations on the new column
+            for (int i = 0; i < j; ++i) {
+                const zd a = Hat(i, j), b2 = Hat(i + 1, j);
+                Hat(i, j) = cs[i] * a + sn[i] * b2;
+                Hat(i + 1, j) = -std::conj(sn[i]) * a + cs[i] * b2;
+            }
+            // new rotation zeroing the subdiagonal hn (real, >= 0)
+            const zd a = Hat(j, j);
+            const double aa = std::abs(a), rr = std::hypot(aa, hn);
+            if (aa == 0.0) {
+                cs[j] = 0.0;
+                sn[j] = 1.0;
+            } else {
+                cs[j] = aa / rr;
+                sn[j] = (a / aa) * hn / rr;
+            }
+            Hat(j, j) = cs[j] * a + sn[j] * hn;
+            g[j + 1] = -std::conj(sn[j]) * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            const double est = std::abs(g[j + 1]);
+            if (hn == 0.0 || est <= tol || used >= s->scheme.gmres_max_iter) break;
+            if (j + 1 < m) CN_TRY(launch_cn_scale(c.work, c.vec(j + 1), 4 * c.npts, 1.0 / hn, c.st), "normalise");
+        }
+        // back substitution H y = g and x += V y
+        for (int i = k - 1; i >= 0; --i) {
+            zd acc = g[i];
+            for (int l = i + 1; l < k; ++l) acc -= Hat(i, l) * y[l];
+            y[i] = acc / Hat(i, i);
+        }
+        for (int i = 0; i < k; ++i) {
+            upload[2 * i] = y[i].real();
+            upload[2 * i + 1] = y[i].imag();
+        }
+        CN_TRY(hipMemcpyAsync(c.coef_row(3), upload.data(), 2 * k * sizeof(double), hipMemcpyHostToDevice, c.st),
+               "upload update");
+        CN_TRY(launch_cn_axpy(c.V, c.vstride, k, c.coef_row(3), c.psi, c.ncplx, -1.0, c.st), "solution update");
+    }
+    iters += used;
+    return DIRAC_OK;
+}
+
+}  // namespace
+
+dirac_status cn_step_n(dirac_solver* s, int64_t nsteps) {
+    if (nsteps == 0) return DIRAC_OK;
+    char* b = s->base;
+    CnCtx c{};
+    c.s = s;
+    c.st = s->stream;
+    c.npts = (size_t)s->g.n1 * s->g.n2;
+    c.ncplx = 2 * c.npts;
+    c.vstride = s->lay.cn_vecbytes / sizeof(double);
+    c.psi = reinterpret_cast<double*>(b + s->lay.psi);
+    double* vecs = reinterpret_cast<double*>(b + s->lay.cn_vec);
+    c.rhs = vecs;
+    c.work = vecs + c.vstride;
+    c.V = vecs + 2 * c.vstride;
+    c.part = reinterpret_cast<double*>(b + s->lay.cn_part);
+    c.coef = reinterpret_cast<double*>(b + s->lay.cn_coef);
+    c.h = 0.5 * s->g.dt * s->g.c;
+    const double* E = s->curved ? reinterpret_cast<const double*>(b + s->lay.E) : nullptr;
+    std::vector<double> host(3 * 128);
+    for (int64_t n = 0; n < nsteps; ++n) {
+        // Step 3 of the previous step and Step 1 of this one are the same constant E
+        CN_TRY(launch_cn_exp(c.psi, E, s->e0u_re, s->e0u_im, c.npts, n == 0 ? 1 : 2, c.st), "Step 1");
+        CN_TRY(apply_G(c, c.psi, c.rhs, -1.0), "apply G~");
+        CN_TRY(norm2_dev(c, c.rhs, 2), "right-hand side norm");
+        dirac_status r = read_coef(c, host.data(), 3 * 128);
+        if (r != DIRAC_OK) return r;
+        const double bnorm = std::sqrt(host[256]);
+        r = gmres(c, bnorm, s->cn_iters, s->cn_last_res);
+        if (r != DIRAC_OK) return r;
+        s->step += 1;
+    }
+    CN_TRY(launch_cn_exp(c.psi, E, s->e0u_re, s->e0u_im, c.npts, 1, c.st), "Step 3");
+    CN_TRY(hipStreamSynchronize(c.st), "synchronise");
+    return DIRAC_OK;
+}
+
+}  // namespace dirac

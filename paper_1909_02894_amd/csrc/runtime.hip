@@ -21,6 +21,7 @@
 #include "setup_kernels.hpp"
 #include "solver.hpp"
 #include "stage_kernels.hpp"
+#include "cn_kernels.hpp"
 
 namespace dirac {
 
@@ -55,8 +56,30 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // ---------------------------------------------------------------- validation
 
-dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec) {
+dirac_scheme scheme_or_default(const dirac_scheme* sc) {
+    dirac_scheme d{};
+    if (sc) d = *sc;
+    if (d.scheme == DIRAC_SCHEME_CN_GMRES) {
+        if (d.gmres_restart == 0) d.gmres_restart = 20;
+        if (d.gmres_max_iter == 0) d.gmres_max_iter = 400;
+        if (d.gmres_rtol == 0) d.gmres_rtol = 1e-13;
+    }
+    return d;
+}
+
+dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
+                      const dirac_scheme* scp) {
     if (!g || !m || !pml) return fail(DIRAC_E_ARG, "null grid, metric or pml");
+    const dirac_scheme sc = scheme_or_default(scp);
+    if (sc.scheme != DIRAC_SCHEME_EXP_SPLIT && sc.scheme != DIRAC_SCHEME_CN_GMRES)
+        return fail(DIRAC_E_ARG, "unknown scheme %d", sc.scheme);
+    if (sc.scheme == DIRAC_SCHEME_CN_GMRES) {
+        if (prec != DIRAC_FP64) return fail(DIRAC_E_ARG, "Scheme I is built in FP64 only");
+        if (g->n1 > 2048 || g->n2 > 2048) return fail(DIRAC_E_SIZE, "Scheme I needs n1, n2 <= 2048");
+        if (sc.gmres_restart < 2 || sc.gmres_restart > 63) return fail(DIRAC_E_ARG, "gmres_restart must be in [2, 63]");
+        if (sc.gmres_max_iter < 1) return fail(DIRAC_E_ARG, "gmres_max_iter must be >= 1");
+        if (!(sc.gmres_rtol > 0) || !std::isfinite(sc.gmres_rtol)) return fail(DIRAC_E_ARG, "gmres_rtol must be > 0");
+    }
     if (prec != DIRAC_FP64 && prec != DIRAC_FP32) return fail(DIRAC_E_ARG, "precision must be 0 (FP64) or 1 (FP32)");
     if (!is_pow2_in_range(g->n1) || !is_pow2_in_range(g->n2))
         return fail(DIRAC_E_SIZE, "n1 = %d, n2 = %d: each must be a power of two in [16, 8192]", g->n1, g->n2);
@@ -80,6 +103,8 @@ dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pm
         if (pml->type < 1 || pml->type > 6) return fail(DIRAC_E_ARG, "pml type must be 1..6");
         if (!std::isfinite(pml->sigma0) || pml->sigma0 < 0) return fail(DIRAC_E_ARG, "pml sigma0 must be finite and >= 0");
         if (!std::isfinite(pml->theta)) return fail(DIRAC_E_ARG, "pml theta must be finite");
+        if (std::fabs(std::sin(pml->theta)) > 0 && pml->sigma0 > 0 && sc.scheme == DIRAC_SCHEME_CN_GMRES)
+            return fail(DIRAC_E_ARG, "Scheme I is built for a real stretch S (theta = %g has sin != 0)", pml->theta);
         if (std::fabs(std::sin(pml->theta)) > 0 && pml->sigma0 > 0)
             return fail(DIRAC_E_UNSTABLE,
                         "complex stretch (theta = %g) makes the blend coefficient complex; the directional "
@@ -88,8 +113,10 @@ dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pm
     return DIRAC_OK;
 }
 
-Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec) {
+Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
+                   const dirac_scheme* scp) {
     Layout L{};
+    const dirac_scheme sc = scheme_or_default(scp);
     const size_t N = (size_t)g->n1 * g->n2;
     const size_t sz = prec == DIRAC_FP32 ? 4 : 8;
     const bool curved = m->kind != DIRAC_METRIC_FLAT;
@@ -110,6 +137,15 @@ Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* 
     }
     const size_t setup_parts = ((N + 255) / 256) * 3;
     const size_t obs_parts = ((size_t)g->n1 + g->n2) * 8;
+    if (sc.scheme == DIRAC_SCHEME_CN_GMRES) {
+        L.cn_vecbytes = align256(N * 32);
+        L.cn_vec = take(L.cn_vecbytes * (size_t)(sc.gmres_restart + 3));
+        L.cn_part = take((size_t)kCnDotBlocks * 64 * 2 * 8);
+        L.cn_coef = take(4 * 64 * 2 * 8);
+    } else {
+        L.cn_vec = L.cn_part = L.cn_coef = SIZE_MAX;
+        L.cn_vecbytes = 0;
+    }
     L.partials = take(std::max(setup_parts, obs_parts) * 8);
     L.out = take(64 * 8);
     L.total = off + 256;     // slack so that an unaligned caller buffer can be aligned up
@@ -286,20 +322,39 @@ extern "C" {
 const char* dirac_last_error(void) { return g_last_error.c_str(); }
 
 size_t dirac_footprint_bytes(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec) {
-    if (validate(g, m, pml, prec) != DIRAC_OK) return 0;
-    return make_layout(g, m, pml, prec).total;
+    return dirac_footprint_bytes_scheme(g, m, pml, prec, nullptr);
+}
+
+size_t dirac_footprint_bytes_scheme(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
+                                    const dirac_scheme* sc) {
+    if (validate(g, m, pml, prec, sc) != DIRAC_OK) return 0;
+    return make_layout(g, m, pml, prec, sc).total;
 }
 
 dirac_status dirac_create_metric(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml,
                                  int32_t prec, void* device_buffer, size_t bytes, void* hip_stream,
                                  dirac_solver** out) {
+    return dirac_create_solver(g, m, pml, prec, nullptr, device_buffer, bytes, hip_stream, out);
+}
+
+dirac_status dirac_cn_stats(const dirac_solver* s, int64_t* iterations, double* last_rel_residual) {
+    if (!s || !iterations || !last_rel_residual) return fail(DIRAC_E_ARG, "null argument");
+    *iterations = s->cn_iters;
+    *last_rel_residual = s->cn_last_res;
+    return DIRAC_OK;
+}
+
+dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml,
+                                 int32_t prec, const dirac_scheme* scp, void* device_buffer, size_t bytes,
+                                 void* hip_stream, dirac_solver** out) {
     g_last_error.clear();
     if (!out) return fail(DIRAC_E_ARG, "null output handle");
     *out = nullptr;
-    dirac_status st = validate(g, m, pml, prec);
+    dirac_status st = validate(g, m, pml, prec, scp);
     if (st != DIRAC_OK) return st;
     if (!device_buffer) return fail(DIRAC_E_ARG, "null device buffer");
-    Layout lay = make_layout(g, m, pml, prec);
+    const dirac_scheme sc = scheme_or_default(scp);
+    Layout lay = make_layout(g, m, pml, prec, scp);
     if (bytes < lay.total)
         return fail(DIRAC_E_SIZE, "device buffer of %zu bytes < footprint %zu", bytes, lay.total);
     for (int dir = 0; dir < 2; ++dir) {
@@ -320,6 +375,7 @@ dirac_status dirac_create_metric(const dirac_grid* g, const dirac_metric* m, con
     s->metric.phi = s->metric.psi = s->metric.dphi_dx = s->metric.dphi_dy = s->metric.dpsi_dx = s->metric.dpsi_dy = nullptr;
     s->pmlp = *pml;
     s->prec = prec;
+    s->scheme = sc;
     s->stream = static_cast<hipStream_t>(hip_stream);
     const uintptr_t raw = reinterpret_cast<uintptr_t>(device_buffer);
     s->base = reinterpret_cast<char*>((raw + 255) & ~uintptr_t(255));
@@ -382,7 +438,7 @@ dirac_status dirac_create_metric(const dirac_grid* g, const dirac_metric* m, con
     if (e != hipSuccess) return bail(hip_fail(e, "setup synchronise"));
     if (host_fold[2] != 0.0)
         return bail(fail(DIRAC_E_NONFINITE, "%.0f grid points have non-finite metric fields or tables", host_fold[2]));
-    if (host_fold[0] < 0.0 || host_fold[1] > 1.0 + 1e-12)
+    if (sc.scheme == DIRAC_SCHEME_EXP_SPLIT && (host_fold[0] < 0.0 || host_fold[1] > 1.0 + 1e-12))
         return bail(fail(DIRAC_E_UNSTABLE,
                          "blend coefficient b = a/S ranges over [%.17g, %.17g]; the directional step is "
                          "stable only for b in [0, 1]", host_fold[0], host_fold[1]));
@@ -433,6 +489,7 @@ dirac_status dirac_step_n(dirac_solver* s, int64_t nsteps) {
     if (!s) return fail(DIRAC_E_ARG, "null solver");
     if (nsteps < 0) return fail(DIRAC_E_ARG, "nsteps must be >= 0");
     if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
+    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES) return cn_step_n(s, nsteps);
     dirac_status r = enqueue_steps(s, nsteps, true);
     if (r != DIRAC_OK) return r;
     s->step += nsteps;
@@ -563,6 +620,7 @@ dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
     if (!s || !ms_out || !counts_out) return fail(DIRAC_E_ARG, "null argument");
     if (nsteps < 0) return fail(DIRAC_E_ARG, "nsteps must be >= 0");
     if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
+    if (s->scheme.scheme != DIRAC_SCHEME_EXP_SPLIT) return fail(DIRAC_E_ARG, "per-direction timing is for Scheme II");
     ms_out[0] = ms_out[1] = 0.0;
     counts_out[0] = counts_out[1] = 0;
     if (nsteps == 0) return DIRAC_OK;
@@ -598,6 +656,7 @@ dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
 
 dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
     if (!s || reps < 1) return fail(DIRAC_E_ARG, "bad arguments");
+    if (s->scheme.scheme != DIRAC_SCHEME_EXP_SPLIT) return fail(DIRAC_E_ARG, "schedules apply to Scheme II only");
     if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
     const size_t N = (size_t)s->g.n1 * s->g.n2;
     const size_t bytes = N * 4 * (s->prec == DIRAC_FP32 ? 4 : 8);

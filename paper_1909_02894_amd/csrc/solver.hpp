@@ -23,14 +23,22 @@ struct Layout {
     size_t K[2];       // directional symbols per axis (complex T)
     size_t D[2];       // derivative symbols per axis (T)
     size_t tw[2];      // FFT twiddles per axis (complex T)
+    size_t cn_vec;     // Scheme I: gmres_restart + 3 FP64 vectors (rhs, work, Krylov basis)
+    size_t cn_part;    // Scheme I: dot-product partials
+    size_t cn_coef;    // Scheme I: device coefficient vectors
+    size_t cn_vecbytes;
     size_t partials;   // reduction partials (FP64)
     size_t out;        // small reduction outputs (FP64)
     size_t total;      // footprint including alignment slack
 };
 
 dirac_status fail(dirac_status st, const char* fmt, ...);
-dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec);
-Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec);
+dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
+                      const dirac_scheme* sc);
+Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
+                   const dirac_scheme* sc);
+dirac_scheme scheme_or_default(const dirac_scheme* sc);
+dirac_status cn_step_n(dirac_solver* s, int64_t nsteps);
 const KernelEntry* pick_entry(int prec, int n, int dir, int other, int mode);
 
 }  // namespace dirac
@@ -55,4 +63,8 @@ struct dirac_solver {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<hipEvent_t> events;
+    dirac_scheme scheme{};
+    int64_t cn_iters = 0;
+    double cn_last_res = 0;
+    std::vector<double> cn_host;     // host source of the last GMRES update upload
 };

@@ -23,9 +23,11 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdirac.so
 FP64, FP32 = 0, 1
 METRIC_FLAT, METRIC_GAUSS_BUMP, METRIC_PAPER_EXP3, METRIC_FIELDS = 0, 1, 2, 3
 SPIN_NONE, SPIN_PAPER, SPIN_2P1 = 0, 1, 2
+SCHEME_EXP_SPLIT, SCHEME_CN_GMRES = 0, 1
 
 STATUS = {0: "DIRAC_OK", -1: "DIRAC_E_ARG", -2: "DIRAC_E_SIZE", -3: "DIRAC_E_UNSTABLE",
-          -4: "DIRAC_E_NOMEM", -5: "DIRAC_E_DEVICE", -6: "DIRAC_E_STATE", -7: "DIRAC_E_NONFINITE"}
+          -4: "DIRAC_E_NOMEM", -5: "DIRAC_E_DEVICE", -6: "DIRAC_E_STATE", -7: "DIRAC_E_NONFINITE",
+          -8: "DIRAC_E_NOCONV"}
 
 _dp = C.POINTER(C.c_double)
 
@@ -58,6 +60,11 @@ class Schedule(C.Structure):
     _fields_ = [("radix", C.c_int32), ("lines_per_wg", C.c_int32), ("components_per_thread", C.c_int32)]
 
 
+class Scheme(C.Structure):
+    _fields_ = [("scheme", C.c_int32), ("gmres_restart", C.c_int32), ("gmres_max_iter", C.c_int32),
+                ("reserved", C.c_int32), ("gmres_rtol", C.c_double)]
+
+
 class DiracError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -70,6 +77,11 @@ SIGNATURES = {
     "dirac_footprint_bytes": (C.c_size_t, [C.POINTER(Grid), C.POINTER(Metric), C.POINTER(Pml), C.c_int32]),
     "dirac_create_metric": (C.c_int32, [C.POINTER(Grid), C.POINTER(Metric), C.POINTER(Pml), C.c_int32, _vp,
                                         C.c_size_t, _vp, C.POINTER(_vp)]),
+    "dirac_footprint_bytes_scheme": (C.c_size_t, [C.POINTER(Grid), C.POINTER(Metric), C.POINTER(Pml), C.c_int32,
+                                                   C.POINTER(Scheme)]),
+    "dirac_create_solver": (C.c_int32, [C.POINTER(Grid), C.POINTER(Metric), C.POINTER(Pml), C.c_int32,
+                                        C.POINTER(Scheme), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "dirac_cn_stats": (C.c_int32, [_vp, C.POINTER(C.c_int64), _dp]),
     "dirac_set_initial_spinor": (C.c_int32, [_vp, _dp]),
     "dirac_set_initial_spinor_device": (C.c_int32, [_vp, _vp]),
     "dirac_step_n": (C.c_int32, [_vp, C.c_int64]),
@@ -161,6 +173,27 @@ def create_metric(grid, metric, pml, precision, device_ptr: int, nbytes: int, st
     return h
 
 
+def footprint_bytes_scheme(grid: Grid, metric: Metric, pml: Pml, precision: int, scheme: Scheme | None) -> int:
+    return int(lib.dirac_footprint_bytes_scheme(C.byref(grid), C.byref(metric), C.byref(pml), precision,
+                                                C.byref(scheme) if scheme is not None else None))
+
+
+def create_solver(grid, metric, pml, precision, scheme: Scheme | None, device_ptr: int, nbytes: int,
+                  stream_ptr: int | None):
+    h = _vp()
+    _check(lib.dirac_create_solver(C.byref(grid), C.byref(metric), C.byref(pml), precision,
+                                   C.byref(scheme) if scheme is not None else None, _vp(device_ptr), nbytes,
+                                   _vp(stream_ptr or 0), C.byref(h)))
+    return h
+
+
+def cn_stats(h):
+    it = C.c_int64()
+    res = C.c_double()
+    _check(lib.dirac_cn_stats(h, C.byref(it), C.byref(res)))
+    return int(it.value), float(res.value)
+
+
 def set_initial_spinor(h, psi: np.ndarray):
     psi = np.ascontiguousarray(psi, dtype=np.complex128)
     _check(lib.dirac_set_initial_spinor(h, psi.view(np.float64).ctypes.data_as(_dp)))
@@ -214,21 +247,23 @@ class Solver:
 
     def __init__(self, n1, n2, a1, a2, dt, c=1.0, m=1.0, precision=FP64, metric=METRIC_FLAT, spin=SPIN_NONE,
                  bump_A=0.0, bump_s=1.0, fields=None, pml_width=0, pml_type=1, pml_sigma0=1.0, pml_theta=0.0,
-                 device=None, stream=None):
+                 device=None, stream=None, scheme=SCHEME_EXP_SPLIT, gmres_restart=0, gmres_max_iter=0,
+                 gmres_rtol=0.0):
         import torch
         self.n1, self.n2, self.precision = n1, n2, precision
         self.grid, self.metric, self.pml, keep = make_structs(n1, n2, a1, a2, dt, c, m, metric, spin, bump_A,
                                                               bump_s, fields, pml_width, pml_type, pml_sigma0,
                                                               pml_theta)
-        self.nbytes = footprint_bytes(self.grid, self.metric, self.pml, precision)
+        self.scheme = Scheme(scheme, gmres_restart, gmres_max_iter, 0, gmres_rtol)
+        self.nbytes = footprint_bytes_scheme(self.grid, self.metric, self.pml, precision, self.scheme)
         if self.nbytes == 0:
             raise DiracError(-1, last_error())
         device = device or torch.device("cuda", torch.cuda.current_device())
         self.stream = stream or torch.cuda.current_stream(device)
         self.buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
         self.h = None
-        self.h = create_metric(self.grid, self.metric, self.pml, precision, self.buffer.data_ptr(), self.nbytes,
-                               self.stream.cuda_stream)
+        self.h = create_solver(self.grid, self.metric, self.pml, precision, self.scheme, self.buffer.data_ptr(),
+                               self.nbytes, self.stream.cuda_stream)
         del keep
 
     @classmethod
@@ -273,6 +308,10 @@ class Solver:
 
     def autotune(self, reps=20):
         _check(lib.dirac_autotune(self.h, reps))
+
+    def cn_stats(self):
+        """(total GMRES iterations, last relative residual) of a Scheme I solver."""
+        return cn_stats(self.h)
 
     def close(self):
         if self.h is not None:

@@ -88,3 +88,39 @@ def test_every_size_and_precision_has_kernels():
                     # cpt = 1: 2 (n / r) lines threads, 32 logical threads per wave
                     nt = (n // r) * lines * (2 if cpt == 1 else 1)
                     assert n % r == 0 and nt <= 1024 and (cpt == 2 or (n // r) * lines % 32 == 0)
+
+
+def test_scheme_selection_is_validated():
+    from paper_1909_02894_amd import dirac as D
+    g, m, p, _ = D.make_structs(256, 128, 10.0, 10.0, 0.01, 1.0, 1.0, pml_width=16)
+    split = D.footprint_bytes(g, m, p, D.FP64)
+    assert D.footprint_bytes_scheme(g, m, p, D.FP64, None) == split
+    assert D.footprint_bytes_scheme(g, m, p, D.FP64, D.Scheme(D.SCHEME_EXP_SPLIT, 0, 0, 0, 0.0)) == split
+    cn = D.footprint_bytes_scheme(g, m, p, D.FP64, D.Scheme(D.SCHEME_CN_GMRES, 10, 0, 0, 0.0))
+    # GMRES(10): rhs, work and 11 Krylov vectors of 32 bytes per point
+    assert cn >= split + 13 * 256 * 128 * 32
+    assert D.footprint_bytes_scheme(g, m, p, D.FP64, D.Scheme(D.SCHEME_CN_GMRES, 20, 0, 0, 0.0)) > cn
+
+    def create_status(scheme, prec=D.FP64, **kw):
+        args = dict(n1=64, n2=64, a1=5.0, a2=5.0, dt=0.01, c=1.0, m=1.0)
+        args.update(kw)
+        g, m, p, keep = D.make_structs(**args)
+        h = ctypes.c_void_p()
+        return D.lib.dirac_create_solver(ctypes.byref(g), ctypes.byref(m), ctypes.byref(p), prec,
+                                         ctypes.byref(scheme), None, 0, None, ctypes.byref(h))
+
+    CN = D.SCHEME_CN_GMRES
+    assert create_status(D.Scheme(5, 0, 0, 0, 0.0)) == -1                     # unknown scheme
+    assert create_status(D.Scheme(CN, 0, 0, 0, 0.0), prec=D.FP32) == -1       # FP64 only
+    assert "FP64" in D.last_error()
+    assert create_status(D.Scheme(CN, 0, 0, 0, 0.0), n1=4096) == -2           # n <= 2048
+    assert create_status(D.Scheme(CN, 1, 0, 0, 0.0)) == -1                    # restart below 2
+    assert create_status(D.Scheme(CN, 64, 0, 0, 0.0)) == -1                   # restart above 63
+    assert create_status(D.Scheme(CN, 0, -3, 0, 0.0)) == -1
+    assert create_status(D.Scheme(CN, 0, 0, 0, -1e-9)) == -1
+    assert create_status(D.Scheme(CN, 0, 0, 0, float("nan"))) == -1
+    assert create_status(D.Scheme(CN, 0, 0, 0, 0.0), pml_width=8, pml_theta=0.3) == -1
+    assert "real stretch" in D.last_error()
+    assert create_status(D.Scheme(CN, 0, 0, 0, 0.0)) == -1                    # valid; null device buffer
+    assert "null device buffer" in D.last_error()
+    assert D.lib.dirac_cn_stats(None, None, None) == -1

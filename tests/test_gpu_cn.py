@@ -1,0 +1,126 @@
+"""GPU parity of Numerical Scheme I (Sec. 5.1, eq. (cn)): the device GMRES
+solve of the Crank-Nicolson transport step against the oracle's (scipy GMRES on
+the same operator).
+
+Tolerance: both sides stop their Krylov iteration at a relative residual of
+1e-14 (GPU) / 1e-14 (oracle); G = I + (dt/2) alpha.T has singular values >= 1 in
+the flat case and close to 1 here, so each solve differs from the exact one by
+about the residual, and the states agree to ~ steps x 1e-14 -- checked at 1e-11
+(relative L2), like the Scheme II FP64 parity.  With a looser GPU tolerance the
+bound scales with it (restart test).
+"""
+import numpy as np
+import pytest
+
+from oracle import dirac_oracle as O
+from paper_1909_02894_amd import workloads as W
+from tests.helpers import oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_02894_amd import dirac
+    return dirac
+
+
+def cn_solver(D, spec, fields=None, rtol=1e-14, restart=0, max_iter=0):
+    return D.Solver.from_spec(spec, precision=D.FP64, fields=fields, scheme=D.SCHEME_CN_GMRES,
+                              gmres_restart=restart, gmres_max_iter=max_iter, gmres_rtol=rtol)
+
+
+def x_only_fields(n1, n2, a):
+    """a = e^{Phi - Psi} > 1 varying along x only (the Scheme I order pin's metric)."""
+    X, _ = np.meshgrid(O.grid_points(n1, a), O.grid_points(n2, a))
+    z = np.zeros_like(X)
+    psi = -0.3 * np.exp(-X ** 2 / 4.0)
+    return O.MetricFields(z, psi, z, z, 0.3 * X / 2.0 * np.exp(-X ** 2 / 4.0), z)
+
+
+def test_cn_flat_matches_oracle_cayley_and_conserves_norm(D):
+    spec = W.flat_small(n=64, steps=10)
+    spec.n2, spec.dt, spec.m = 32, 0.05, 0.8
+    psi0 = W.initial_spinor(spec)
+    s = cn_solver(D, spec)
+    s.set_initial_spinor(psi0)
+    s.step_n(3)
+    s.step_n(7)
+    g = s.get_spinor()
+    T = O.build_tables(oracle_problem(spec))
+    assert O.rel_l2(g, O.cn_run(psi0, T, 10)) < TOL
+    ex = O.cn_flat_exact(psi0, spec.n1, spec.n2, spec.a1, spec.a2, spec.m, spec.c, spec.dt, 10)
+    assert O.rel_l2(g, ex) < TOL
+    ob = s.observables()
+    assert ob["step"] == 10
+    assert abs(ob["norm_l2"] / O.observables(psi0, T).norm_l2 - 1) < 1e-12
+    iters, res = s.cn_stats()
+    assert iters >= 10 and res <= 1e-14
+    # the same ten steps in one call give the same bits
+    s2 = cn_solver(D, spec)
+    s2.set_initial_spinor(psi0)
+    s2.step_n(10)
+    assert np.array_equal(s2.get_spinor(), g)
+
+
+@pytest.mark.parametrize("m", [0.0, 1.0])
+def test_cn_curved_bump_with_layer(D, m):
+    spec = W.curved_bump(n=64, steps=8, m=m)
+    psi0 = W.initial_spinor(spec)
+    s = cn_solver(D, spec)
+    s.set_initial_spinor(psi0)
+    s.step_n(8)
+    T = O.build_tables(oracle_problem(spec))
+    assert O.rel_l2(s.get_spinor(), O.cn_run(psi0, T, 8)) < TOL
+
+
+def test_cn_accepts_a_above_one_that_scheme_two_rejects(D):
+    n1, n2, a = 64, 16, 8.0
+    f = x_only_fields(n1, n2, a)
+    arr = (f.phi, f.psi, f.phi_x, f.phi_y, f.psi_x, f.psi_y)
+    spec = W.flat_small(n=n1, steps=6)
+    spec.n2, spec.a1, spec.a2, spec.dt, spec.m = n2, a, a, 0.4 / 16, 0.5
+    spec.metric, spec.spin = W.METRIC_FIELDS, W.SPIN_NONE
+    with pytest.raises(D.DiracError) as ei:
+        D.Solver.from_spec(spec, fields=arr)
+    assert ei.value.status == -3
+    X, _ = np.meshgrid(O.grid_points(n1, a), O.grid_points(n2, a))
+    psi0 = np.zeros((n2, n1, 2), complex)
+    psi0[..., 0] = np.exp(-(X + 1) ** 2 / 2.0 + 1.5j * X)
+    s = cn_solver(D, spec, fields=arr)
+    s.set_initial_spinor(psi0)
+    s.step_n(6)
+    T = O.build_tables(oracle_problem(spec, f))
+    assert np.max(T.bx) > 1.2
+    assert O.rel_l2(s.get_spinor(), O.cn_run(psi0, T, 6)) < TOL
+
+
+def test_cn_restarted_gmres_large_step(D):
+    # dt well beyond the explicit limit: GMRES(3) needs several restart cycles
+    spec = W.curved_bump(n=64, steps=4, m=1.0)
+    spec.dt = 0.4
+    psi0 = W.initial_spinor(spec)
+    s = cn_solver(D, spec, rtol=1e-13, restart=3)
+    s.set_initial_spinor(psi0)
+    s.step_n(4)
+    iters, res = s.cn_stats()
+    assert iters > 4 * 3 and res <= 1e-13
+    T = O.build_tables(oracle_problem(spec))
+    assert O.rel_l2(s.get_spinor(), O.cn_run(psi0, T, 4)) < 1e-10
+
+
+def test_cn_reports_no_convergence(D):
+    spec = W.curved_bump(n=32, steps=1, m=1.0)
+    spec.dt = 0.4
+    s = cn_solver(D, spec, rtol=1e-15, restart=2, max_iter=2)
+    s.set_initial_spinor(W.initial_spinor(spec))
+    with pytest.raises(D.DiracError) as ei:
+        s.step_n(1)
+    assert ei.value.status == -8
+    with pytest.raises(D.DiracError):
+        s.autotune(2)

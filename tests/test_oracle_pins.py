@@ -474,3 +474,57 @@ def test_curved_step_matches_dense_brute_force():
     assert O.rel_l2(O.step(psi, T), ref) < 1e-13
     # and the oracle's own layer profile agrees with the one built here
     assert np.allclose(O.pml_inverse_stretch(n1, a1, w1, 1, s0, 0.0).real, inv_s(n1, a1, w1), atol=1e-16)
+
+
+# --- Scheme I (Crank-Nicolson + GMRES) --------------------------------------------
+
+def test_cn_flat_matches_per_mode_cayley_and_conserves_norm():
+    n1, n2, a, m, c, dt = 32, 16, 5.0, 0.8, 1.1, 0.05
+    p = O.Problem(n1=n1, n2=n2, a1=a, a2=a, dt=dt, c=c, m=m)
+    T = O.build_tables(p)
+    psi0 = W.gaussian_packet(n1, n2, a, a, (0.3, -0.2), (1.0, 2.0), 1.0)
+    out = O.cn_run(psi0, T, 6)
+    assert O.rel_l2(out, O.cn_flat_exact(psi0, n1, n2, a, a, m, c, dt, 6)) < 1e-12
+    n0 = O.observables(psi0, T).norm_l2
+    assert abs(O.observables(out, T).norm_l2 / n0 - 1) < 1e-12     # Scheme I proposition, flat case
+
+
+def test_cn_curved_step_matches_dense_solve():
+    # one curved step with layers against a dense matrix of G built column by column
+    n1, n2 = 8, 8
+    p = O.Problem(n1=n1, n2=n2, a1=3.0, a2=2.0, dt=0.2, c=1.0, m=0.7, metric=O.METRIC_PAPER_EXP3,
+                  spin=O.SPIN_PAPER, pml_width=2, pml_sigma0=0.8)
+    T = O.build_tables(p)
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal((n2, n1, 2)) + 1j * rng.standard_normal((n2, n1, 2))
+    G, Gt = O.cn_operators(T)
+    nn = psi.size
+    M = np.empty((nn, nn), complex)
+    for k in range(nn):
+        e = np.zeros(nn, complex)
+        e[k] = 1.0
+        M[:, k] = G(e.reshape(psi.shape)).ravel()
+    half = O.apply_pointwise(T.E, psi)
+    star = np.linalg.solve(M, Gt(half).ravel()).reshape(psi.shape)
+    ref = O.apply_pointwise(T.E, star)
+    assert O.rel_l2(O.cn_step(psi, T), ref) < 1e-12
+
+
+def test_cn_is_second_order_for_x_only_data_and_unconditionally_stable():
+    # data constant in y: no splitting error between directions; CN transport is
+    # second order; with a > 1 (outside Scheme II's stability range) the plain norm
+    # stays bounded.
+    n, a, t = 64, 8.0, 0.4
+    x = O.grid_points(n, a)
+    X, Y = np.meshgrid(x, O.grid_points(16, a))
+    f = O.MetricFields(np.zeros_like(X), -0.3 * np.exp(-X ** 2 / 4.0), np.zeros_like(X), np.zeros_like(X),
+                       0.3 * X / 2.0 * np.exp(-X ** 2 / 4.0), np.zeros_like(X))
+    base = dict(n1=n, n2=16, a1=a, a2=a, c=1.0, m=0.5, metric=O.METRIC_FIELDS, spin=O.SPIN_NONE, fields=f)
+    psi0 = np.zeros((16, n, 2), complex)
+    psi0[..., 0] = np.exp(-(X + 1) ** 2 / 2.0 + 1.5j * X)
+    T_ref = O.build_tables(O.Problem(dt=t / 128, **base))
+    assert np.max(T_ref.bx) > 1.2                      # a = e^{-Psi} > 1: Scheme II would reject it
+    ref = O.cn_run(psi0, T_ref, 128)
+    errs = [O.rel_l2(O.cn_run(psi0, O.build_tables(O.Problem(dt=t / k, **base)), k), ref) for k in (8, 16)]
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs
+    assert O.observables(ref, T_ref).norm_l2 < 1.5 * O.observables(psi0, T_ref).norm_l2
