@@ -137,6 +137,25 @@ def bench_batch(D, W, count=256, steps=1000):
                               "state_bytes": pts * 16}}
 
 
+def bench_cn(D, spec, steps=40):
+    """Scheme I (Crank-Nicolson transport + device GMRES) on the same workload."""
+    import torch
+    from paper_1909_02894_amd import workloads as W
+    s = D.Solver.from_spec(spec, precision=D.FP64, scheme=D.SCHEME_CN_GMRES, gmres_restart=20, gmres_rtol=1e-12)
+    s.set_initial_spinor(W.initial_spinor(spec))
+    s.step_n(3)
+    it0, _ = s.cn_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step_n(steps)                  # synchronous: the host drives the Krylov iteration
+    dt = time.perf_counter() - t0
+    it1, res = s.cn_stats()
+    s.close()
+    return {"value": spec.n1 * spec.n2 * steps / dt, "unit": "grid-point*steps/s", "dtype": "f64",
+            "steps": steps, "ms_per_step": dt * 1e3 / steps, "gmres_iterations_per_step": (it1 - it0) / steps,
+            "gmres_restart": 20, "gmres_rtol": 1e-12, "last_relative_residual": res}
+
+
 def bench_serve(count, rate, budget, quantum=64, seed=5000):
     from paper_1909_02894_amd import serve as S
     reqs = S.make_requests(count, rate, seed=seed)
@@ -231,6 +250,7 @@ def main():
             "note": "flat 4096x4096 packet solve, 256 MiB state (beyond the Infinity Cache)",
             "roofline": roofline_for(big, "flat", D.FP32, rb),
             "schedule": {"x": rb["sched"][0], "y": rb["sched"][1]}}
+        variants["scheme1_cn_gmres"] = bench_cn(D, spec)
         bt = bench_batch(D, W)
         variants["batch_256_mixed"] = bt
         # serving at ~0.7x the measured batch capacity

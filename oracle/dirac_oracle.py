@@ -50,8 +50,14 @@ them):
   square u.u is real (possibly negative), so exp = C I + D (u . sigma) with
   real C, D (cosh/sinh for u.u >= 0, cos/sin otherwise);
 * R7 the initial spinor is taken as given (not normalised); the metric is
-  static, so the half-step exponential is time independent (Q14 in the paper's
-  notation: F evaluated at t_{n+1/2} does not depend on t here).
+  static, so the half-step exponential is time independent (F evaluated at
+  t_{n+1/2} does not depend on t here);
+* R15 eq. (step2bis) is implemented as printed (STEP2BIS_PRINTED) and, because
+  the printed correction has neither the sign nor the size that the Taylor
+  expansion of the blend asks for, also as the second-order correction derived
+  from that expansion (STEP2BIS_CORRECTED); the latter uses the gradient of
+  a along the direction and holds the layer factor 1/S fixed.  Both are
+  explicit (the implicit treatment the paper mentions is not specified).
 """
 from __future__ import annotations
 
@@ -73,6 +79,11 @@ METRIC_FIELDS = 3
 SPIN_NONE = 0
 SPIN_PAPER = 1   # chi = Phi   (the printed 2-D equation, Numerical Experiment 3)
 SPIN_2P1 = 2     # chi = Phi + Psi
+
+# Directional step (Sec. 5.2): eq. (second_scheme), or eq. (step2bis) in two readings
+STEP2_PLAIN = 0              # eq. (second_scheme)
+STEP2BIS_PRINTED = 1         # eq. (step2bis) as printed: + b (c dt)^2 [[d^2]] Xi
+STEP2BIS_CORRECTED = 2       # second-order Taylor correction of the blend (R15)
 
 
 # ---------------------------------------------------------------------------
@@ -317,6 +328,7 @@ class Problem:
     pml_type: int = 1
     pml_sigma0: float = 1.0
     pml_theta: float = 0.0
+    step2: int = STEP2_PLAIN
 
 
 @dataclass
@@ -338,6 +350,8 @@ class Tables:
     chi_x: np.ndarray = field(default=None)
     chi_y: np.ndarray = field(default=None)
     chi: np.ndarray = field(default=None)
+    dbx: np.ndarray = field(default=None)     # (d_x a) / S^1, (n2, n1)
+    dby: np.ndarray = field(default=None)     # (d_y a) / S^2, (n2, n1)
 
 
 def build_tables(p: Problem) -> Tables:
@@ -356,9 +370,12 @@ def build_tables(p: Problem) -> Tables:
     xi1 = wavenumbers(p.n1, p.a1)
     xi2 = wavenumbers(p.n2, p.a2)
     chi_x, chi_y, chi = spin_potential(p.spin, f)
+    # gradient of a = e^{Phi - Psi}; the layer factor 1/S is held fixed (R15)
+    dbx = a * (f.phi_x - f.psi_x) * invS1[None, :].real
+    dby = a * (f.phi_y - f.psi_y) * invS2[:, None].real
     return Tables(p, x, y, 2 * p.a1 / p.n1, 2 * p.a2 / p.n2, xi1, xi2, f, a, bx, by, E,
                   directional_symbol(xi1, p.c, p.dt, SIGMA_X),
-                  directional_symbol(xi2, p.c, p.dt, SIGMA_Y), chi_x, chi_y, chi)
+                  directional_symbol(xi2, p.c, p.dt, SIGMA_Y), chi_x, chi_y, chi, dbx, dby)
 
 
 def blend_is_stable(b: np.ndarray) -> bool:
@@ -380,12 +397,57 @@ def directional_stage(psi: np.ndarray, axis: int, K: np.ndarray, b: np.ndarray) 
     return b[..., None] * Xi + (1.0 - b[..., None]) * psi
 
 
+def directional_stage_2bis(psi: np.ndarray, axis: int, K: np.ndarray, b: np.ndarray, xi: np.ndarray,
+                           c: float, dt: float, variant: int, db: np.ndarray | None = None) -> np.ndarray:
+    """One direction of eq. (step2bis).
+
+    STEP2BIS_PRINTED, the formula as printed (with the transport speed c):
+        psi* = b Xi + (1 - b) psi + b (c dt)^2 [[d_i^2]] Xi,   Xi = F_i^{-1}[K F_i psi].
+
+    STEP2BIS_CORRECTED (R15): the blend b Xi + (1 - b) psi equals, to second order
+    in dt, psi - c dt b sigma_i d_i psi + ((c dt)^2 / 2) b d_i^2 psi (e^{-i theta}
+    expanded with its factor 1/2), while the exact transport d_t psi = -c b sigma_i
+    d_i psi gives psi - c dt b sigma_i d_i psi + ((c dt)^2 / 2) b d_i(b d_i psi)
+    (sigma_i^2 = I).  Adding the difference makes the step second order:
+        psi* = b Xi + (1 - b) psi
+               + ((c dt)^2 / 2) (-b (1 - b) [[d_i^2]] psi + b b' [[d_i]] psi),
+    with b' = (d_i a) / S^i (the layer factor held fixed) and the spectral
+    derivatives of eq. (trick): [[d_i]] <-> i xi, [[d_i^2]] <-> -xi^2.
+    """
+    P = partial_dft(psi, axis)
+    if axis == 1:
+        KP = np.einsum("qab,jqb->jqa", K, P)
+        shape = (1, -1, 1)
+    else:
+        KP = np.einsum("qab,qib->qia", K, P)
+        shape = (-1, 1, 1)
+    Xi = partial_idft(KP, axis)
+    bb = b[..., None]
+    out = bb * Xi + (1.0 - bb) * psi
+    xs = xi.reshape(shape)
+    if variant == STEP2BIS_PRINTED:
+        d2Xi = partial_idft(-(xs ** 2) * KP, axis)
+        out = out + bb * (c * dt) ** 2 * d2Xi
+    elif variant == STEP2BIS_CORRECTED:
+        d2psi = partial_idft(-(xs ** 2) * P, axis)
+        d1psi = partial_idft(1j * xs * P, axis)
+        out = out + 0.5 * (c * dt) ** 2 * (-bb * (1.0 - bb) * d2psi + bb * db[..., None] * d1psi)
+    else:
+        raise ValueError(f"unknown step2bis variant {variant}")
+    return out
+
+
 def step_stages(psi: np.ndarray, T: Tables):
     """One time step, returning every stage boundary (after Step 1, after the
     x direction, after the y direction, after Step 5)."""
+    p = T.prob
     s1 = apply_pointwise(T.E, psi)                       # Step 1
-    s2 = directional_stage(s1, 1, T.Kx, T.bx)            # direction 1 (x)
-    s3 = directional_stage(s2, 0, T.Ky, T.by)            # direction 2 (y)
+    if p.step2 == STEP2_PLAIN:
+        s2 = directional_stage(s1, 1, T.Kx, T.bx)        # direction 1 (x)
+        s3 = directional_stage(s2, 0, T.Ky, T.by)        # direction 2 (y)
+    else:
+        s2 = directional_stage_2bis(s1, 1, T.Kx, T.bx, T.xi1, p.c, p.dt, p.step2, T.dbx)
+        s3 = directional_stage_2bis(s2, 0, T.Ky, T.by, T.xi2, p.c, p.dt, p.step2, T.dby)
     s4 = apply_pointwise(T.E, s3)                        # Step 5
     return s1, s2, s3, s4
 

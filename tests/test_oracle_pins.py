@@ -528,3 +528,104 @@ def test_cn_is_second_order_for_x_only_data_and_unconditionally_stable():
     errs = [O.rel_l2(O.cn_run(psi0, O.build_tables(O.Problem(dt=t / k, **base)), k), ref) for k in (8, 16)]
     assert 3.0 < errs[0] / errs[1] < 5.0, errs
     assert O.observables(ref, T_ref).norm_l2 < 1.5 * O.observables(psi0, T_ref).norm_l2
+
+
+# --- eq. (step2bis): the directional step with a second-order correction ---------
+
+def test_step2bis_single_mode_factors():
+    # sigma_x eigenmode e^{i xi x} (1, +-1) with constant b, theta = c dt xi:
+    #   as printed:  g = b (1 - theta^2) e^{-+ i theta} + 1 - b
+    #   corrected:   g = b e^{-+ i theta} + 1 - b + b (1 - b) theta^2 / 2
+    n1, n2, a, c, dt, b = 16, 4, 3.0, 1.3, 0.15, 0.7
+    x = O.grid_points(n1, a)
+    xi = O.wavenumbers(n1, a)
+    K = O.directional_symbol(xi, c, dt, O.SIGMA_X)
+    bb = np.full((n2, n1), b)
+    zero = np.zeros((n2, n1))
+    for p, sgn in ((2, 1), (-5, -1), (-8, 1)):
+        th = c * dt * p * math.pi / a
+        psi = np.zeros((n2, n1, 2), complex)
+        psi[..., 0] = np.exp(1j * p * math.pi / a * x)[None, :]
+        psi[..., 1] = sgn * psi[..., 0]
+        out = O.directional_stage_2bis(psi, 1, K, bb, xi, c, dt, O.STEP2BIS_PRINTED)
+        g = b * (1 - th * th) * np.exp(-1j * sgn * th) + 1 - b
+        assert np.allclose(out, g * psi, atol=1e-13)
+        out = O.directional_stage_2bis(psi, 1, K, bb, xi, c, dt, O.STEP2BIS_CORRECTED, zero)
+        g = b * np.exp(-1j * sgn * th) + 1 - b + b * (1 - b) * th * th / 2
+        assert np.allclose(out, g * psi, atol=1e-13)
+
+
+@pytest.mark.parametrize("axis", [1, 0])
+def test_step2bis_corrected_stage_matches_dense_construction(axis):
+    # variable b and b' along the axis; derivatives from the Appendix-B matrix
+    # written out here (D1), D2 = D1 D1; the transform of Xi from explicit DFT sums
+    n, m, a, c, dt = 16, 6, 2.5, 1.2, 0.09
+    rng = np.random.default_rng(21 + axis)
+    shape = (m, n) if axis == 1 else (n, m)
+    psi = rng.standard_normal(shape + (2,)) + 1j * rng.standard_normal(shape + (2,))
+    b = rng.uniform(0.3, 1.0, shape)
+    db = rng.uniform(-0.5, 0.5, shape)
+    D1 = np.empty((n, n), complex)
+    for k in range(n):
+        for kp in range(n):
+            D1[k, kp] = (-1j * math.pi / (2 * a) if k == kp else
+                         math.pi / (2 * a) * (-1) ** (k - kp) * (1 / math.tan(math.pi * (k - kp) / n) - 1j))
+    D2 = D1 @ D1
+    xi = np.array([(q if q < n // 2 else q - n) * math.pi / a for q in range(n)])
+    F = np.exp(-2j * math.pi * np.outer(np.arange(n), np.arange(n)) / n)
+    sig = O.SIGMA_X if axis == 1 else O.SIGMA_Y
+    K = np.array([math.cos(c * dt * z) * O.ID2 - 1j * math.sin(c * dt * z) * sig for z in xi])
+    lines = psi if axis == 1 else psi.transpose(1, 0, 2)
+    bl = b if axis == 1 else b.T
+    dbl = db if axis == 1 else db.T
+    ref = np.empty_like(lines)
+    for j in range(m):
+        v = lines[j]
+        P = F @ v
+        Xi = np.conj(F) @ np.einsum("qab,qb->qa", K, P) / n
+        ref[j] = (bl[j][:, None] * Xi + (1 - bl[j][:, None]) * v
+                  + 0.5 * (c * dt) ** 2 * (-(bl[j] * (1 - bl[j]))[:, None] * (D2 @ v)
+                                           + (bl[j] * dbl[j])[:, None] * (D1 @ v)))
+    if axis == 0:
+        ref = ref.transpose(1, 0, 2)
+    out = O.directional_stage_2bis(psi, axis, K, b, xi, c, dt, O.STEP2BIS_CORRECTED, db)
+    assert O.rel_l2(out, ref) < 1e-13
+
+
+def _x_only_problem(step2, dt):
+    n, a = 64, 8.0
+    X, _ = np.meshgrid(O.grid_points(n, a), O.grid_points(16, a))
+    z = np.zeros_like(X)
+    g = np.exp(-X ** 2 / 4.0)
+    f = O.MetricFields(z, 0.3 * g, z, z, -0.3 * X / 2.0 * g, z)       # a = e^{-Psi} in [0.74, 1]
+    p = O.Problem(n1=n, n2=16, a1=a, a2=a, dt=dt, c=1.0, m=0.5, metric=O.METRIC_FIELDS, spin=O.SPIN_NONE,
+                  fields=f, step2=step2)
+    psi0 = np.zeros((16, n, 2), complex)
+    psi0[..., 0] = np.exp(-(X + 1) ** 2 / 2.0 + 1.5j * X)
+    psi0[..., 1] = 0.5 * np.exp(-(X - 1) ** 2 / 2.0 - 1.0j * X)
+    return p, psi0
+
+
+def test_step2bis_time_order():
+    # Data constant in y (no splitting error between directions) on a variable
+    # a(x) < 1: the plain blend and the printed correction are first order, the
+    # corrected step second order; the corrected and Crank-Nicolson steps
+    # converge to the same solution.
+    t = 0.4
+    orders = {}
+    fine = {}
+    for v in (O.STEP2_PLAIN, O.STEP2BIS_PRINTED, O.STEP2BIS_CORRECTED):
+        p, psi0 = _x_only_problem(v, t / 256)
+        ref = O.run(psi0, O.build_tables(p), 256)
+        fine[v] = ref
+        errs = []
+        for k in (16, 32):
+            p, _ = _x_only_problem(v, t / k)
+            errs.append(O.rel_l2(O.run(psi0, O.build_tables(p), k), ref))
+        orders[v] = errs[0] / errs[1]
+    assert 1.7 < orders[O.STEP2_PLAIN] < 2.4, orders
+    assert 1.7 < orders[O.STEP2BIS_PRINTED] < 2.4, orders
+    assert 3.4 < orders[O.STEP2BIS_CORRECTED] < 4.6, orders
+    p, psi0 = _x_only_problem(O.STEP2_PLAIN, t / 256)
+    cn = O.cn_run(psi0, O.build_tables(p), 256)
+    assert O.rel_l2(fine[O.STEP2BIS_CORRECTED], cn) < 0.1 * O.rel_l2(fine[O.STEP2_PLAIN], cn)
