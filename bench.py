@@ -58,14 +58,15 @@ def load_traffic(name: str):
     return d.get("kernels", {}).get(name)
 
 
-def time_solve(D, spec, precision, steps, warmup, timed_steps):
+def time_solve(D, spec, precision, steps, warmup, timed_steps, scheme=0):
     import torch
-    s = D.Solver.from_spec(spec, precision=precision)
+    s = D.Solver.from_spec(spec, precision=precision, scheme=scheme)
     from paper_1909_02894_amd import workloads as W
     psi0 = torch.from_numpy(W.initial_spinor(spec).view(np.float64).copy()).cuda()
     s.set_initial_spinor_device(psi0)
     torch.cuda.synchronize()
-    s.autotune(20)                   # warm-up part 1: pick the fastest compiled schedules
+    if scheme != D.SCHEME_EXP_SPLIT_2BIS:
+        s.autotune(20)               # warm-up part 1: pick the fastest compiled schedules
     s.step_n(warmup)
     torch.cuda.synchronize()
     st = s.stream
@@ -250,6 +251,12 @@ def main():
             "note": "flat 4096x4096 packet solve, 256 MiB state (beyond the Infinity Cache)",
             "roofline": roofline_for(big, "flat", D.FP32, rb),
             "schedule": {"x": rb["sched"][0], "y": rb["sched"][1]}}
+        rc = time_solve(D, spec, D.FP64, 500, args.warmup, 100, scheme=D.SCHEME_EXP_SPLIT_2BIS)
+        variants["step2bis_corrected_fp64"] = {
+            "value": N * 500 / (rc["ms"] * 1e-3), "ms_per_step": rc["ms"] / 500, "dtype": "f64",
+            "note": "second-order directional step (three inverse transforms per direction), same workload",
+            "x_avg_us": round(rc["kernel_ms"][0] / rc["kernel_count"][0] * 1e3, 3),
+            "y_avg_us": round(rc["kernel_ms"][1] / rc["kernel_count"][1] * 1e3, 3)}
         variants["scheme1_cn_gmres"] = bench_cn(D, spec)
         bt = bench_batch(D, W)
         variants["batch_256_mixed"] = bt

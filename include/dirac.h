@@ -127,13 +127,27 @@ typedef struct dirac_solver dirac_solver;
  *    G = I + (dt/2) alpha(x).T, G~ = I - (dt/2) alpha(x).T (spectral derivative of
  *    eq. (trick), alpha(x).T = c (b_x sigma_x d_x + b_y sigma_y d_y)), solved by
  *    restarted GMRES on the device, then Step 3.  Unconditionally stable for any
- *    real b (so b > 1 is accepted); FP64 only, n1, n2 <= 2048. */
-enum { DIRAC_SCHEME_EXP_SPLIT = 0, DIRAC_SCHEME_CN_GMRES = 1 };
+ *    real b (so b > 1 is accepted); FP64 only, n1, n2 <= 2048.
+ *  DIRAC_SCHEME_EXP_SPLIT_2BIS_PRINTED: Scheme II with the directional step of
+ *    eq. (step2bis) as printed, psi* = b Xi + (1-b) psi + b (c dt)^2 [[d^2]] Xi,
+ *    i.e. the symbol K (1 - (c dt xi)^2).  First order in dt; |amplification| <= 1
+ *    needs c dt max|xi| <= sqrt(2) on both axes (else DIRAC_E_UNSTABLE).
+ *  DIRAC_SCHEME_EXP_SPLIT_2BIS: Scheme II with the second-order correction of the
+ *    blend that eq. (step2bis) aims at: psi* = b Xi + (1-b) psi
+ *    + ((c dt)^2/2) (-b(1-b) [[d^2]] psi + b b' [[d]] psi), b' = (d_i a)/S^i (the
+ *    layer factor held fixed).  Second order in dt for the transport of each
+ *    direction; explicit, so not unconditionally stable.  n1, n2 <= 2048. */
+enum {
+    DIRAC_SCHEME_EXP_SPLIT = 0,
+    DIRAC_SCHEME_CN_GMRES = 1,
+    DIRAC_SCHEME_EXP_SPLIT_2BIS_PRINTED = 2,
+    DIRAC_SCHEME_EXP_SPLIT_2BIS = 3
+};
 typedef struct {
     int32_t scheme;          /* DIRAC_SCHEME_*                                         */
     int32_t gmres_restart;   /* Krylov vectors per cycle, 2..63 (0 = 20)                */
     int32_t gmres_max_iter;  /* total iterations per step before DIRAC_E_NOCONV (0 = 400) */
-    int32_t reserved;
+    int32_t reserved;        /* 0                                                      */
     double gmres_rtol;       /* stop at ||G x - b|| <= rtol ||b|| (0 = 1e-13)           */
 } dirac_scheme;
 

@@ -142,7 +142,8 @@ dirac_status dirac_batch_create(int32_t prec, int32_t capacity, void* device_buf
 dirac_status dirac_batch_add(dirac_batch* b, dirac_solver* s, int32_t* slot_out) {
     if (!b || !s || !slot_out) return fail(DIRAC_E_ARG, "null argument");
     if (s->prec != b->prec) return fail(DIRAC_E_ARG, "solver precision differs from the batch");
-    if (s->scheme.scheme != DIRAC_SCHEME_EXP_SPLIT) return fail(DIRAC_E_ARG, "batches run Scheme II solves only");
+    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS)
+        return fail(DIRAC_E_ARG, "batches run Scheme II solves with the plain or printed directional step only");
     if (s->g.n1 > 2048 || s->g.n2 > 2048) return fail(DIRAC_E_SIZE, "batched solves need n1, n2 <= 2048");
     if (!s->has_state) return fail(DIRAC_E_STATE, "set the solver's initial spinor first");
     for (auto* t : b->slots)

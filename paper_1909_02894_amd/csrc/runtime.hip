@@ -22,8 +22,20 @@
 #include "solver.hpp"
 #include "stage_kernels.hpp"
 #include "cn_kernels.hpp"
+#include "bis_kernels.hpp"
 
 namespace dirac {
+
+const BisEntry* bis_entries_f64(int* count);
+const BisEntry* bis_entries_f32(int* count);
+
+const BisEntry* bis_entry(int prec, int n, int dir) {
+    int cnt = 0;
+    const BisEntry* e = prec == DIRAC_FP64 ? bis_entries_f64(&cnt) : bis_entries_f32(&cnt);
+    for (int i = 0; i < cnt; ++i)
+        if (e[i].n == n && e[i].dir == dir) return &e[i];
+    return nullptr;
+}
 
 std::vector<KernelEntry>& kernel_registry() {
     static std::vector<KernelEntry> r;
@@ -71,8 +83,10 @@ dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pm
                       const dirac_scheme* scp) {
     if (!g || !m || !pml) return fail(DIRAC_E_ARG, "null grid, metric or pml");
     const dirac_scheme sc = scheme_or_default(scp);
-    if (sc.scheme != DIRAC_SCHEME_EXP_SPLIT && sc.scheme != DIRAC_SCHEME_CN_GMRES)
+    if (sc.scheme < DIRAC_SCHEME_EXP_SPLIT || sc.scheme > DIRAC_SCHEME_EXP_SPLIT_2BIS)
         return fail(DIRAC_E_ARG, "unknown scheme %d", sc.scheme);
+    if (sc.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS && (g->n1 > 2048 || g->n2 > 2048))
+        return fail(DIRAC_E_SIZE, "the second-order directional step is built for n1, n2 <= 2048");
     if (sc.scheme == DIRAC_SCHEME_CN_GMRES) {
         if (prec != DIRAC_FP64) return fail(DIRAC_E_ARG, "Scheme I is built in FP64 only");
         if (g->n1 > 2048 || g->n2 > 2048) return fail(DIRAC_E_SIZE, "Scheme I needs n1, n2 <= 2048");
@@ -90,6 +104,15 @@ dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pm
     if (!(g->dt > 0) || !std::isfinite(g->dt)) return fail(DIRAC_E_ARG, "dt must be finite and > 0");
     if (!(g->c > 0) || !std::isfinite(g->c)) return fail(DIRAC_E_ARG, "c must be finite and > 0");
     if (!(g->m >= 0) || !std::isfinite(g->m)) return fail(DIRAC_E_ARG, "m must be finite and >= 0");
+    if (sc.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS_PRINTED) {
+        // per-mode factor b (1 - theta^2) e^{-i theta} + 1 - b stays in the unit
+        // disk for every b in [0, 1] iff |1 - theta^2| <= 1
+        const double th1 = g->c * g->dt * M_PI * (g->n1 / 2) / g->a1;
+        const double th2 = g->c * g->dt * M_PI * (g->n2 / 2) / g->a2;
+        if (std::max(th1, th2) > std::sqrt(2.0))
+            return fail(DIRAC_E_UNSTABLE, "eq. (step2bis) as printed needs c dt max|xi| <= sqrt(2); got %.6g",
+                        std::max(th1, th2));
+    }
     if (m->kind < 0 || m->kind > 3) return fail(DIRAC_E_ARG, "unknown metric kind %d", m->kind);
     if (m->spin < 0 || m->spin > 2) return fail(DIRAC_E_ARG, "unknown spin selector %d", m->spin);
     if (m->kind == DIRAC_METRIC_GAUSS_BUMP && (!(m->bump_s > 0) || !std::isfinite(m->bump_s) || !std::isfinite(m->bump_A)))
@@ -125,6 +148,7 @@ Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* 
     L.psi = take(N * 4 * sz);
     L.a = curved ? take(N * sz) : SIZE_MAX;
     L.E = curved ? take(N * 4 * sz) : SIZE_MAX;
+    L.da = curved && sc.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS ? take(N * 2 * sz) : SIZE_MAX;
     L.obs = take(5 * N * 8);
     L.fields = m->kind == DIRAC_METRIC_FIELDS ? take(6 * N * 8) : SIZE_MAX;
     L.scratch = take(N * 4 * 8);
@@ -217,16 +241,46 @@ StageParams<T> stage_params(const dirac_solver* s, int dir, int e_pre, int e_pos
     return p;
 }
 
+template <typename T>
+BisParams<T> bis_params(const dirac_solver* s, int dir, int e_pre, int e_post) {
+    BisParams<T> p{};
+    char* b = s->base;
+    p.s = stage_params<T>(s, dir, e_pre, e_post);
+    p.da = s->lay.da != SIZE_MAX ? reinterpret_cast<const T*>(b + s->lay.da) : nullptr;
+    p.D = reinterpret_cast<const T*>(b + s->lay.D[dir]);
+    p.hh = (T)(0.5 * (s->g.c * s->g.dt) * (s->g.c * s->g.dt));
+    p.n = (T)(dir == 0 ? s->g.n1 : s->g.n2);
+    return p;
+}
+
 // One stage launch description (kernel + by-value parameter block).
 struct Launch {
     const void* fn;
     dim3 grid, block;
-    alignas(16) unsigned char params[sizeof(StageParams<double>)];
+    alignas(16) unsigned char params[sizeof(BisParams<double>)];
     size_t psize;
 };
 
 Launch make_launch(const dirac_solver* s, int dir, int e_pre, int e_post) {
     Launch L{};
+    if (s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS && (s->curved || s->pml)) {
+        // second-order directional step (b = 1 everywhere makes it the plain step)
+        const int nlines = dir == 0 ? s->g.n2 : s->g.n1;
+        const BisEntry* e = bis_entry(s->prec, dir == 0 ? s->g.n1 : s->g.n2, dir);
+        L.fn = e->fn[s->curved ? 1 : 0];
+        L.grid = dim3((nlines + e->lines - 1) / e->lines);
+        L.block = dim3(e->nthreads);
+        if (s->prec == DIRAC_FP64) {
+            auto p = bis_params<double>(s, dir, e_pre, e_post);
+            std::memcpy(L.params, &p, sizeof p);
+            L.psize = sizeof p;
+        } else {
+            auto p = bis_params<float>(s, dir, e_pre, e_post);
+            std::memcpy(L.params, &p, sizeof p);
+            L.psize = sizeof p;
+        }
+        return L;
+    }
     const KernelEntry* e = s->sched[dir];
     const int nlines = dir == 0 ? s->g.n2 : s->g.n1;
     L.fn = e->stage_fn[s->curved ? 2 : (s->pml ? 1 : 0)];
@@ -409,6 +463,7 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
         ap.sigma0 = pml->sigma0;
         ap.ctheta = std::cos(pml->theta);
         ap.fp32 = fp32;
+        ap.k_printed = sc.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS_PRINTED;
         ap.inv_s = b + lay.inv_s[ax];
         ap.K = b + lay.K[ax];
         ap.D = b + lay.D[ax];
@@ -426,6 +481,7 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
     pp.fp32 = fp32;
     pp.a_out = s->curved ? b + lay.a : nullptr;
     pp.E_out = s->curved ? b + lay.E : nullptr;
+    pp.da_out = lay.da != SIZE_MAX ? b + lay.da : nullptr;
     pp.obs = reinterpret_cast<double*>(b + lay.obs);
     pp.partial = reinterpret_cast<double*>(b + lay.partials);
     double* fold = reinterpret_cast<double*>(b + lay.out);
@@ -438,7 +494,7 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
     if (e != hipSuccess) return bail(hip_fail(e, "setup synchronise"));
     if (host_fold[2] != 0.0)
         return bail(fail(DIRAC_E_NONFINITE, "%.0f grid points have non-finite metric fields or tables", host_fold[2]));
-    if (sc.scheme == DIRAC_SCHEME_EXP_SPLIT && (host_fold[0] < 0.0 || host_fold[1] > 1.0 + 1e-12))
+    if (sc.scheme != DIRAC_SCHEME_CN_GMRES && (host_fold[0] < 0.0 || host_fold[1] > 1.0 + 1e-12))
         return bail(fail(DIRAC_E_UNSTABLE,
                          "blend coefficient b = a/S ranges over [%.17g, %.17g]; the directional step is "
                          "stable only for b in [0, 1]", host_fold[0], host_fold[1]));
@@ -620,7 +676,7 @@ dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
     if (!s || !ms_out || !counts_out) return fail(DIRAC_E_ARG, "null argument");
     if (nsteps < 0) return fail(DIRAC_E_ARG, "nsteps must be >= 0");
     if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
-    if (s->scheme.scheme != DIRAC_SCHEME_EXP_SPLIT) return fail(DIRAC_E_ARG, "per-direction timing is for Scheme II");
+    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES) return fail(DIRAC_E_ARG, "per-direction timing is for Scheme II");
     ms_out[0] = ms_out[1] = 0.0;
     counts_out[0] = counts_out[1] = 0;
     if (nsteps == 0) return DIRAC_OK;
@@ -656,7 +712,8 @@ dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
 
 dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
     if (!s || reps < 1) return fail(DIRAC_E_ARG, "bad arguments");
-    if (s->scheme.scheme != DIRAC_SCHEME_EXP_SPLIT) return fail(DIRAC_E_ARG, "schedules apply to Scheme II only");
+    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS)
+        return fail(DIRAC_E_ARG, "schedules apply to Scheme II's plain and printed directional steps only");
     if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
     const size_t N = (size_t)s->g.n1 * s->g.n2;
     const size_t bytes = N * 4 * (s->prec == DIRAC_FP32 ? 4 : 8);

@@ -43,7 +43,8 @@ __global__ void setup_axis_kernel(SetupAxisParams p) {
     const int pp = k < n / 2 ? k : k - n;               // Nyquist keeps p = -n/2
     const double xi = pp * M_PI / p.a;
     const double th = p.c * p.dt * xi;
-    const double cs = cos(th), sn = sin(th);
+    const double g = p.k_printed ? 1.0 - th * th : 1.0;
+    const double cs = g * cos(th), sn = g * sin(th);
     double ts, tc;
     sincospi(2.0 * k / n, &ts, &tc);                    // exp(-2 pi i k / n) = (tc, -ts)
     const double inv_n = 1.0 / n;
@@ -137,6 +138,11 @@ __global__ void setup_point_kernel(SetupPointParams p) {
         const double e0r = C, e0i = -D * wz, e1r = D * ux, e1i = -D * uy;
         if (p.a_out) {
             if (p.fp32) put<float>(p.a_out, q, a); else put<double>(p.a_out, q, a);
+        }
+        if (p.da_out) {
+            const double dax = a * (f.phix - f.psix), day = a * (f.phiy - f.psiy);
+            if (p.fp32) { put<float>(p.da_out, 2 * q, dax); put<float>(p.da_out, 2 * q + 1, day); }
+            else { put<double>(p.da_out, 2 * q, dax); put<double>(p.da_out, 2 * q + 1, day); }
         }
         if (p.E_out) {
             if (p.fp32) {

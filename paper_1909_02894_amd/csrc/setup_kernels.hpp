@@ -12,6 +12,7 @@ struct SetupAxisParams {
     int pml_width, pml_type;
     double sigma0, ctheta;
     int fp32;
+    int k_printed; // symbol of eq. (step2bis) as printed: K (1 - (c dt xi)^2)
     void* inv_s;   // n reals
     void* K;       // n complex: (cos, sin)(c dt xi) / n
     void* D;       // n reals: xi / n
@@ -29,6 +30,7 @@ struct SetupPointParams {
     int fp32;
     void* a_out;            // per point a (or null)
     void* E_out;            // per point (e0 re, e0 im, e1 re, e1 im) (or null)
+    void* da_out;           // per point (d_x a, d_y a) (or null)
     double* obs;            // 5 planes: w, c a, gx, gy, V
     double* partial;        // 3 doubles per workgroup of 256
 };

@@ -16,6 +16,7 @@ struct Layout {
     size_t psi;        // state, n1 n2 points x 2 components x complex (T)
     size_t a;          // a(x) per point (T), curved metrics only
     size_t E;          // Step-1 exponential per point, 4 T (curved only)
+    size_t da;         // (d_x a, d_y a) per point, 2 T (second-order directional step, curved only)
     size_t obs;        // 5 FP64 planes for the observables
     size_t fields;     // FIELDS metric staging, 6 FP64 planes
     size_t scratch;    // n1 n2 x 32 bytes: complex128 staging / autotune save

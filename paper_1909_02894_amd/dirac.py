@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdirac.so
 FP64, FP32 = 0, 1
 METRIC_FLAT, METRIC_GAUSS_BUMP, METRIC_PAPER_EXP3, METRIC_FIELDS = 0, 1, 2, 3
 SPIN_NONE, SPIN_PAPER, SPIN_2P1 = 0, 1, 2
-SCHEME_EXP_SPLIT, SCHEME_CN_GMRES = 0, 1
+SCHEME_EXP_SPLIT, SCHEME_CN_GMRES, SCHEME_EXP_SPLIT_2BIS_PRINTED, SCHEME_EXP_SPLIT_2BIS = 0, 1, 2, 3
 
 STATUS = {0: "DIRAC_OK", -1: "DIRAC_E_ARG", -2: "DIRAC_E_SIZE", -3: "DIRAC_E_UNSTABLE",
           -4: "DIRAC_E_NOMEM", -5: "DIRAC_E_DEVICE", -6: "DIRAC_E_STATE", -7: "DIRAC_E_NONFINITE",

@@ -124,3 +124,27 @@ def test_scheme_selection_is_validated():
     assert create_status(D.Scheme(CN, 0, 0, 0, 0.0)) == -1                    # valid; null device buffer
     assert "null device buffer" in D.last_error()
     assert D.lib.dirac_cn_stats(None, None, None) == -1
+
+
+def test_step2bis_scheme_validation():
+    from paper_1909_02894_amd import dirac as D
+    g, m, p, _ = D.make_structs(256, 128, 20.0, 20.0, 0.01, 1.0, 0.0, metric=D.METRIC_GAUSS_BUMP,
+                                spin=D.SPIN_2P1, bump_A=1.0, bump_s=3.0, pml_width=16)
+    plain = D.footprint_bytes(g, m, p, D.FP64)
+    printed = D.footprint_bytes_scheme(g, m, p, D.FP64, D.Scheme(D.SCHEME_EXP_SPLIT_2BIS_PRINTED, 0, 0, 0, 0.0))
+    corr = D.footprint_bytes_scheme(g, m, p, D.FP64, D.Scheme(D.SCHEME_EXP_SPLIT_2BIS, 0, 0, 0, 0.0))
+    assert printed == plain
+    assert corr >= plain + 256 * 128 * 16                  # (d_x a, d_y a) per point
+    # flat solves carry no gradient table
+    gf, mf, pf, _ = D.make_structs(64, 64, 5.0, 5.0, 0.01, 1.0, 1.0, pml_width=4)
+    assert (D.footprint_bytes_scheme(gf, mf, pf, D.FP32, D.Scheme(D.SCHEME_EXP_SPLIT_2BIS, 0, 0, 0, 0.0))
+            == D.footprint_bytes(gf, mf, pf, D.FP32))
+    # printed form: c dt max|xi| = 0.05 pi 256 / 5 > sqrt(2)
+    gb, mb, pb, _ = D.make_structs(512, 512, 5.0, 5.0, 0.05, 1.0, 1.0)
+    assert D.footprint_bytes_scheme(gb, mb, pb, D.FP64, D.Scheme(D.SCHEME_EXP_SPLIT_2BIS_PRINTED, 0, 0, 0, 0.0)) == 0
+    assert "sqrt(2)" in D.last_error()
+    assert D.footprint_bytes_scheme(gb, mb, pb, D.FP64, None) > 0
+    g4, m4, p4, _ = D.make_structs(4096, 64, 5.0, 5.0, 1e-4, 1.0, 1.0)
+    assert D.footprint_bytes_scheme(g4, m4, p4, D.FP32, D.Scheme(D.SCHEME_EXP_SPLIT_2BIS, 0, 0, 0, 0.0)) == 0
+    assert D.footprint_bytes_scheme(g4, m4, p4, D.FP32, D.Scheme(D.SCHEME_EXP_SPLIT_2BIS_PRINTED, 0, 0, 0, 0.0)) > 0
+    assert D.footprint_bytes_scheme(g4, m4, p4, D.FP32, D.Scheme(7, 0, 0, 0, 0.0)) == 0

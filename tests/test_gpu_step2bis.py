@@ -1,0 +1,126 @@
+"""GPU parity of the directional step of eq. (step2bis) (Sec. 5.2): as printed
+(symbol K (1 - (c dt xi)^2) in the plain direction kernels) and corrected (the
+three-inverse-transform kernels), against the oracle's directional_stage_2bis.
+
+Tolerances as for the plain step: FP64 1e-11 relative L2; FP32 (FP64 tables
+rounded once) 2e-5 after a few tens of steps.
+"""
+import numpy as np
+import pytest
+
+from oracle import dirac_oracle as O
+from paper_1909_02894_amd import workloads as W
+from tests.helpers import oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32 = 2e-5
+
+
+@pytest.fixture(scope="module")
+def D():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_02894_amd import dirac
+    return dirac
+
+
+def run_pair(D, spec, steps, scheme, step2, precision=0, fields=None, ofields=None, psi0=None, split=()):
+    psi0 = W.initial_spinor(spec) if psi0 is None else psi0
+    s = D.Solver.from_spec(spec, precision=precision, fields=fields, scheme=scheme)
+    s.set_initial_spinor(psi0)
+    done = 0
+    for k in sorted(set(split) | {steps}):
+        s.step_n(k - done)
+        done = k
+    g = s.get_spinor()
+    ref = O.run(psi0, O.build_tables(oracle_problem(spec, ofields, step2=step2)), steps)
+    return s, g, ref
+
+
+@pytest.mark.parametrize("m", [0.0, 1.0])
+def test_corrected_curved_bump_with_layer_fp64(D, m):
+    spec = W.curved_bump(n=64, steps=12, m=m)
+    _, g, ref = run_pair(D, spec, 12, D.SCHEME_EXP_SPLIT_2BIS, O.STEP2BIS_CORRECTED, split=(1, 5))
+    assert O.rel_l2(g, ref) < TOL64
+
+
+def test_corrected_curved_bump_fp32(D):
+    spec = W.curved_bump(n=128, steps=20, m=1.0)
+    _, g, ref = run_pair(D, spec, 20, D.SCHEME_EXP_SPLIT_2BIS, O.STEP2BIS_CORRECTED, precision=D.FP32)
+    assert O.rel_l2(g, ref) < TOL32
+
+
+def test_corrected_exp3_rectangular_and_flat_layer(D):
+    spec = W.paper_exp3(n=64, steps=8)
+    spec.n2 = 32
+    _, g, ref = run_pair(D, spec, 8, D.SCHEME_EXP_SPLIT_2BIS, O.STEP2BIS_CORRECTED)
+    assert O.rel_l2(g, ref) < TOL64
+    spec = W.flat_small(n=64, steps=10)
+    spec.n2, spec.pml_width = 128, 8
+    _, g, ref = run_pair(D, spec, 10, D.SCHEME_EXP_SPLIT_2BIS, O.STEP2BIS_CORRECTED)
+    assert O.rel_l2(g, ref) < TOL64
+
+
+@pytest.mark.parametrize("n1,n2", [(2048, 16), (16, 2048)])
+def test_corrected_largest_lines(D, n1, n2):
+    # 2048-point lines (512-thread workgroups) in each direction, random data, a
+    # metric that varies along the long axis, and a layer on both axes
+    a = 40.0
+    spec = W.flat_small(n=16, steps=4)
+    spec.n1, spec.n2, spec.a1, spec.a2, spec.dt, spec.m = n1, n2, a, a, 0.02, 0.5
+    spec.metric, spec.spin, spec.pml_width = W.METRIC_FIELDS, W.SPIN_NONE, 6
+    X, Y = np.meshgrid(O.grid_points(n1, a), O.grid_points(n2, a))
+    z = np.zeros_like(X)
+    if n1 > n2:
+        g = np.exp(-X ** 2 / 4.0)
+        f = O.MetricFields(z, 0.3 * g, z, z, -0.3 * X / 2.0 * g, z)
+    else:
+        g = np.exp(-Y ** 2 / 4.0)
+        f = O.MetricFields(z, 0.3 * g, z, z, z, -0.3 * Y / 2.0 * g)
+    arr = (f.phi, f.psi, f.phi_x, f.phi_y, f.psi_x, f.psi_y)
+    _, g, ref = run_pair(D, spec, 4, D.SCHEME_EXP_SPLIT_2BIS, O.STEP2BIS_CORRECTED, fields=arr, ofields=f,
+                         psi0=W.random_spinor(n1, n2, 7))
+    assert O.rel_l2(g, ref) < TOL64
+
+
+def test_corrected_flat_without_layer_is_the_plain_step(D):
+    spec = W.flat_small(n=64, steps=10)
+    s1 = D.Solver.from_spec(spec, scheme=D.SCHEME_EXP_SPLIT_2BIS)
+    s2 = D.Solver.from_spec(spec)
+    for s in (s1, s2):
+        s.set_initial_spinor(W.initial_spinor(spec))
+        s.step_n(10)
+    assert np.array_equal(s1.get_spinor(), s2.get_spinor())
+
+
+def test_printed_fp64_and_fp32(D):
+    spec = W.curved_bump(n=64, steps=12, m=1.0)
+    _, g, ref = run_pair(D, spec, 12, D.SCHEME_EXP_SPLIT_2BIS_PRINTED, O.STEP2BIS_PRINTED, split=(3,))
+    assert O.rel_l2(g, ref) < TOL64
+    _, g, ref = run_pair(D, spec, 12, D.SCHEME_EXP_SPLIT_2BIS_PRINTED, O.STEP2BIS_PRINTED, precision=D.FP32)
+    assert O.rel_l2(g, ref) < TOL32
+
+
+def test_step2bis_limits(D):
+    spec = W.flat_small(n=512, steps=1)
+    spec.a1 = spec.a2 = 5.0
+    spec.dt = 0.05                                   # c dt max|xi| = 8 > sqrt(2)
+    with pytest.raises(D.DiracError) as ei:
+        D.Solver.from_spec(spec, scheme=D.SCHEME_EXP_SPLIT_2BIS_PRINTED)
+    assert "sqrt(2)" in str(ei.value)
+    spec = W.curved_bump(n=64, steps=1)
+    s = D.Solver.from_spec(spec, scheme=D.SCHEME_EXP_SPLIT_2BIS)
+    s.set_initial_spinor(W.initial_spinor(spec))
+    with pytest.raises(D.DiracError):
+        s.autotune(2)
+    b = D.Batch(precision=D.FP64, capacity=2)
+    with pytest.raises(D.DiracError):
+        b.add(s)
+    b.close()
+    spec = W.curved_bump(n=4096, steps=1)
+    with pytest.raises(D.DiracError) as ei:
+        D.Solver.from_spec(spec, scheme=D.SCHEME_EXP_SPLIT_2BIS)
+    assert "2048" in str(ei.value)
