@@ -236,13 +236,23 @@ dirac_status dirac_set_schedule(dirac_solver* s, int32_t direction, const dirac_
  * HIP graph of 2 * graph_chunk stage kernels (default, chunk 32). */
 dirac_status dirac_set_launch_mode(dirac_solver* s, int32_t use_graph, int32_t graph_chunk);
 
-/* Advance nsteps like dirac_step_n with one kernel launch per stage and a HIP
- * event recorded on the solver's stream before the first launch and after every
- * launch (so the intervals tile the timed region), then synchronise.
- * ms_out[0] / ms_out[1] = summed duration of the x / y stage kernels in
- * milliseconds, counts_out[0..1] = number of launches of each. */
+/* Advance nsteps like dirac_step_n with one kernel launch per stage, each
+ * launched with its own start/stop HIP events (hipExtLaunchKernel), so the
+ * durations are the kernels' execution times in the x, y, x, y ... order of a
+ * real run; then synchronise.  ms_out[0] / ms_out[1] = summed duration of the
+ * x / y stage kernels in milliseconds, counts_out[0..1] = number of launches. */
 dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
                                 int64_t* counts_out);
+
+/* Average device time of one launch of each direction kernel: for each
+ * direction, `reps` launches of that kernel alone (the mid-run form: the x
+ * kernel applies Step 5 and Step 1, the y kernel neither) are recorded into a
+ * HIP graph and replayed between two HIP events on the solver's stream.
+ * us_out[0] / us_out[1] = microseconds per x / y launch (graph-internal
+ * launch gaps included).  The state and the step counter are saved and
+ * restored; synchronises.  Not for Scheme I or solves with time-dependent
+ * potentials (DIRAC_E_ARG). */
+dirac_status dirac_time_directions(dirac_solver* s, int32_t reps, double* us_out);
 
 /* Autotuner: time every compiled schedule of both directions on this solver's
  * own buffers (the state is saved and restored, so the solve is unchanged),

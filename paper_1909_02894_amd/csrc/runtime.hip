@@ -1,6 +1,7 @@
 // runtime.hip -- the C ABI of libdirac: validation, device-buffer layout,
 // setup, the step launcher (direct or HIP-graph replay), observables,
 // conversions, schedules, timing and the autotuner.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -680,34 +681,91 @@ dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
     ms_out[0] = ms_out[1] = 0.0;
     counts_out[0] = counts_out[1] = 0;
     if (nsteps == 0) return DIRAC_OK;
-    // one event before the first launch and one after every launch: launch i
-    // spans events i .. i+1, so the intervals tile the whole timed region
+    // every launch carries its own start/stop events (hipExtLaunchKernel): the
+    // timestamps are those of the kernel dispatch itself, so the durations are
+    // kernel execution times in the real x, y, x, y ... order, with no extra
+    // packets between the launches
     const size_t nl = (size_t)nsteps * 2;
-    while (s->events.size() < nl + 1) {
+    while (s->events.size() < 2 * nl) {
         hipEvent_t ev;
         HIP_TRY(hipEventCreate(&ev), "hipEventCreate");
         s->events.push_back(ev);
     }
     hipStream_t st = s->stream;
-    HIP_TRY(hipEventRecord(s->events[0], st), "hipEventRecord");
     size_t k = 0;
     for (int64_t n = 0; n < nsteps; ++n) {
         Launch lx = make_launch(s, 0, n == 0 ? 1 : 2, 0);
         Launch ly = make_launch(s, 1, 0, n == nsteps - 1 ? 1 : 0);
-        HIP_TRY(do_launch(lx, st), "launch x stage");
-        HIP_TRY(hipEventRecord(s->events[++k], st), "hipEventRecord");
-        HIP_TRY(do_launch(ly, st), "launch y stage");
-        HIP_TRY(hipEventRecord(s->events[++k], st), "hipEventRecord");
+        for (Launch* L : {&lx, &ly}) {
+            void* args[] = {L->params};
+            HIP_TRY(hipExtLaunchKernel(L->fn, L->grid, L->block, args, 0, st, s->events[2 * k],
+                                       s->events[2 * k + 1], 0), "launch stage");
+            ++k;
+        }
     }
     HIP_TRY(hipStreamSynchronize(st), "synchronise");
     for (size_t i = 0; i < k; ++i) {
         float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, s->events[i], s->events[i + 1]), "hipEventElapsedTime");
+        HIP_TRY(hipEventElapsedTime(&ms, s->events[2 * i], s->events[2 * i + 1]), "hipEventElapsedTime");
         ms_out[i & 1] += ms;
         counts_out[i & 1] += 1;
     }
     s->step += nsteps;
     return DIRAC_OK;
+}
+
+dirac_status dirac_time_directions(dirac_solver* s, int32_t reps, double* us_out) {
+    if (!s || !us_out || reps < 1 || reps > 100000) return fail(DIRAC_E_ARG, "bad arguments");
+    if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
+    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES) return fail(DIRAC_E_ARG, "per-direction timing is for Scheme II");
+    const size_t N = (size_t)s->g.n1 * s->g.n2;
+    const size_t bytes = N * 4 * (s->prec == DIRAC_FP32 ? 4 : 8);
+    char* b = s->base;
+    hipStream_t st = s->stream;
+    HIP_TRY(hipMemcpyAsync(b + s->lay.scratch, b + s->lay.psi, bytes, hipMemcpyDeviceToDevice, st), "save state");
+    hipEvent_t ev[2];
+    HIP_TRY(hipEventCreate(&ev[0]), "hipEventCreate");
+    if (hipEventCreate(&ev[1]) != hipSuccess) { (void)hipEventDestroy(ev[0]); return fail(DIRAC_E_DEVICE, "hipEventCreate"); }
+    dirac_status result = DIRAC_OK;
+    for (int dir = 0; dir < 2 && result == DIRAC_OK; ++dir) {
+        Launch L = make_launch(s, dir, dir == 0 ? 2 : 0, 0);
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        auto step = [&]() -> dirac_status {
+            HIP_TRY(hipGraphCreate(&graph, 0), "hipGraphCreate");
+            hipGraphNode_t prev = nullptr;
+            for (int k = 0; k < reps; ++k) {
+                void* args[] = {L.params};
+                hipKernelNodeParams kp{};
+                kp.func = const_cast<void*>(L.fn);
+                kp.gridDim = L.grid;
+                kp.blockDim = L.block;
+                kp.kernelParams = args;
+                hipGraphNode_t node;
+                HIP_TRY(hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp),
+                        "hipGraphAddKernelNode");
+                prev = node;
+            }
+            HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            HIP_TRY(hipGraphLaunch(exec, st), "hipGraphLaunch");          // warm
+            HIP_TRY(hipEventRecord(ev[0], st), "hipEventRecord");
+            HIP_TRY(hipGraphLaunch(exec, st), "hipGraphLaunch");
+            HIP_TRY(hipEventRecord(ev[1], st), "hipEventRecord");
+            HIP_TRY(hipEventSynchronize(ev[1]), "hipEventSynchronize");
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]), "hipEventElapsedTime");
+            us_out[dir] = 1e3 * (double)ms / reps;
+            return DIRAC_OK;
+        };
+        result = step();
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    HIP_TRY(hipMemcpyAsync(b + s->lay.psi, b + s->lay.scratch, bytes, hipMemcpyDeviceToDevice, st), "restore state");
+    HIP_TRY(hipStreamSynchronize(st), "synchronise");
+    return result;
 }
 
 dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {

@@ -96,6 +96,7 @@ SIGNATURES = {
     "dirac_set_launch_mode": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
     "dirac_step_n_timed": (C.c_int32, [_vp, C.c_int64, _dp, C.POINTER(C.c_int64)]),
     "dirac_autotune": (C.c_int32, [_vp, C.c_int32]),
+    "dirac_time_directions": (C.c_int32, [_vp, C.c_int32, _dp]),
     "dirac_tune_cache_save": (C.c_int32, [C.c_char_p]),
     "dirac_tune_cache_load": (C.c_int32, [C.c_char_p]),
     "dirac_batch_footprint_bytes": (C.c_size_t, [C.c_int32]),
@@ -308,6 +309,12 @@ class Solver:
 
     def autotune(self, reps=20):
         _check(lib.dirac_autotune(self.h, reps))
+
+    def time_directions(self, reps=200):
+        """Microseconds per launch of the x and y kernels (each replayed alone)."""
+        us = (C.c_double * 2)()
+        _check(lib.dirac_time_directions(self.h, reps, us))
+        return [us[0], us[1]]
 
     def cn_stats(self):
         """(total GMRES iterations, last relative residual) of a Scheme I solver."""

@@ -270,3 +270,14 @@ def test_precision_report_flat_2048(D, capsys):
         print("\nprecision 2048^2 flat: step, fp32 rel_l2, fp32 maxabs/max, fp64 rel_l2, fp64 maxabs/max")
         for r in rows:
             print("  %5d  %.3e  %.3e  %.3e  %.3e" % r)
+
+
+def test_time_directions_restores_the_state(D):
+    spec = W.curved_bump(n=128, steps=6, m=1.0)
+    s, g = gpu_run(D, spec, 3)
+    us = s.time_directions(20)
+    assert all(u > 0 for u in us)
+    s.step_n(3)
+    _, ref = gpu_run(D, spec, 6)
+    assert np.array_equal(s.get_spinor(), ref[6])
+    assert s.observables()["step"] == 6
