@@ -57,7 +57,12 @@ them):
   expansion of the blend asks for, also as the second-order correction derived
   from that expansion (STEP2BIS_CORRECTED); the latter uses the gradient of
   a along the direction and holds the layer factor 1/S fixed.  Both are
-  explicit (the implicit treatment the paper mentions is not specified).
+  explicit (the implicit treatment the paper mentions is not specified);
+* R16 electromagnetic potentials enter F(t, x) of Sec. 2 as
+  -e c a (A_x sigma_x + A_y sigma_y) - e A0 (the conformal 2-D form of
+  -i alpha(x).(-i e A) - e A0), each separable: A0 = V(x) fV(t),
+  A_i = A_i(x) fA(t), with fV, fA of the form c0 + c1 sin(omega t + phase) g(t),
+  g a Gaussian window or 1; Steps 1 and 5 of step n use F at t_{n+1/2}.
 """
 from __future__ import annotations
 
@@ -156,6 +161,34 @@ class MetricFields:
     phi_y: np.ndarray
     psi_x: np.ndarray
     psi_y: np.ndarray
+
+
+@dataclass
+class Envelope:
+    """Time profile f(t) = c0 + c1 sin(omega t + phase) g(t), g(t) =
+    exp(-((t - t0) / tau)^2) for tau > 0, else 1 (R16)."""
+    c0: float = 1.0
+    c1: float = 0.0
+    omega: float = 0.0
+    phase: float = 0.0
+    t0: float = 0.0
+    tau: float = 0.0
+
+    def __call__(self, t: float) -> float:
+        g = math.exp(-((t - self.t0) / self.tau) ** 2) if self.tau > 0 else 1.0
+        return self.c0 + self.c1 * math.sin(self.omega * t + self.phase) * g
+
+
+@dataclass
+class EMPotentials:
+    """Electromagnetic potentials of F(t, x) (Sec. 2): A0(t, x) = V(x) fV(t) and
+    A_i(t, x) = A_i(x) fA(t), with charge e; arrays of shape (n2, n1)."""
+    V: np.ndarray
+    Ax: np.ndarray
+    Ay: np.ndarray
+    charge: float = 1.0
+    fV: Envelope = field(default_factory=Envelope)
+    fA: Envelope = field(default_factory=Envelope)
 
 
 def metric_fields(kind: int, x: np.ndarray, y: np.ndarray, bump_A: float = 0.0,
@@ -291,6 +324,36 @@ def half_step_exponential(f: MetricFields, spin: int, m: float, c: float, dt: fl
     return E
 
 
+def half_step_exponential_em(f: MetricFields, spin: int, m: float, c: float, dt: float,
+                             em: EMPotentials, t: float) -> np.ndarray:
+    """E(t) = exp(-i dt/2 [beta(x) m c^2 + F(t, x)]) with the electromagnetic part of
+    F (Sec. 2): -e c a (A_x sigma_x + A_y sigma_y) - e A0 I (alpha(x) = c a alpha in
+    the conformal 2-D form).  The exponent is i (dt/2) e A0 I + u . sigma with
+        u = (-(dt/4) c a chi_x + i (dt/2) e c a A_x, -(dt/4) c a chi_y + i (dt/2) e c a A_y,
+             -i (dt/2) m c^2 e^Phi),
+    and now u . u is complex: exp(u . sigma) = C I + D u . sigma with C = cosh r,
+    D = sinh r / r, r^2 = u . u (both even in r), series near u . u = 0."""
+    chi_x, chi_y, _ = spin_potential(spin, f)
+    a = np.exp(f.phi - f.psi)
+    fa, fv = em.fA(t), em.fV(t)
+    ux = -(dt / 4.0) * c * a * chi_x + 0.5j * dt * em.charge * c * a * em.Ax * fa
+    uy = -(dt / 4.0) * c * a * chi_y + 0.5j * dt * em.charge * c * a * em.Ay * fa
+    uz = -0.5j * dt * m * c * c * np.exp(f.phi) * np.ones_like(a)
+    s2 = ux * ux + uy * uy + uz * uz
+    r = np.sqrt(s2.astype(np.complex128))
+    small = np.abs(s2) < 1e-8
+    with np.errstate(invalid="ignore", divide="ignore"):
+        C = np.cosh(r)
+        D = np.sinh(r) / r
+    C = np.where(small, 1.0 + s2 / 2.0 + s2 * s2 / 24.0, C)
+    D = np.where(small, 1.0 + s2 / 6.0 + s2 * s2 / 120.0, D)
+    phase = np.exp(0.5j * dt * em.charge * em.V * fv)
+    E = (C[..., None, None] * ID2
+         + D[..., None, None] * (ux[..., None, None] * SIGMA_X + uy[..., None, None] * SIGMA_Y
+                                 + uz[..., None, None] * SIGMA_Z))
+    return phase[..., None, None] * E
+
+
 def apply_pointwise(M: np.ndarray, psi: np.ndarray) -> np.ndarray:
     """psi_k <- M_k psi_k for 2x2 matrices M of shape (..., 2, 2)."""
     return np.einsum("...ab,...b->...a", M, psi)
@@ -329,6 +392,7 @@ class Problem:
     pml_sigma0: float = 1.0
     pml_theta: float = 0.0
     step2: int = STEP2_PLAIN
+    em: EMPotentials | None = None
 
 
 @dataclass
@@ -437,29 +501,39 @@ def directional_stage_2bis(psi: np.ndarray, axis: int, K: np.ndarray, b: np.ndar
     return out
 
 
-def step_stages(psi: np.ndarray, T: Tables):
-    """One time step, returning every stage boundary (after Step 1, after the
-    x direction, after the y direction, after Step 5)."""
+def step_exponential(T: Tables, n: int) -> np.ndarray:
+    """The Step-1 / Step-5 factor of step n: F at t_{n+1/2} = (n + 1/2) dt (eq. (step1))."""
     p = T.prob
-    s1 = apply_pointwise(T.E, psi)                       # Step 1
+    if p.em is None:
+        return T.E
+    return half_step_exponential_em(T.fields, p.spin, p.m, p.c, p.dt, p.em, (n + 0.5) * p.dt)
+
+
+def step_stages(psi: np.ndarray, T: Tables, n: int = 0):
+    """Step n (from t_n to t_{n+1}), returning every stage boundary (after Step 1,
+    after the x direction, after the y direction, after Step 5)."""
+    p = T.prob
+    E = step_exponential(T, n)
+    s1 = apply_pointwise(E, psi)                         # Step 1
     if p.step2 == STEP2_PLAIN:
         s2 = directional_stage(s1, 1, T.Kx, T.bx)        # direction 1 (x)
         s3 = directional_stage(s2, 0, T.Ky, T.by)        # direction 2 (y)
     else:
         s2 = directional_stage_2bis(s1, 1, T.Kx, T.bx, T.xi1, p.c, p.dt, p.step2, T.dbx)
         s3 = directional_stage_2bis(s2, 0, T.Ky, T.by, T.xi2, p.c, p.dt, p.step2, T.dby)
-    s4 = apply_pointwise(T.E, s3)                        # Step 5
+    s4 = apply_pointwise(E, s3)                          # Step 5
     return s1, s2, s3, s4
 
 
-def step(psi: np.ndarray, T: Tables) -> np.ndarray:
-    return step_stages(psi, T)[3]
+def step(psi: np.ndarray, T: Tables, n: int = 0) -> np.ndarray:
+    return step_stages(psi, T, n)[3]
 
 
-def run(psi0: np.ndarray, T: Tables, nsteps: int, callback=None) -> np.ndarray:
+def run(psi0: np.ndarray, T: Tables, nsteps: int, callback=None, start: int = 0) -> np.ndarray:
+    """Steps start .. start + nsteps - 1 (the index fixes the time of F)."""
     psi = np.array(psi0, dtype=np.complex128, copy=True)
-    for n in range(nsteps):
-        psi = step(psi, T)
+    for n in range(start, start + nsteps):
+        psi = step(psi, T, n)
         if callback is not None:
             callback(n + 1, psi)
     return psi
@@ -476,9 +550,10 @@ def weight(T: Tables) -> np.ndarray:
     return np.exp(T.chi - T.fields.phi + T.fields.psi)
 
 
-def apply_hamiltonian(psi: np.ndarray, T: Tables) -> np.ndarray:
+def apply_hamiltonian(psi: np.ndarray, T: Tables, t: float = 0.0) -> np.ndarray:
     """H psi = -i c a (sigma_x [[d_x]] + sigma_y [[d_y]]) psi
                - i (c a / 2)(chi_x sigma_x + chi_y sigma_y) psi + e^Phi m c^2 sigma_z psi
+               [- e c a (A_x sigma_x + A_y sigma_y) psi - e A0 psi at time t]
     (2-D equation of Sec. 6 with [[d_i]] of eq. (trick); no PML stretch)."""
     p = T.prob
     dx = spectral_derivative(psi, 1, T.xi1)
@@ -488,7 +563,14 @@ def apply_hamiltonian(psi: np.ndarray, T: Tables) -> np.ndarray:
                                  + apply_pointwise(np.broadcast_to(SIGMA_Y, psi.shape[:2] + (2, 2)), dy))
     spin = -0.5j * ca[..., None, None] * (T.chi_x[..., None, None] * SIGMA_X + T.chi_y[..., None, None] * SIGMA_Y)
     mass = (np.exp(T.fields.phi) * p.m * p.c * p.c)[..., None, None] * SIGMA_Z
-    return out + apply_pointwise(spin + mass, psi)
+    pot = spin + mass
+    if p.em is not None:
+        em = p.em
+        fa, fv = em.fA(t), em.fV(t)
+        pot = pot - (em.charge * ca * fa)[..., None, None] * (em.Ax[..., None, None] * SIGMA_X
+                                                              + em.Ay[..., None, None] * SIGMA_Y)
+        pot = pot - (em.charge * em.V * fv)[..., None, None] * ID2
+    return out + apply_pointwise(pot, psi)
 
 
 @dataclass
@@ -502,14 +584,16 @@ class Observables:
     finite: bool
 
 
-def observables(psi: np.ndarray, T: Tables) -> Observables:
+def observables(psi: np.ndarray, T: Tables, t: float = 0.0) -> Observables:
+    """Norms, weighted energy <psi, H(t) psi>_w and mean position (t enters only
+    through time-dependent potentials)."""
     dens = np.sum(np.abs(psi) ** 2, axis=2)
     dA = T.h1 * T.h2
     w = weight(T)
     finite = bool(np.all(np.isfinite(psi)))
     X, Y = np.meshgrid(T.x, T.y)
     n2 = dA * dens.sum()
-    en = dA * np.sum(w * np.sum(np.conj(psi) * apply_hamiltonian(psi, T), axis=2))
+    en = dA * np.sum(w * np.sum(np.conj(psi) * apply_hamiltonian(psi, T, t), axis=2))
     return Observables(float(n2), float(dA * np.sum(w * dens)), float(en.real), float(en.imag),
                        float(np.sum(X * dens) / dens.sum()), float(np.sum(Y * dens) / dens.sum()), finite)
 
@@ -617,18 +701,19 @@ def cn_solve(rhs: np.ndarray, T: Tables, x0: np.ndarray | None = None, rtol: flo
     return x.reshape(shape)
 
 
-def cn_step(psi: np.ndarray, T: Tables, rtol: float = 1e-14) -> np.ndarray:
-    """One step of Scheme I, eq. (cn): Step 1 (E), G psi* = G~ psi^{n+1/2}, Step 3 (E)."""
-    half = apply_pointwise(T.E, psi)
+def cn_step(psi: np.ndarray, T: Tables, rtol: float = 1e-14, n: int = 0) -> np.ndarray:
+    """Step n of Scheme I, eq. (cn): Step 1 (E), G psi* = G~ psi^{n+1/2}, Step 3 (E)."""
+    E = step_exponential(T, n)
+    half = apply_pointwise(E, psi)
     _, Gt = cn_operators(T)
     star = cn_solve(Gt(half), T, x0=half, rtol=rtol)
-    return apply_pointwise(T.E, star)
+    return apply_pointwise(E, star)
 
 
-def cn_run(psi0: np.ndarray, T: Tables, nsteps: int, rtol: float = 1e-14) -> np.ndarray:
+def cn_run(psi0: np.ndarray, T: Tables, nsteps: int, rtol: float = 1e-14, start: int = 0) -> np.ndarray:
     psi = np.array(psi0, dtype=np.complex128, copy=True)
-    for _ in range(nsteps):
-        psi = cn_step(psi, T, rtol)
+    for n in range(start, start + nsteps):
+        psi = cn_step(psi, T, rtol, n)
     return psi
 
 

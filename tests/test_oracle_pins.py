@@ -629,3 +629,98 @@ def test_step2bis_time_order():
     p, psi0 = _x_only_problem(O.STEP2_PLAIN, t / 256)
     cn = O.cn_run(psi0, O.build_tables(p), 256)
     assert O.rel_l2(fine[O.STEP2BIS_CORRECTED], cn) < 0.1 * O.rel_l2(fine[O.STEP2_PLAIN], cn)
+
+
+# --- electromagnetic potentials in F(t, x) (Sec. 2) ----------------------------------
+
+def _em_fields(n1, n2, a1, a2, seed):
+    x, y = O.grid_points(n1, a1), O.grid_points(n2, a2)
+    X, Y = np.meshgrid(x, y)
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.2, 1.0, 4)
+    return (c[0] * np.exp(-(X ** 2 + Y ** 2) / 8.0), c[1] * np.tanh(Y / 3.0), c[2] * np.sin(X / 2.0) + c[3])
+
+
+@pytest.mark.parametrize("spin,t", [(O.SPIN_PAPER, 0.0), (O.SPIN_2P1, 0.37), (O.SPIN_NONE, 1.1)])
+def test_em_half_step_exponential_matches_expm(spin, t):
+    n1, n2, a1, a2, c, m, dt, e = 8, 6, 4.0, 3.0, 1.3, 0.7, 0.2, 1.7
+    V, Ax, Ay = _em_fields(n1, n2, a1, a2, 3)
+    em = O.EMPotentials(V, Ax, Ay, e, O.Envelope(0.5, 1.0, 2.0, 0.3), O.Envelope(-0.2, 2.0, 3.0, 0.0, 0.5, 0.8))
+    x, y = O.grid_points(n1, a1), O.grid_points(n2, a2)
+    f = O.metric_fields(O.METRIC_PAPER_EXP3, x, y)
+    E = O.half_step_exponential_em(f, spin, m, c, dt, em, t)
+    chi_x, chi_y, _ = O.spin_potential(spin, f)
+    fv = 0.5 + 1.0 * math.sin(2.0 * t + 0.3)
+    fa = -0.2 + 2.0 * math.sin(3.0 * t) * math.exp(-((t - 0.5) / 0.8) ** 2)
+    for j in range(n2):
+        for i in range(n1):
+            a = math.exp(f.phi[j, i] - f.psi[j, i])
+            F = (-0.5j * c * a * (chi_x[j, i] * O.SIGMA_X + chi_y[j, i] * O.SIGMA_Y)
+                 - e * c * a * fa * (Ax[j, i] * O.SIGMA_X + Ay[j, i] * O.SIGMA_Y) - e * V[j, i] * fv * O.ID2)
+            M = math.exp(f.phi[j, i]) * m * c * c * O.SIGMA_Z + F
+            assert np.allclose(E[j, i], scipy.linalg.expm(-0.5j * dt * M), atol=1e-14, rtol=0)
+
+
+def test_em_uniform_scalar_potential_is_a_global_phase():
+    # A0 = V0 fV(t), uniform: every step multiplies by e^{i e V0 fV(t_{n+1/2}) dt}
+    spec = W.curved_bump(n=32, steps=7, m=1.0)
+    V0, e = 0.8, 1.3
+    env = O.Envelope(0.3, 1.0, 5.0, 0.2, 0.03, 0.05)
+    z = np.zeros((32, 32))
+    p0 = oracle_problem(spec)
+    p1 = oracle_problem(spec)
+    p1.em = O.EMPotentials(np.full((32, 32), V0), z, z, e, env, O.Envelope())
+    psi0 = W.initial_spinor(spec)
+    out0 = O.run(psi0, O.build_tables(p0), 7, start=2)
+    out1 = O.run(psi0, O.build_tables(p1), 7, start=2)
+    ph = sum(env((n + 0.5) * spec.dt) for n in range(2, 9)) * spec.dt * e * V0
+    assert O.rel_l2(out1, np.exp(1j * ph) * out0) < 1e-13
+
+
+def test_em_uniform_vector_potential_is_a_discrete_gauge_shift():
+    # flat, m = 0, data constant in y, uniform A_x with e A_x = k pi / a: the
+    # scheme maps e^{i e A x} psi to e^{i e A x} (free scheme of psi) exactly,
+    # as long as the shifted modes do not wrap past the Nyquist index
+    n1, n2, a, c, dt, e = 64, 16, 6.0, 1.0, 0.05, 0.5
+    k = 5
+    A = k * math.pi / a / e
+    x = O.grid_points(n1, a)
+    rng = np.random.default_rng(8)
+    P = np.zeros((n1, 2), complex)
+    for q in list(range(0, 8)) + list(range(n1 - 7, n1)):
+        P[q] = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+    line = np.fft.ifft(P, axis=0)
+    psi0 = np.broadcast_to(line[None, :, :], (n2, n1, 2)).copy()
+    free = O.Problem(n1=n1, n2=n2, a1=a, a2=a, dt=dt, c=c, m=0.0)
+    z = np.zeros((n2, n1))
+    gauged = O.Problem(n1=n1, n2=n2, a1=a, a2=a, dt=dt, c=c, m=0.0,
+                       em=O.EMPotentials(z, np.full((n2, n1), A), z, e))
+    phase = np.exp(1j * e * A * x)[None, :, None]
+    out0 = O.run(psi0, O.build_tables(free), 9)
+    out1 = O.run(phase * psi0, O.build_tables(gauged), 9)
+    assert O.rel_l2(out1, phase * out0) < 1e-13
+    # with the opposite sign of the coupling the identity fails
+    wrong = O.Problem(n1=n1, n2=n2, a1=a, a2=a, dt=dt, c=c, m=0.0,
+                      em=O.EMPotentials(z, np.full((n2, n1), -A), z, e))
+    assert O.rel_l2(O.run(phase * psi0, O.build_tables(wrong), 9), phase * out0) > 1e-2
+
+
+def test_em_energy_of_plane_wave_eigenstates():
+    # flat, m = 0: e^{i xi x} (1, s) with uniform A_x, V0 has energy
+    # s c (xi - e A fA(t)) - e V0 fV(t) per unit weighted norm
+    n1, n2, a, c, e = 32, 8, 5.0, 1.2, 0.7
+    A, V0, t = 0.4, -0.9, 0.25
+    envA, envV = O.Envelope(0.5, 1.0, 2.0, 0.0), O.Envelope(1.0, 0.5, 1.0, 0.4)
+    z = np.zeros((n2, n1))
+    p = O.Problem(n1=n1, n2=n2, a1=a, a2=a, dt=0.01, c=c, m=0.0,
+                  em=O.EMPotentials(np.full((n2, n1), V0), np.full((n2, n1), A), z, e, envV, envA))
+    T = O.build_tables(p)
+    x = O.grid_points(n1, a)
+    for q, s in ((3, 1), (-4, -1)):
+        xi = q * math.pi / a
+        psi = np.zeros((n2, n1, 2), complex)
+        psi[..., 0] = np.exp(1j * xi * x)[None, :]
+        psi[..., 1] = s * psi[..., 0]
+        ob = O.observables(psi, T, t)
+        lam = s * c * (xi - e * A * envA(t)) - e * V0 * envV(t)
+        assert abs(ob.energy_re / ob.norm_w - lam) < 1e-12 and abs(ob.energy_im) < 1e-12
