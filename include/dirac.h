@@ -169,13 +169,40 @@ dirac_status dirac_create_metric(const dirac_grid* grid, const dirac_metric* met
                                  void* device_buffer, size_t bytes, void* hip_stream,
                                  dirac_solver** out);
 
+/* Time profile of a potential: f(t) = c0 + c1 sin(omega t + phase) g(t) with
+ * g(t) = exp(-((t - t0) / tau)^2) for tau > 0, else g = 1. */
+typedef struct {
+    double c0, c1, omega, phase, t0, tau;
+} dirac_envelope;
+
+/* Electromagnetic potentials in F(t, x) (Sec. 2, the Hamiltonian with A and A0):
+ * A0(t, x) = V(x) fV(t) and A_i(t, x) = A_i(x) fA(t).  In the conformal 2-D form
+ * they add -e c a (A_x sigma_x + A_y sigma_y) - e A0 to beta m + F, so the Step 1 /
+ * Step 5 exponential of step n is evaluated at t_{n+1/2} = (n + 1/2) dt
+ * (eqs. (step1), (step3)), per point inside the direction kernels.  V, Ax, Ay are
+ * host arrays [n2][n1] of doubles (NULL = 0), copied during creation; the step
+ * index n counts from the last dirac_set_initial_spinor.  Schemes: the plain and
+ * printed directional steps and Scheme I; n1, n2 <= 2048. */
+typedef struct {
+    const double* V;
+    const double* Ax;
+    const double* Ay;
+    double charge;           /* e */
+    dirac_envelope fV;       /* time profile of A0 */
+    dirac_envelope fA;       /* time profile of (A_x, A_y) */
+} dirac_em;
+
 /* Footprint and creation with an explicit time integrator (scheme NULL = the
- * default Scheme II); dirac_create_metric(...) = dirac_create_solver(..., NULL, ...). */
+ * default Scheme II) and optional electromagnetic potentials (em NULL = none);
+ * dirac_create_metric(...) = dirac_create_solver(..., NULL, NULL, ...) and
+ * dirac_footprint_bytes_scheme(..., sc) = dirac_footprint_bytes_ex(..., sc, NULL). */
 size_t dirac_footprint_bytes_scheme(const dirac_grid* grid, const dirac_metric* metric, const dirac_pml* pml,
                                     int32_t precision, const dirac_scheme* scheme);
+size_t dirac_footprint_bytes_ex(const dirac_grid* grid, const dirac_metric* metric, const dirac_pml* pml,
+                                int32_t precision, const dirac_scheme* scheme, const dirac_em* em);
 dirac_status dirac_create_solver(const dirac_grid* grid, const dirac_metric* metric, const dirac_pml* pml,
-                                 int32_t precision, const dirac_scheme* scheme, void* device_buffer,
-                                 size_t bytes, void* hip_stream, dirac_solver** out);
+                                 int32_t precision, const dirac_scheme* scheme, const dirac_em* em,
+                                 void* device_buffer, size_t bytes, void* hip_stream, dirac_solver** out);
 
 /* Scheme I statistics since creation: total GMRES iterations, and the relative
  * residual reached by the last solve. */

@@ -142,6 +142,7 @@ dirac_status dirac_batch_create(int32_t prec, int32_t capacity, void* device_buf
 dirac_status dirac_batch_add(dirac_batch* b, dirac_solver* s, int32_t* slot_out) {
     if (!b || !s || !slot_out) return fail(DIRAC_E_ARG, "null argument");
     if (s->prec != b->prec) return fail(DIRAC_E_ARG, "solver precision differs from the batch");
+    if (s->has_em) return fail(DIRAC_E_ARG, "batches run solves without time-dependent potentials only");
     if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS)
         return fail(DIRAC_E_ARG, "batches run Scheme II solves with the plain or printed directional step only");
     if (s->g.n1 > 2048 || s->g.n2 > 2048) return fail(DIRAC_E_SIZE, "batched solves need n1, n2 <= 2048");

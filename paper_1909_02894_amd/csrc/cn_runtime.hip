@@ -20,6 +20,7 @@
 
 #include "../../include/dirac.h"
 #include "cn_kernels.hpp"
+#include "em_kernels.hpp"
 #include "solver.hpp"
 
 namespace dirac {
@@ -190,9 +191,25 @@ dirac_status cn_step_n(dirac_solver* s, int64_t nsteps) {
     c.h = 0.5 * s->g.dt * s->g.c;
     const double* E = s->curved ? reinterpret_cast<const double*>(b + s->lay.E) : nullptr;
     std::vector<double> host(3 * 128);
+    // Step 3 of the previous step, then Step 1 of this one (one application when
+    // the step opens the call, or Step 3 alone after the last step); with
+    // time-dependent potentials the two use t_{n-1/2} and t_{n+1/2}
+    auto exp_steps = [&](int64_t n_abs, int times, bool closing) -> hipError_t {
+        if (!s->has_em) return launch_cn_exp(c.psi, E, s->e0u_re, s->e0u_im, c.npts, times, c.st);
+        const double dt = s->g.dt;
+        double t[2];
+        if (closing) t[0] = (n_abs + 0.5) * dt;
+        else if (times == 2) { t[0] = (n_abs - 0.5) * dt; t[1] = (n_abs + 0.5) * dt; }
+        else t[0] = (n_abs + 0.5) * dt;
+        double fA[2] = {0, 0}, fV[2] = {0, 0};
+        for (int k = 0; k < times; ++k) {
+            fA[k] = envelope_at(s->env_A, t[k]);
+            fV[k] = envelope_at(s->env_V, t[k]);
+        }
+        return launch_em_exp(c.psi, reinterpret_cast<const double*>(b + s->lay.em), c.npts, times, fA, fV, c.st);
+    };
     for (int64_t n = 0; n < nsteps; ++n) {
-        // Step 3 of the previous step and Step 1 of this one are the same constant E
-        CN_TRY(launch_cn_exp(c.psi, E, s->e0u_re, s->e0u_im, c.npts, n == 0 ? 1 : 2, c.st), "Step 1");
+        CN_TRY(exp_steps(s->step, n == 0 ? 1 : 2, false), "Step 1");
         CN_TRY(apply_G(c, c.psi, c.rhs, -1.0), "apply G~");
         CN_TRY(norm2_dev(c, c.rhs, 2), "right-hand side norm");
         dirac_status r = read_coef(c, host.data(), 3 * 128);
@@ -202,7 +219,7 @@ dirac_status cn_step_n(dirac_solver* s, int64_t nsteps) {
         if (r != DIRAC_OK) return r;
         s->step += 1;
     }
-    CN_TRY(launch_cn_exp(c.psi, E, s->e0u_re, s->e0u_im, c.npts, 1, c.st), "Step 3");
+    CN_TRY(exp_steps(s->step - 1, 1, true), "Step 3");
     CN_TRY(hipStreamSynchronize(c.st), "synchronise");
     return DIRAC_OK;
 }

@@ -1,0 +1,193 @@
+// em_kernels.hpp -- direction kernels for solves with time-dependent
+// electromagnetic potentials (Sec. 2: F(t, x) with A and A0).  The directional
+// step is that of eq. (second_scheme); the Step 1 / Step 5 exponential is built
+// per point inside the kernel for the time of the step instead of being read
+// from a table:
+//   E(t) = e^{i (dt/2) e A0} (C I + D u.sigma),  u.u = r^2,  C = cosh r,  D = sinh r / r,
+//   u = (sx + i qx fA(t), sy + i qy fA(t), -i wz),
+// from a per-point record (sx, sy, wz, qx, qy, q0, a, 0):
+//   sx = -(dt/4) c a chi_x, sy = -(dt/4) c a chi_y, wz = (dt/2) m c^2 e^Phi,
+//   qx = (dt/2) e c a A_x(x), qy = (dt/2) e c a A_y(x), q0 = (dt/2) e V(x).
+// E is evaluated in FP64 and rounded to the state precision.
+#pragma once
+#include "stage_kernels.hpp"
+
+namespace dirac {
+
+template <typename T>
+struct EmParams {
+    StageParams<T> s;            // psi, inv_s, K, tw, n1, nlines, e_pre, e_post (a, E, e0u unused)
+    const T* rec;                // 8 T per point
+    double fA[3], fV[3];         // envelope values: Step-1 applications in order, then Step 5
+};
+
+struct EmEntry {
+    int prec, n, dir, lines, nthreads;
+    const void* fn;
+};
+
+__host__ __device__ constexpr int em_radix(int n) { return n <= 64 ? 4 : 8; }
+__host__ __device__ constexpr int em_lines(int n) { return (n / em_radix(n)) >= 256 ? 1 : 256 / (n / em_radix(n)); }
+__host__ __device__ constexpr int em_threads(int n) { return (n / em_radix(n)) * em_lines(n); }
+
+const EmEntry* em_entry(int prec, int n, int dir);
+hipError_t launch_em_exp(double* psi, const double* rec, size_t npts, int times, const double* fA, const double* fV,
+                         hipStream_t s);
+
+struct Mat2 {
+    cpx<double> m00, m01, m10, m11;
+};
+
+__device__ __forceinline__ cpx<double> cmul_d(cpx<double> a, cpx<double> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// Principal square root, in the cancellation-free form.
+__device__ __forceinline__ cpx<double> csqrt_d(cpx<double> z) {
+    const double r = hypot(z.re, z.im);
+    if (z.re >= 0) {
+        const double t = sqrt(0.5 * (r + z.re));
+        return {t, t > 0 ? 0.5 * z.im / t : 0.0};
+    }
+    const double t = sqrt(0.5 * (r - z.re));
+    return {0.5 * fabs(z.im) / t, copysign(t, z.im)};
+}
+
+__device__ __forceinline__ Mat2 em_exponential(const double (&q)[6], double fA, double fV) {
+    const cpx<double> ux{q[0], q[3] * fA}, uy{q[1], q[4] * fA}, uz{0.0, -q[2]};
+    const cpx<double> s2 = cmul_d(ux, ux) + cmul_d(uy, uy) + cmul_d(uz, uz);
+    cpx<double> C, D;
+    if (hypot(s2.re, s2.im) < 1e-8) {
+        const cpx<double> s4 = cmul_d(s2, s2);
+        C = cpx<double>{1.0 + s2.re / 2.0 + s4.re / 24.0, s2.im / 2.0 + s4.im / 24.0};
+        D = cpx<double>{1.0 + s2.re / 6.0 + s4.re / 120.0, s2.im / 6.0 + s4.im / 120.0};
+    } else {
+        const cpx<double> r = csqrt_d(s2);
+        double sn, cs;
+        sincos(r.im, &sn, &cs);
+        const double ep = exp(r.re), em = exp(-r.re);
+        const cpx<double> epr{ep * cs, ep * sn}, emr{em * cs, -em * sn};   // e^{r}, e^{-r}
+        C = cpx<double>{0.5 * (epr.re + emr.re), 0.5 * (epr.im + emr.im)};
+        const cpx<double> sh{0.5 * (epr.re - emr.re), 0.5 * (epr.im - emr.im)};
+        const double den = r.re * r.re + r.im * r.im;                    // sinh r / r
+        D = cpx<double>{(sh.re * r.re + sh.im * r.im) / den, (sh.im * r.re - sh.re * r.im) / den};
+    }
+    double ps, pc;
+    sincos(q[5] * fV, &ps, &pc);
+    const cpx<double> ph{pc, ps};
+    const cpx<double> Duz = cmul_d(D, uz);
+    const cpx<double> a = cpx<double>{ux.re + uy.im, ux.im - uy.re};            // ux - i uy
+    const cpx<double> b = cpx<double>{ux.re - uy.im, ux.im + uy.re};            // ux + i uy
+    Mat2 m;
+    m.m00 = cmul_d(ph, C + Duz);
+    m.m01 = cmul_d(ph, cmul_d(D, a));
+    m.m10 = cmul_d(ph, cmul_d(D, b));
+    m.m11 = cmul_d(ph, cpx<double>{C.re - Duz.re, C.im - Duz.im});
+    return m;
+}
+
+// Point record: 8 T (64 B FP64 / 32 B FP32), read with 16-byte loads.
+template <typename T>
+__device__ __forceinline__ void load_record(const T* rec, uint32_t idx, double (&q)[6], double& a) {
+    const char* b = reinterpret_cast<const char*>(rec) + idx * (uint32_t)(8 * sizeof(T));
+    if constexpr (sizeof(T) == 8) {
+        const double2 r0 = reinterpret_cast<const double2*>(b)[0], r1 = reinterpret_cast<const double2*>(b)[1];
+        const double2 r2 = reinterpret_cast<const double2*>(b)[2], r3 = reinterpret_cast<const double2*>(b)[3];
+        q[0] = r0.x; q[1] = r0.y; q[2] = r1.x; q[3] = r1.y; q[4] = r2.x; q[5] = r2.y; a = r3.x;
+    } else {
+        const float4 r0 = reinterpret_cast<const float4*>(b)[0], r1 = reinterpret_cast<const float4*>(b)[1];
+        q[0] = r0.x; q[1] = r0.y; q[2] = r0.z; q[3] = r0.w; q[4] = r1.x; q[5] = r1.y; a = r1.z;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void apply_mat(const Mat2& m, cpx<T>& u, cpx<T>& v) {
+    const cpx<T> m00{(T)m.m00.re, (T)m.m00.im}, m01{(T)m.m01.re, (T)m.m01.im};
+    const cpx<T> m10{(T)m.m10.re, (T)m.m10.im}, m11{(T)m.m11.re, (T)m.m11.im};
+    const cpx<T> nu = cmul(m00, u) + cmul(m01, v);
+    const cpx<T> nv = cmul(m10, u) + cmul(m11, v);
+    u = nu;
+    v = nv;
+}
+
+template <typename T, int N, bool COLS>
+__global__ void __launch_bounds__(em_threads(N)) em_stage_kernel(EmParams<T> ep) {
+    constexpr int R = em_radix(N), L = em_lines(N);
+    using F = LineFFT<T, N, R, L, COLS, 2>;
+    using TS = TwStage<T, N>;
+    constexpr int P = F::P;
+    __shared__ cpx<T> lds[F::LDS_ELEMS];
+    __shared__ cpx<T> twl[TS::ELEMS];
+    const StageParams<T>& p = ep.s;
+    const typename F::Coord c = F::coord(threadIdx.x);
+    const int line = xcd_tile(blockIdx.x, gridDim.x) * L + c.l;
+    const bool valid = line < p.nlines;
+    const uint32_t n1 = (uint32_t)p.n1;
+    auto gidx = [&](int pos) -> uint32_t { return COLS ? (uint32_t)pos * n1 + line : (uint32_t)line * n1 + pos; };
+
+    cpx<T> v[2][R], old[2][R];
+    T b[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        v[0][r] = v[1][r] = cpx<T>{0, 0};
+        const int pos = c.j + r * P;
+        double q[6] = {0, 0, 0, 0, 0, 0}, a = 0.0;
+        if (valid) {
+            load_point(p.psi, gidx(pos), v[0][r], v[1][r]);
+            load_record(ep.rec, gidx(pos), q, a);
+        }
+        for (int k = 0; k < p.e_pre; ++k) apply_mat(em_exponential(q, ep.fA[k], ep.fV[k]), v[0][r], v[1][r]);
+        b[r] = (T)a * (p.inv_s ? p.inv_s[pos] : T(1));
+        old[0][r] = v[0][r];
+        old[1][r] = v[1][r];
+    }
+    const cpx<T>* tw = p.tw;
+    if constexpr (TS::ON) {
+        for (int k = threadIdx.x; k < N; k += F::NT) twl[k] = p.tw[k];
+        tw = twl;
+    }
+    F::template fft<false>(v, lds, c, tw);
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+        const cpx<T> k = p.K[c.j + s * P];
+        const cpx<T> a0 = v[0][s], a1 = v[1][s];
+        if constexpr (!COLS) {                 // K_x = cos I - i sin sigma_x
+            v[0][s] = scal(k.re, a0) + mul_mi(scal(k.im, a1));
+            v[1][s] = scal(k.re, a1) + mul_mi(scal(k.im, a0));
+        } else {                               // K_y = [[cos, -sin], [sin, cos]]
+            v[0][s] = scal(k.re, a0) - scal(k.im, a1);
+            v[1][s] = scal(k.re, a1) + scal(k.im, a0);
+        }
+    }
+    F::template fft<true>(v, lds, c, tw);
+    if (!valid) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t g = gidx(c.j + r * P);
+        cpx<T> u = scal(b[r], v[0][r]) + scal(T(1) - b[r], old[0][r]);
+        cpx<T> w = scal(b[r], v[1][r]) + scal(T(1) - b[r], old[1][r]);
+        if (p.e_post) {
+            double q[6], a;
+            load_record(ep.rec, g, q, a);
+            apply_mat(em_exponential(q, ep.fA[2], ep.fV[2]), u, w);
+        }
+        store_point(p.psi, g, u, w);
+    }
+}
+
+// psi <- E(t_k) psi for k < times (Scheme I with potentials), one thread per point.
+template <typename T>
+__global__ void em_exp_kernel(T* psi, const T* rec, size_t npts, int times, double fA0, double fV0, double fA1,
+                              double fV1) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npts) return;
+    cpx<T> u, v;
+    double q[6], a;
+    load_point(psi, (uint32_t)i, u, v);
+    load_record(rec, (uint32_t)i, q, a);
+    if (times > 0) apply_mat(em_exponential(q, fA0, fV0), u, v);
+    if (times > 1) apply_mat(em_exponential(q, fA1, fV1), u, v);
+    store_point(psi, (uint32_t)i, u, v);
+}
+
+}  // namespace dirac

@@ -24,8 +24,25 @@
 #include "stage_kernels.hpp"
 #include "cn_kernels.hpp"
 #include "bis_kernels.hpp"
+#include "em_kernels.hpp"
 
 namespace dirac {
+
+const EmEntry* em_entries_f64(int* count);
+const EmEntry* em_entries_f32(int* count);
+
+const EmEntry* em_entry(int prec, int n, int dir) {
+    int cnt = 0;
+    const EmEntry* e = prec == DIRAC_FP64 ? em_entries_f64(&cnt) : em_entries_f32(&cnt);
+    for (int i = 0; i < cnt; ++i)
+        if (e[i].n == n && e[i].dir == dir) return &e[i];
+    return nullptr;
+}
+
+double envelope_at(const dirac_envelope& e, double t) {
+    const double g = e.tau > 0 ? std::exp(-((t - e.t0) / e.tau) * ((t - e.t0) / e.tau)) : 1.0;
+    return e.c0 + e.c1 * std::sin(e.omega * t + e.phase) * g;
+}
 
 const BisEntry* bis_entries_f64(int* count);
 const BisEntry* bis_entries_f32(int* count);
@@ -80,9 +97,22 @@ dirac_scheme scheme_or_default(const dirac_scheme* sc) {
     return d;
 }
 
+static bool envelope_ok(const dirac_envelope& e) {
+    return std::isfinite(e.c0) && std::isfinite(e.c1) && std::isfinite(e.omega) && std::isfinite(e.phase) &&
+           std::isfinite(e.t0) && std::isfinite(e.tau) && e.tau >= 0;
+}
+
 dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
-                      const dirac_scheme* scp) {
+                      const dirac_scheme* scp, const dirac_em* em) {
     if (!g || !m || !pml) return fail(DIRAC_E_ARG, "null grid, metric or pml");
+    if (em) {
+        if (!std::isfinite(em->charge)) return fail(DIRAC_E_ARG, "charge must be finite");
+        if (!envelope_ok(em->fV) || !envelope_ok(em->fA))
+            return fail(DIRAC_E_ARG, "envelope parameters must be finite with tau >= 0");
+        if (scp && scp->scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS)
+            return fail(DIRAC_E_ARG, "potentials are built for the plain and printed directional steps and Scheme I");
+        if (g->n1 > 2048 || g->n2 > 2048) return fail(DIRAC_E_SIZE, "solves with potentials need n1, n2 <= 2048");
+    }
     const dirac_scheme sc = scheme_or_default(scp);
     if (sc.scheme < DIRAC_SCHEME_EXP_SPLIT || sc.scheme > DIRAC_SCHEME_EXP_SPLIT_2BIS)
         return fail(DIRAC_E_ARG, "unknown scheme %d", sc.scheme);
@@ -138,7 +168,7 @@ dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pm
 }
 
 Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
-                   const dirac_scheme* scp) {
+                   const dirac_scheme* scp, const dirac_em* em) {
     Layout L{};
     const dirac_scheme sc = scheme_or_default(scp);
     const size_t N = (size_t)g->n1 * g->n2;
@@ -150,7 +180,8 @@ Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* 
     L.a = curved ? take(N * sz) : SIZE_MAX;
     L.E = curved ? take(N * 4 * sz) : SIZE_MAX;
     L.da = curved && sc.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS ? take(N * 2 * sz) : SIZE_MAX;
-    L.obs = take(5 * N * 8);
+    L.em = em ? take(N * 8 * sz) : SIZE_MAX;
+    L.obs = take((em ? 8 : 5) * N * 8);
     L.fields = m->kind == DIRAC_METRIC_FIELDS ? take(6 * N * 8) : SIZE_MAX;
     L.scratch = take(N * 4 * 8);
     for (int ax = 0; ax < 2; ++ax) {
@@ -254,16 +285,57 @@ BisParams<T> bis_params(const dirac_solver* s, int dir, int e_pre, int e_post) {
     return p;
 }
 
+template <typename T>
+EmParams<T> em_params(const dirac_solver* s, int dir, int e_pre, int e_post, int64_t step) {
+    EmParams<T> p{};
+    p.s = stage_params<T>(s, dir, e_pre, e_post);
+    p.rec = reinterpret_cast<const T*>(s->base + s->lay.em);
+    // Step 1 of step n (and Step 5 of step n - 1 before it) and Step 5 of step n
+    // evaluate the potentials at t_{n+1/2} (resp. t_{n-1/2})
+    const double dt = s->g.dt;
+    double times[3] = {0, 0, 0};
+    if (e_pre == 2) { times[0] = (step - 0.5) * dt; times[1] = (step + 0.5) * dt; }
+    else if (e_pre == 1) { times[0] = (step + 0.5) * dt; }
+    times[2] = (step + 0.5) * dt;
+    for (int k = 0; k < 3; ++k) {
+        p.fA[k] = envelope_at(s->env_A, times[k]);
+        p.fV[k] = envelope_at(s->env_V, times[k]);
+    }
+    return p;
+}
+
+static constexpr size_t kMaxParams = sizeof(BisParams<double>) > sizeof(EmParams<double>) ? sizeof(BisParams<double>)
+                                                                                          : sizeof(EmParams<double>);
+
 // One stage launch description (kernel + by-value parameter block).
 struct Launch {
     const void* fn;
     dim3 grid, block;
-    alignas(16) unsigned char params[sizeof(BisParams<double>)];
+    alignas(16) unsigned char params[kMaxParams];
     size_t psize;
 };
 
-Launch make_launch(const dirac_solver* s, int dir, int e_pre, int e_post) {
+// `step` is the index of the step the launch belongs to (it fixes the time of
+// the potentials; unused otherwise).
+Launch make_launch(const dirac_solver* s, int dir, int e_pre, int e_post, int64_t step = 0) {
     Launch L{};
+    if (s->has_em) {
+        const int nlines = dir == 0 ? s->g.n2 : s->g.n1;
+        const EmEntry* e = em_entry(s->prec, dir == 0 ? s->g.n1 : s->g.n2, dir);
+        L.fn = e->fn;
+        L.grid = dim3((nlines + e->lines - 1) / e->lines);
+        L.block = dim3(e->nthreads);
+        if (s->prec == DIRAC_FP64) {
+            auto p = em_params<double>(s, dir, e_pre, e_post, step);
+            std::memcpy(L.params, &p, sizeof p);
+            L.psize = sizeof p;
+        } else {
+            auto p = em_params<float>(s, dir, e_pre, e_post, step);
+            std::memcpy(L.params, &p, sizeof p);
+            L.psize = sizeof p;
+        }
+        return L;
+    }
     if (s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS && (s->curved || s->pml)) {
         // second-order directional step (b = 1 everywhere makes it the plain step)
         const int nlines = dir == 0 ? s->g.n2 : s->g.n1;
@@ -340,6 +412,17 @@ static dirac_status build_graph(dirac_solver* s) {
 dirac_status enqueue_steps(dirac_solver* s, int64_t nsteps, bool allow_graph) {
     if (nsteps <= 0) return DIRAC_OK;
     hipStream_t st = s->stream;
+    if (s->has_em) {
+        // the potentials' time enters every launch's parameters: direct launches
+        const int64_t n0 = s->step;
+        for (int64_t k = 0; k < nsteps; ++k) {
+            Launch lx = make_launch(s, 0, k == 0 ? 1 : 2, 0, n0 + k);
+            Launch ly = make_launch(s, 1, 0, k == nsteps - 1 ? 1 : 0, n0 + k);
+            HIP_TRY(do_launch(lx, st), "launch x stage");
+            HIP_TRY(do_launch(ly, st), "launch y stage");
+        }
+        return DIRAC_OK;
+    }
     Launch x1 = make_launch(s, 0, 1, 0);
     HIP_TRY(do_launch(x1, st), "launch x stage");
     int64_t middle = nsteps - 1;     // number of (y, x(E E)) pairs
@@ -382,14 +465,19 @@ size_t dirac_footprint_bytes(const dirac_grid* g, const dirac_metric* m, const d
 
 size_t dirac_footprint_bytes_scheme(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
                                     const dirac_scheme* sc) {
-    if (validate(g, m, pml, prec, sc) != DIRAC_OK) return 0;
-    return make_layout(g, m, pml, prec, sc).total;
+    return dirac_footprint_bytes_ex(g, m, pml, prec, sc, nullptr);
+}
+
+size_t dirac_footprint_bytes_ex(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
+                                const dirac_scheme* sc, const dirac_em* em) {
+    if (validate(g, m, pml, prec, sc, em) != DIRAC_OK) return 0;
+    return make_layout(g, m, pml, prec, sc, em).total;
 }
 
 dirac_status dirac_create_metric(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml,
                                  int32_t prec, void* device_buffer, size_t bytes, void* hip_stream,
                                  dirac_solver** out) {
-    return dirac_create_solver(g, m, pml, prec, nullptr, device_buffer, bytes, hip_stream, out);
+    return dirac_create_solver(g, m, pml, prec, nullptr, nullptr, device_buffer, bytes, hip_stream, out);
 }
 
 dirac_status dirac_cn_stats(const dirac_solver* s, int64_t* iterations, double* last_rel_residual) {
@@ -400,16 +488,16 @@ dirac_status dirac_cn_stats(const dirac_solver* s, int64_t* iterations, double* 
 }
 
 dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml,
-                                 int32_t prec, const dirac_scheme* scp, void* device_buffer, size_t bytes,
-                                 void* hip_stream, dirac_solver** out) {
+                                 int32_t prec, const dirac_scheme* scp, const dirac_em* em, void* device_buffer,
+                                 size_t bytes, void* hip_stream, dirac_solver** out) {
     g_last_error.clear();
     if (!out) return fail(DIRAC_E_ARG, "null output handle");
     *out = nullptr;
-    dirac_status st = validate(g, m, pml, prec, scp);
+    dirac_status st = validate(g, m, pml, prec, scp, em);
     if (st != DIRAC_OK) return st;
     if (!device_buffer) return fail(DIRAC_E_ARG, "null device buffer");
     const dirac_scheme sc = scheme_or_default(scp);
-    Layout lay = make_layout(g, m, pml, prec, scp);
+    Layout lay = make_layout(g, m, pml, prec, scp, em);
     if (bytes < lay.total)
         return fail(DIRAC_E_SIZE, "device buffer of %zu bytes < footprint %zu", bytes, lay.total);
     for (int dir = 0; dir < 2; ++dir) {
@@ -431,6 +519,12 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
     s->pmlp = *pml;
     s->prec = prec;
     s->scheme = sc;
+    if (em) {
+        s->has_em = true;
+        s->em_charge = em->charge;
+        s->env_V = em->fV;
+        s->env_A = em->fA;
+    }
     s->stream = static_cast<hipStream_t>(hip_stream);
     const uintptr_t raw = reinterpret_cast<uintptr_t>(device_buffer);
     s->base = reinterpret_cast<char*>((raw + 255) & ~uintptr_t(255));
@@ -451,6 +545,16 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
         for (int k = 0; k < 6; ++k) {
             hipError_t e = hipMemcpyAsync(b + lay.fields + k * N * 8, planes[k], N * 8, hipMemcpyHostToDevice, s->stream);
             if (e != hipSuccess) return bail(hip_fail(e, "upload metric fields"));
+        }
+    }
+    if (em) {
+        // potential profiles staged as FP64 planes in the scratch area
+        const double* planes[3] = {em->V, em->Ax, em->Ay};
+        for (int k = 0; k < 3; ++k) {
+            char* dst = b + lay.scratch + k * N * 8;
+            hipError_t e = planes[k] ? hipMemcpyAsync(dst, planes[k], N * 8, hipMemcpyHostToDevice, s->stream)
+                                     : hipMemsetAsync(dst, 0, N * 8, s->stream);
+            if (e != hipSuccess) return bail(hip_fail(e, "upload potentials"));
         }
     }
     for (int ax = 0; ax < 2; ++ax) {
@@ -483,6 +587,10 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
     pp.a_out = s->curved ? b + lay.a : nullptr;
     pp.E_out = s->curved ? b + lay.E : nullptr;
     pp.da_out = lay.da != SIZE_MAX ? b + lay.da : nullptr;
+    pp.em_planes = em ? reinterpret_cast<const double*>(b + lay.scratch) : nullptr;
+    pp.charge = em ? em->charge : 0.0;
+    pp.em_out = em ? b + lay.em : nullptr;
+    pp.obs_em = em ? reinterpret_cast<double*>(b + lay.obs) + 5 * N : nullptr;
     pp.obs = reinterpret_cast<double*>(b + lay.obs);
     pp.partial = reinterpret_cast<double*>(b + lay.partials);
     double* fold = reinterpret_cast<double*>(b + lay.out);
@@ -562,6 +670,12 @@ dirac_status dirac_observables(dirac_solver* s, dirac_obs* out) {
     p.psi = b + s->lay.psi;
     const double* obs = reinterpret_cast<const double*>(b + s->lay.obs);
     p.w = obs; p.ca = obs + N; p.gx = obs + 2 * N; p.gy = obs + 3 * N; p.V = obs + 4 * N;
+    if (s->has_em) {
+        const double t = s->step * s->g.dt;
+        p.ax = obs + 5 * N; p.ay = obs + 6 * N; p.v0 = obs + 7 * N;
+        p.fA = envelope_at(s->env_A, t);
+        p.fV = envelope_at(s->env_V, t);
+    }
     p.n1 = s->g.n1; p.n2 = s->g.n2;
     p.a1 = s->g.a1; p.a2 = s->g.a2;
     p.h1 = 2.0 * s->g.a1 / s->g.n1; p.h2 = 2.0 * s->g.a2 / s->g.n2;
@@ -694,8 +808,8 @@ dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
     hipStream_t st = s->stream;
     size_t k = 0;
     for (int64_t n = 0; n < nsteps; ++n) {
-        Launch lx = make_launch(s, 0, n == 0 ? 1 : 2, 0);
-        Launch ly = make_launch(s, 1, 0, n == nsteps - 1 ? 1 : 0);
+        Launch lx = make_launch(s, 0, n == 0 ? 1 : 2, 0, s->step + n);
+        Launch ly = make_launch(s, 1, 0, n == nsteps - 1 ? 1 : 0, s->step + n);
         for (Launch* L : {&lx, &ly}) {
             void* args[] = {L->params};
             HIP_TRY(hipExtLaunchKernel(L->fn, L->grid, L->block, args, 0, st, s->events[2 * k],
@@ -728,7 +842,7 @@ dirac_status dirac_time_directions(dirac_solver* s, int32_t reps, double* us_out
     if (hipEventCreate(&ev[1]) != hipSuccess) { (void)hipEventDestroy(ev[0]); return fail(DIRAC_E_DEVICE, "hipEventCreate"); }
     dirac_status result = DIRAC_OK;
     for (int dir = 0; dir < 2 && result == DIRAC_OK; ++dir) {
-        Launch L = make_launch(s, dir, dir == 0 ? 2 : 0, 0);
+        Launch L = make_launch(s, dir, dir == 0 ? 2 : 0, 0, s->step);
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         auto step = [&]() -> dirac_status {
@@ -770,8 +884,9 @@ dirac_status dirac_time_directions(dirac_solver* s, int32_t reps, double* us_out
 
 dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
     if (!s || reps < 1) return fail(DIRAC_E_ARG, "bad arguments");
-    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS)
-        return fail(DIRAC_E_ARG, "schedules apply to Scheme II's plain and printed directional steps only");
+    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || s->has_em)
+        return fail(DIRAC_E_ARG, "schedules apply to Scheme II's plain and printed directional steps without "
+                                 "potentials only");
     if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
     const size_t N = (size_t)s->g.n1 * s->g.n2;
     const size_t bytes = N * 4 * (s->prec == DIRAC_FP32 ? 4 : 8);

@@ -139,6 +139,25 @@ __global__ void setup_point_kernel(SetupPointParams p) {
         if (p.a_out) {
             if (p.fp32) put<float>(p.a_out, q, a); else put<double>(p.a_out, q, a);
         }
+        double emv = 0.0, emx = 0.0, emy = 0.0;
+        if (p.em_planes) {
+            emv = p.em_planes[q];
+            emx = p.em_planes[N + q];
+            emy = p.em_planes[2 * N + q];
+        }
+        if (p.em_out) {
+            // record for the in-kernel exponential with potentials (e = charge)
+            const double rec[8] = {ux, uy, wz, (p.dt / 2.0) * p.charge * p.c * a * emx,
+                                   (p.dt / 2.0) * p.charge * p.c * a * emy, (p.dt / 2.0) * p.charge * emv, a, 0.0};
+            for (int k = 0; k < 8; ++k) {
+                if (p.fp32) put<float>(p.em_out, 8 * q + k, rec[k]); else put<double>(p.em_out, 8 * q + k, rec[k]);
+            }
+        }
+        if (p.obs_em) {
+            p.obs_em[q] = p.charge * p.c * a * emx;
+            p.obs_em[N + q] = p.charge * p.c * a * emy;
+            p.obs_em[2 * N + q] = p.charge * emv;
+        }
         if (p.da_out) {
             const double dax = a * (f.phix - f.psix), day = a * (f.phiy - f.psiy);
             if (p.fp32) { put<float>(p.da_out, 2 * q, dax); put<float>(p.da_out, 2 * q + 1, day); }
@@ -164,7 +183,8 @@ __global__ void setup_point_kernel(SetupPointParams p) {
         bmax = fmax(bx, by);
         const bool fin = isfinite(f.phi) && isfinite(f.psi) && isfinite(f.phix) && isfinite(f.phiy)
                          && isfinite(f.psix) && isfinite(f.psiy) && isfinite(bx) && isfinite(by)
-                         && isfinite(e0r) && isfinite(e0i) && isfinite(e1r) && isfinite(e1i);
+                         && isfinite(e0r) && isfinite(e0i) && isfinite(e1r) && isfinite(e1i)
+                         && isfinite(emv) && isfinite(emx) && isfinite(emy);
         bad = fin ? 0.0 : 1.0;
     }
     __shared__ double smin[256], smax[256], sbad[256];

@@ -31,6 +31,10 @@ struct SetupPointParams {
     void* a_out;            // per point a (or null)
     void* E_out;            // per point (e0 re, e0 im, e1 re, e1 im) (or null)
     void* da_out;           // per point (d_x a, d_y a) (or null)
+    const double* em_planes;// electromagnetic profiles V, A_x, A_y (3 FP64 planes) or null
+    double charge;          // e
+    void* em_out;           // per point (sx, sy, wz, qx, qy, q0, a, 0) (or null)
+    double* obs_em;         // 3 FP64 planes: e c a A_x, e c a A_y, e V (or null)
     double* obs;            // 5 planes: w, c a, gx, gy, V
     double* partial;        // 3 doubles per workgroup of 256
 };

@@ -17,6 +17,7 @@ struct Layout {
     size_t a;          // a(x) per point (T), curved metrics only
     size_t E;          // Step-1 exponential per point, 4 T (curved only)
     size_t da;         // (d_x a, d_y a) per point, 2 T (second-order directional step, curved only)
+    size_t em;         // per-point record of the time-dependent exponential, 8 T (potentials only)
     size_t obs;        // 5 FP64 planes for the observables
     size_t fields;     // FIELDS metric staging, 6 FP64 planes
     size_t scratch;    // n1 n2 x 32 bytes: complex128 staging / autotune save
@@ -35,9 +36,10 @@ struct Layout {
 
 dirac_status fail(dirac_status st, const char* fmt, ...);
 dirac_status validate(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
-                      const dirac_scheme* sc);
+                      const dirac_scheme* sc, const dirac_em* em);
 Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml, int32_t prec,
-                   const dirac_scheme* sc);
+                   const dirac_scheme* sc, const dirac_em* em);
+double envelope_at(const dirac_envelope& e, double t);
 dirac_scheme scheme_or_default(const dirac_scheme* sc);
 dirac_status cn_step_n(dirac_solver* s, int64_t nsteps);
 const KernelEntry* pick_entry(int prec, int n, int dir, int other, int mode);
@@ -68,4 +70,7 @@ struct dirac_solver {
     int64_t cn_iters = 0;
     double cn_last_res = 0;
     std::vector<double> cn_host;     // host source of the last GMRES update upload
+    bool has_em = false;             // time-dependent potentials
+    double em_charge = 0;
+    dirac_envelope env_V{}, env_A{};
 };

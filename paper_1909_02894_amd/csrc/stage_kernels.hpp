@@ -41,6 +41,10 @@ struct ObsParams {
     const double* gx;            //   gx = c a chi_x / 2, gy = c a chi_y / 2,
     const double* gy;            //   V = e^Phi m c^2
     const double* V;
+    const double* ax;            // potentials, or null: e c a A_x, e c a A_y, e V planes
+    const double* ay;
+    const double* v0;
+    double fA, fV;               //   and their envelopes at the observation time
     const void* D;               // derivative symbol xi_p / n (T), n entries
     const void* tw;              // twiddles (cpx<T>)
     double* partials;            // 8 doubles per workgroup
@@ -365,13 +369,21 @@ obs_kernel(ObsParams p) {
                 ei = -ca * sr;
                 // conj(own) [coef other] with coef = -i (gx - i gy) for component 0 and
                 // -i (gx + i gy) for component 1, plus +-V |own|^2
-                const double gx = p.gx[q], gy = p.gy[q], V = p.V[q];
-                const double ar = -sgn * gy, ai = -gx;
+                const double gx = p.gx[q], gy = p.gy[q];
+                double V = sgn * p.V[q];
+                double ar = -sgn * gy, ai = -gx;
+                if (p.ax) {
+                    // - e c a fA (A_x sigma_x + A_y sigma_y) - e A0: the other component's
+                    // coefficient gains -fA (ax -+ i ay), the diagonal -fV v0
+                    ar -= p.fA * p.ax[q];
+                    ai += sgn * p.fA * p.ay[q];
+                    V -= p.fV * p.v0[q];
+                }
                 const double tr = ar * orr - ai * oi, ti = ar * oi + ai * orr;
                 er += pr * tr + pi * ti;
                 ei += pr * ti - pi * tr;
                 const double dens = pr * pr + pi * pi;
-                er += sgn * V * dens;
+                er += V * dens;
                 const int ix = COLS ? line : c.j + r * P;
                 const int iy = COLS ? c.j + r * P : line;
                 const double x = -p.a1 + ix * p.h1, y = -p.a2 + iy * p.h2;

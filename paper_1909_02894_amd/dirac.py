@@ -65,6 +65,15 @@ class Scheme(C.Structure):
                 ("reserved", C.c_int32), ("gmres_rtol", C.c_double)]
 
 
+class Envelope(C.Structure):
+    _fields_ = [("c0", C.c_double), ("c1", C.c_double), ("omega", C.c_double), ("phase", C.c_double),
+                ("t0", C.c_double), ("tau", C.c_double)]
+
+
+class Em(C.Structure):
+    _fields_ = [("V", _dp), ("Ax", _dp), ("Ay", _dp), ("charge", C.c_double), ("fV", Envelope), ("fA", Envelope)]
+
+
 class DiracError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -79,8 +88,10 @@ SIGNATURES = {
                                         C.c_size_t, _vp, C.POINTER(_vp)]),
     "dirac_footprint_bytes_scheme": (C.c_size_t, [C.POINTER(Grid), C.POINTER(Metric), C.POINTER(Pml), C.c_int32,
                                                    C.POINTER(Scheme)]),
+    "dirac_footprint_bytes_ex": (C.c_size_t, [C.POINTER(Grid), C.POINTER(Metric), C.POINTER(Pml), C.c_int32,
+                                               C.POINTER(Scheme), C.POINTER(Em)]),
     "dirac_create_solver": (C.c_int32, [C.POINTER(Grid), C.POINTER(Metric), C.POINTER(Pml), C.c_int32,
-                                        C.POINTER(Scheme), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+                                        C.POINTER(Scheme), C.POINTER(Em), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     "dirac_cn_stats": (C.c_int32, [_vp, C.POINTER(C.c_int64), _dp]),
     "dirac_set_initial_spinor": (C.c_int32, [_vp, _dp]),
     "dirac_set_initial_spinor_device": (C.c_int32, [_vp, _vp]),
@@ -179,13 +190,36 @@ def footprint_bytes_scheme(grid: Grid, metric: Metric, pml: Pml, precision: int,
                                                 C.byref(scheme) if scheme is not None else None))
 
 
-def create_solver(grid, metric, pml, precision, scheme: Scheme | None, device_ptr: int, nbytes: int,
-                  stream_ptr: int | None):
+def footprint_bytes_ex(grid: Grid, metric: Metric, pml: Pml, precision: int, scheme: Scheme | None,
+                       em: Em | None) -> int:
+    return int(lib.dirac_footprint_bytes_ex(C.byref(grid), C.byref(metric), C.byref(pml), precision,
+                                            C.byref(scheme) if scheme is not None else None,
+                                            C.byref(em) if em is not None else None))
+
+
+def create_solver(grid, metric, pml, precision, scheme: Scheme | None, em: Em | None, device_ptr: int,
+                  nbytes: int, stream_ptr: int | None):
     h = _vp()
     _check(lib.dirac_create_solver(C.byref(grid), C.byref(metric), C.byref(pml), precision,
-                                   C.byref(scheme) if scheme is not None else None, _vp(device_ptr), nbytes,
+                                   C.byref(scheme) if scheme is not None else None,
+                                   C.byref(em) if em is not None else None, _vp(device_ptr), nbytes,
                                    _vp(stream_ptr or 0), C.byref(h)))
     return h
+
+
+def make_em(n1, n2, V=None, Ax=None, Ay=None, charge=1.0, env_V=(1.0, 0, 0, 0, 0, 0), env_A=(1.0, 0, 0, 0, 0, 0)):
+    """An Em struct and the arrays it points to (keep both alive until creation)."""
+    keep = []
+
+    def plane(a):
+        if a is None:
+            return None
+        arr = np.ascontiguousarray(a, dtype=np.float64)
+        assert arr.shape == (n2, n1)
+        keep.append(arr)
+        return arr.ctypes.data_as(_dp)
+    em = Em(plane(V), plane(Ax), plane(Ay), charge, Envelope(*env_V), Envelope(*env_A))
+    return em, keep
 
 
 def cn_stats(h):
@@ -249,22 +283,26 @@ class Solver:
     def __init__(self, n1, n2, a1, a2, dt, c=1.0, m=1.0, precision=FP64, metric=METRIC_FLAT, spin=SPIN_NONE,
                  bump_A=0.0, bump_s=1.0, fields=None, pml_width=0, pml_type=1, pml_sigma0=1.0, pml_theta=0.0,
                  device=None, stream=None, scheme=SCHEME_EXP_SPLIT, gmres_restart=0, gmres_max_iter=0,
-                 gmres_rtol=0.0):
+                 gmres_rtol=0.0, potentials=None):
+        """potentials: None, or a dict with keys V, Ax, Ay (arrays [n2][n1] or None),
+        charge, env_V, env_A ((c0, c1, omega, phase, t0, tau) tuples)."""
         import torch
         self.n1, self.n2, self.precision = n1, n2, precision
         self.grid, self.metric, self.pml, keep = make_structs(n1, n2, a1, a2, dt, c, m, metric, spin, bump_A,
                                                               bump_s, fields, pml_width, pml_type, pml_sigma0,
                                                               pml_theta)
         self.scheme = Scheme(scheme, gmres_restart, gmres_max_iter, 0, gmres_rtol)
-        self.nbytes = footprint_bytes_scheme(self.grid, self.metric, self.pml, precision, self.scheme)
+        self.em, keep_em = (None, None) if potentials is None else make_em(n1, n2, **potentials)
+        self.nbytes = footprint_bytes_ex(self.grid, self.metric, self.pml, precision, self.scheme, self.em)
         if self.nbytes == 0:
             raise DiracError(-1, last_error())
         device = device or torch.device("cuda", torch.cuda.current_device())
         self.stream = stream or torch.cuda.current_stream(device)
         self.buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
         self.h = None
-        self.h = create_solver(self.grid, self.metric, self.pml, precision, self.scheme, self.buffer.data_ptr(),
-                               self.nbytes, self.stream.cuda_stream)
+        self.h = create_solver(self.grid, self.metric, self.pml, precision, self.scheme, self.em,
+                               self.buffer.data_ptr(), self.nbytes, self.stream.cuda_stream)
+        del keep_em
         del keep
 
     @classmethod

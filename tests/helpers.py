@@ -2,8 +2,19 @@
 from oracle import dirac_oracle as O
 
 
-def oracle_problem(s, fields=None, step2=0) -> "O.Problem":
+def oracle_problem(s, fields=None, step2=0, potentials=None) -> "O.Problem":
+    """potentials: the dict Solver(potentials=...) takes (V, Ax, Ay, charge, env_V, env_A)."""
+    em = None
+    if potentials is not None:
+        import numpy as np
+        z = np.zeros((s.n2, s.n1))
+        pv = dict(potentials)
+        em = O.EMPotentials(pv.get("V") if pv.get("V") is not None else z,
+                            pv.get("Ax") if pv.get("Ax") is not None else z,
+                            pv.get("Ay") if pv.get("Ay") is not None else z,
+                            pv.get("charge", 1.0), O.Envelope(*pv.get("env_V", (1.0, 0, 0, 0, 0, 0))),
+                            O.Envelope(*pv.get("env_A", (1.0, 0, 0, 0, 0, 0))))
     return O.Problem(n1=s.n1, n2=s.n2, a1=s.a1, a2=s.a2, dt=s.dt, c=s.c, m=s.m, metric=s.metric,
                      spin=s.spin, bump_A=s.bump_A, bump_s=s.bump_s, fields=fields,
                      pml_width=s.pml_width, pml_type=s.pml_type, pml_sigma0=s.pml_sigma0,
-                     pml_theta=s.pml_theta, step2=step2)
+                     pml_theta=s.pml_theta, step2=step2, em=em)
