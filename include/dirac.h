@@ -331,6 +331,63 @@ dirac_status dirac_batch_set_graph(dirac_batch* b, int32_t use_graph);
 
 dirac_status dirac_batch_destroy(dirac_batch* b);
 
+/* ------------------------------------------------------------------ 3-D ---
+ * The 3-D, 4-spinor form of Scheme II (Sec. 5.2 with three directions): per
+ * step, Step 1 (E), the x, y and z directional steps
+ *   psi <- b_i F_i^{-1}[K_i F_i psi] + (1 - b_i) psi,
+ *   K_i = exp(-i c dt xi alpha^i) = cos I - i sin alpha^i,  b_i = a / S^i,
+ * and Step 5 (E), in the Dirac representation beta = diag(1, 1, -1, -1),
+ * alpha^i = [[0, sigma_i], [sigma_i, 0]] (alpha^i = Pi^i Lambda Pi^{i,dag},
+ * Lambda = diag(1, 1, -1, -1)).  E = exp(-i dt/2 [beta m c^2 e^Phi + F]) with
+ * F = -i c a (alpha . grad chi) / 2 (the 2-D spin selectors carried over),
+ * in closed form C I + D M since M^2 is a real multiple of I.
+ * State: host [n3][n2][n1][4] complex128 (x fastest); device 8 T per point.
+ * Sizes: powers of two in [16, 1024] per axis, state < 2 GiB.  Metrics:
+ * DIRAC_METRIC_FLAT, DIRAC_METRIC_PAPER_EXP3 (Phi = exp(-0.01 r^2),
+ * Psi = exp(-0.005 r^2), r^2 = x^2 + y^2 + z^2) and DIRAC_METRIC_FIELDS (eight
+ * host planes [n3][n2][n1]).  The same real layer (dirac_pml) on every axis;
+ * b = a / S in [0, 1] is required (DIRAC_E_UNSTABLE otherwise). */
+typedef struct {
+    int32_t n1, n2, n3;           /* points along x, y, z                         */
+    double a1, a2, a3;            /* domain [-a1, a1) x [-a2, a2) x [-a3, a3)      */
+    double dt, c, m;
+} dirac3_grid;
+
+typedef struct {
+    int32_t kind;                 /* DIRAC_METRIC_FLAT, _PAPER_EXP3 or _FIELDS     */
+    int32_t spin;                 /* DIRAC_SPIN_*                                  */
+    const double *phi, *psi;      /* FIELDS only                                   */
+    const double *dphi_dx, *dphi_dy, *dphi_dz, *dpsi_dx, *dpsi_dy, *dpsi_dz;
+} dirac3_metric;
+
+typedef struct {
+    int64_t step;
+    double t;
+    double norm_l2;               /* h1 h2 h3 sum |psi|^2                          */
+    double norm_w;                /* with the weight e^{chi - Phi + Psi}           */
+    double x_mean, y_mean, z_mean;
+    int32_t finite;
+    int32_t reserved;
+} dirac3_obs;
+
+typedef struct dirac3_solver dirac3_solver;
+
+size_t dirac3_footprint_bytes(const dirac3_grid* grid, const dirac3_metric* metric, const dirac_pml* pml,
+                              int32_t precision);
+dirac_status dirac3_create(const dirac3_grid* grid, const dirac3_metric* metric, const dirac_pml* pml,
+                           int32_t precision, void* device_buffer, size_t bytes, void* hip_stream,
+                           dirac3_solver** out);
+dirac_status dirac3_set_initial_spinor(dirac3_solver* s, const double* psi_host);
+dirac_status dirac3_set_initial_spinor_device(dirac3_solver* s, const void* psi_dev);
+/* Asynchronous on the solver's stream (HIP-graph replay of 16-step chunks by default). */
+dirac_status dirac3_step_n(dirac3_solver* s, int64_t nsteps);
+dirac_status dirac3_set_launch_mode(dirac3_solver* s, int32_t use_graph, int32_t graph_chunk);
+/* As dirac_step_n_timed, with ms_out[3] / counts_out[3] for the x, y, z kernels. */
+dirac_status dirac3_step_n_timed(dirac3_solver* s, int64_t nsteps, double* ms_out, int64_t* counts_out);
+dirac_status dirac3_observables(dirac3_solver* s, dirac3_obs* out);
+dirac_status dirac3_get_spinor(dirac3_solver* s, double* psi_host_out);
+dirac_status dirac3_destroy(dirac3_solver* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,25 @@ class Em(C.Structure):
     _fields_ = [("V", _dp), ("Ax", _dp), ("Ay", _dp), ("charge", C.c_double), ("fV", Envelope), ("fA", Envelope)]
 
 
+class Grid3(C.Structure):
+    _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("n3", C.c_int32), ("a1", C.c_double), ("a2", C.c_double),
+                ("a3", C.c_double), ("dt", C.c_double), ("c", C.c_double), ("m", C.c_double)]
+
+
+class Metric3(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("spin", C.c_int32), ("phi", _dp), ("psi", _dp), ("dphi_dx", _dp),
+                ("dphi_dy", _dp), ("dphi_dz", _dp), ("dpsi_dx", _dp), ("dpsi_dy", _dp), ("dpsi_dz", _dp)]
+
+
+class Obs3(C.Structure):
+    _fields_ = [("step", C.c_int64), ("t", C.c_double), ("norm_l2", C.c_double), ("norm_w", C.c_double),
+                ("x_mean", C.c_double), ("y_mean", C.c_double), ("z_mean", C.c_double), ("finite", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class DiracError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -118,6 +137,17 @@ SIGNATURES = {
     "dirac_batch_sync": (C.c_int32, [_vp]),
     "dirac_batch_set_graph": (C.c_int32, [_vp, C.c_int32]),
     "dirac_batch_destroy": (C.c_int32, [_vp]),
+    "dirac3_footprint_bytes": (C.c_size_t, [C.POINTER(Grid3), C.POINTER(Metric3), C.POINTER(Pml), C.c_int32]),
+    "dirac3_create": (C.c_int32, [C.POINTER(Grid3), C.POINTER(Metric3), C.POINTER(Pml), C.c_int32, _vp,
+                                  C.c_size_t, _vp, C.POINTER(_vp)]),
+    "dirac3_set_initial_spinor": (C.c_int32, [_vp, _dp]),
+    "dirac3_set_initial_spinor_device": (C.c_int32, [_vp, _vp]),
+    "dirac3_step_n": (C.c_int32, [_vp, C.c_int64]),
+    "dirac3_set_launch_mode": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
+    "dirac3_step_n_timed": (C.c_int32, [_vp, C.c_int64, _dp, C.POINTER(C.c_int64)]),
+    "dirac3_observables": (C.c_int32, [_vp, C.POINTER(Obs3)]),
+    "dirac3_get_spinor": (C.c_int32, [_vp, _dp]),
+    "dirac3_destroy": (C.c_int32, [_vp]),
 }
 
 
@@ -361,6 +391,91 @@ class Solver:
     def close(self):
         if self.h is not None:
             destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_structs3(n1, n2, n3, a1, a2, a3, dt, c, m, metric=METRIC_FLAT, spin=SPIN_NONE, fields=None,
+                  pml_width=0, pml_type=1, pml_sigma0=1.0, pml_theta=0.0):
+    """Grid3, Metric3, Pml and the arrays the metric points to (FIELDS: eight
+    planes phi, psi, dphi_dx, dphi_dy, dphi_dz, dpsi_dx, dpsi_dy, dpsi_dz)."""
+    keep = []
+    ptrs = [None] * 8
+    if fields is not None:
+        for k, f in enumerate(fields):
+            arr = np.ascontiguousarray(f, dtype=np.float64)
+            assert arr.shape == (n3, n2, n1)
+            keep.append(arr)
+            ptrs[k] = arr.ctypes.data_as(_dp)
+    return (Grid3(n1, n2, n3, a1, a2, a3, dt, c, m), Metric3(metric, spin, *ptrs),
+            Pml(pml_width, pml_type, pml_sigma0, pml_theta), keep)
+
+
+class Solver3:
+    """One 3-D, 4-spinor solve on a torch-allocated device buffer and torch's current stream."""
+
+    def __init__(self, n1, n2, n3, a1, a2, a3, dt, c=1.0, m=1.0, precision=FP64, metric=METRIC_FLAT,
+                 spin=SPIN_NONE, fields=None, pml_width=0, pml_type=1, pml_sigma0=1.0, pml_theta=0.0,
+                 device=None, stream=None):
+        import torch
+        self.shape = (n3, n2, n1)
+        self.precision = precision
+        self.grid, self.metric, self.pml, keep = make_structs3(n1, n2, n3, a1, a2, a3, dt, c, m, metric, spin,
+                                                               fields, pml_width, pml_type, pml_sigma0, pml_theta)
+        self.nbytes = int(lib.dirac3_footprint_bytes(C.byref(self.grid), C.byref(self.metric), C.byref(self.pml),
+                                                     precision))
+        if self.nbytes == 0:
+            raise DiracError(-1, last_error())
+        device = device or torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream or torch.cuda.current_stream(device)
+        self.buffer = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.h = None
+        h = _vp()
+        _check(lib.dirac3_create(C.byref(self.grid), C.byref(self.metric), C.byref(self.pml), precision,
+                                 _vp(self.buffer.data_ptr()), self.nbytes, _vp(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        del keep
+
+    def set_initial_spinor(self, psi):
+        psi = np.ascontiguousarray(psi, dtype=np.complex128)
+        assert psi.shape == self.shape + (4,)
+        _check(lib.dirac3_set_initial_spinor(self.h, psi.view(np.float64).ctypes.data_as(_dp)))
+
+    def set_initial_spinor_device(self, tensor):
+        n3, n2, n1 = self.shape
+        assert tensor.is_contiguous() and tensor.numel() * tensor.element_size() == n1 * n2 * n3 * 64
+        _check(lib.dirac3_set_initial_spinor_device(self.h, _vp(tensor.data_ptr())))
+
+    def step_n(self, n):
+        _check(lib.dirac3_step_n(self.h, int(n)))
+
+    def set_launch_mode(self, use_graph: bool, chunk: int = 16):
+        _check(lib.dirac3_set_launch_mode(self.h, int(use_graph), chunk))
+
+    def step_n_timed(self, n):
+        ms = (C.c_double * 3)()
+        cnt = (C.c_int64 * 3)()
+        _check(lib.dirac3_step_n_timed(self.h, int(n), ms, cnt))
+        return list(ms), list(cnt)
+
+    def observables(self):
+        o = Obs3()
+        _check(lib.dirac3_observables(self.h, C.byref(o)))
+        return o.as_dict()
+
+    def get_spinor(self):
+        out = np.empty(self.shape + (4,), dtype=np.complex128)
+        _check(lib.dirac3_get_spinor(self.h, out.view(np.float64).ctypes.data_as(_dp)))
+        return out
+
+    def close(self):
+        if self.h is not None:
+            _check(lib.dirac3_destroy(self.h))
             self.h = None
 
     def __del__(self):

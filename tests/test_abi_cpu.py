@@ -171,3 +171,32 @@ def test_potentials_validation_and_footprint():
     g4, m4, p4, _ = D.make_structs(4096, 64, 10.0, 10.0, 0.001, 1.0, 1.0)
     em4, keep4 = D.make_em(4096, 64)
     assert D.footprint_bytes_ex(g4, m4, p4, D.FP32, None, em4) == 0 and "2048" in D.last_error()
+
+
+def test_3d_footprint_and_validation():
+    from paper_1909_02894_amd import dirac as D
+    g, m, p, _ = D.make_structs3(64, 32, 16, 5.0, 4.0, 3.0, 0.01, 1.0, 1.0, metric=D.METRIC_PAPER_EXP3,
+                                 spin=D.SPIN_PAPER, pml_width=4)
+    N = 64 * 32 * 16
+    f64 = D.lib.dirac3_footprint_bytes(ctypes.byref(g), ctypes.byref(m), ctypes.byref(p), D.FP64)
+    f32 = D.lib.dirac3_footprint_bytes(ctypes.byref(g), ctypes.byref(m), ctypes.byref(p), D.FP32)
+    # state 8 T, a, E record (6 FP64 / 8 FP32), weight, 64-byte staging per point
+    assert f64 >= N * (64 + 8 + 48 + 8 + 64) and f32 >= N * (32 + 4 + 32 + 8 + 64) and f32 < f64
+
+    def status(**kw):
+        args = dict(n1=32, n2=32, n3=32, a1=5.0, a2=5.0, a3=5.0, dt=0.01, c=1.0, m=1.0)
+        args.update(kw)
+        g, m, p, keep = D.make_structs3(**args)
+        h = ctypes.c_void_p()
+        return D.lib.dirac3_create(ctypes.byref(g), ctypes.byref(m), ctypes.byref(p), 0, None, 0, None,
+                                   ctypes.byref(h))
+    assert status(n3=48) == -2
+    assert status(n1=2048) == -2
+    assert status(n1=1024, n2=1024, n3=256) == -2            # state beyond 2 GiB
+    assert status(metric=D.METRIC_GAUSS_BUMP) == -1
+    assert status(metric=D.METRIC_FIELDS) == -1
+    assert status(pml_width=20) == -1
+    assert status(pml_width=4, pml_theta=0.5) == -3
+    assert status(dt=-1.0) == -1
+    assert status() == -1 and "null device buffer" in D.last_error()
+    assert D.lib.dirac3_step_n(None, 1) == -1
