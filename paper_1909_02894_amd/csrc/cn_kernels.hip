@@ -131,17 +131,31 @@ __global__ void __launch_bounds__(256) cn_multidot_kernel(const double* V, size_
     }
 }
 
-// out[k] = sum over blocks of partials[block][k] (fixed order), k < nk; one thread per k.
-__global__ void cn_reduce_kernel(const double* partials, int nblocks, int ldp, int nk, double* out) {
-    const int k = threadIdx.x;
-    if (k >= nk) return;
+// out[k] = sum over blocks of partials[block][k], k < nk: one workgroup per k,
+// a fixed per-thread order over the blocks and a fixed tree, so the result does
+// not depend on timing.
+__global__ void __launch_bounds__(256) cn_reduce_kernel(const double* partials, int nblocks, int ldp, double* out) {
+    const int k = blockIdx.x;
     double r = 0, i = 0;
-    for (int b = 0; b < nblocks; ++b) {
+    for (int b = threadIdx.x; b < nblocks; b += 256) {
         r += partials[2 * ((size_t)b * ldp + k)];
         i += partials[2 * ((size_t)b * ldp + k) + 1];
     }
-    out[2 * k] = r;
-    out[2 * k + 1] = i;
+    __shared__ double sr[256], si[256];
+    sr[threadIdx.x] = r;
+    si[threadIdx.x] = i;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sr[threadIdx.x] += sr[threadIdx.x + off];
+            si[threadIdx.x] += si[threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * k] = sr[0];
+        out[2 * k + 1] = si[0];
+    }
 }
 
 // w <- w - sign sum_k coef[k] V_k (coef complex, read from device memory), k < nk.
@@ -207,7 +221,7 @@ hipError_t launch_cn_dots(const double* V, size_t vstride, int nk, const double*
         hipLaunchKernelGGL(cn_multidot_kernel, dim3(nblocks), dim3(256), 0, s, V, vstride, k0,
                            nk - k0 < 8 ? nk - k0 : 8, w, ncplx, partials, ldp);
     }
-    hipLaunchKernelGGL(cn_reduce_kernel, dim3(1), dim3(64), 0, s, (const double*)partials, nblocks, ldp, nk, out);
+    hipLaunchKernelGGL(cn_reduce_kernel, dim3(nk), dim3(256), 0, s, (const double*)partials, nblocks, ldp, out);
     return hipGetLastError();
 }
 

@@ -39,17 +39,17 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()[:16]
 
 
-_STAGE = re.compile(r"stage_kernel<(double|float), (\d+), (\d+), (\d+), (true|false), (true|false), (\d)>")
+_STAGE = re.compile(r"(?<![a-z0-9_])stage_kernel<(double|float), (\d+), (\d+), (\d+), (true|false), (\d), (\d)>")
 
 
 def bench_name(kernel: str, grid: str):
     """Map a stage-kernel instantiation to bench.py's name, e.g.
-    'void dirac::stage_kernel<double, 512, 8, 2, true, false, 2>(...)' ->
-    'y_stage_f64_512x512_curved'."""
+    'void dirac::stage_kernel<double, 512, 8, 2, true, 2, 1>(...)' ->
+    'y_stage_f64_512x512_curved' (template arguments T, N, R, L, COLS, MODE, CPT)."""
     m = _STAGE.search(kernel)
     if not m:
         return None
-    t, n, r, lines, cols, split, mode = m.groups()
+    t, n, r, lines, cols, mode, cpt = m.groups()
     return f"{'y' if cols == 'true' else 'x'}_stage_{'f64' if t == 'double' else 'f32'}_{grid}_{MODE_NAMES[int(mode)]}"
 
 

@@ -70,6 +70,17 @@ def gaussian_packet(n1: int, n2: int, a1: float, a2: float, x0=(0.0, 0.0), k0=(1
     return out
 
 
+def gaussian_packet3(n1: int, n2: int, n3: int, a1: float, a2: float, a3: float, x0=(0.0, 0.0, 0.0),
+                     k0=(1.0, 0.0, 0.0), width: float = 2.0, comp=(1.0, 0.0, 0.0, 0.0)) -> np.ndarray:
+    """3-D packet exp(-|x - x0|^2 / (2 width^2)) exp(i k0 . x) times a constant
+    4-spinor, shape (n3, n2, n1, 4), x fastest."""
+    ax = [-a + (2.0 * a / n) * np.arange(n) for n, a in ((n1, a1), (n2, a2), (n3, a3))]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    f = (np.exp(-((X - x0[0]) ** 2 + (Y - x0[1]) ** 2 + (Z - x0[2]) ** 2) / (2.0 * width * width))
+         * np.exp(1j * (k0[0] * X + k0[1] * Y + k0[2] * Z)))
+    return np.stack([c * f for c in comp], axis=-1)
+
+
 def initial_spinor(s: SolveSpec) -> np.ndarray:
     return gaussian_packet(s.n1, s.n2, s.a1, s.a2, s.x0, s.k0, s.width, s.comp)
 
