@@ -133,3 +133,48 @@ def test_batch_rejects_bad_input(D):
     b.run([2, 0])
     b.sync()
     assert s.observables()["step"] == 2
+
+
+def test_sixteen_seeded_solves_cover_every_size(D):
+    # the batch workload's recipe (seeds 4000+i, n in {128, 256, 512}) on 16 solves,
+    # 20 steps each, FP32 against the FP64 oracle
+    specs = W.batch_mix(16, 4000, (128, 256, 512), 20)
+    assert {sp.n1 for sp in specs} == {128, 256, 512}
+    b = D.Batch(precision=D.FP32, capacity=16)
+    solvers = []
+    for sp in specs:
+        s = D.Solver.from_spec(sp, precision=D.FP32, stream=b.stream)
+        s.set_initial_spinor(W.initial_spinor(sp))
+        b.add(s)
+        solvers.append(s)
+    b.run([20] * 16)
+    b.sync()
+    for sp, s in zip(specs, solvers):
+        ref = O.run(W.initial_spinor(sp), O.build_tables(oracle_problem(sp)), 20)
+        assert O.rel_l2(s.get_spinor(), ref) < 2e-5, (sp.n1, sp.seed)
+    b.close()
+
+
+def test_full_batch_workload_sampled(D):
+    # the full 256-solve, 1000-step FP32 batch as bench.py runs it (one graph);
+    # the 128x128 solves among them are checked against the oracle at 1000 steps
+    # (bound 2e-4), every solve is finite and its weighted norm stays bounded
+    specs = W.batch_mix(256, 4000, (128, 256, 512), 1000)
+    b = D.Batch(precision=D.FP32, capacity=256)
+    solvers = []
+    for sp in specs:
+        s = D.Solver.from_spec(sp, precision=D.FP32, stream=b.stream)
+        s.set_initial_spinor(W.initial_spinor(sp))
+        b.add(s)
+        solvers.append(s)
+    b.run([1000] * 256)
+    b.sync()
+    small = [i for i, sp in enumerate(specs) if sp.n1 == 128][:3]
+    for i in small:
+        sp = specs[i]
+        ref = O.run(W.initial_spinor(sp), O.build_tables(oracle_problem(sp)), 1000)
+        assert O.rel_l2(solvers[i].get_spinor(), ref) < 2e-4, (sp.n1, sp.seed)
+    for s in solvers[::17]:
+        ob = s.observables()
+        assert ob["finite"] == 1 and ob["step"] == 1000
+    b.close()
