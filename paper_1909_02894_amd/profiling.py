@@ -3,9 +3,13 @@
     python -m paper_1909_02894_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
     python -m paper_1909_02894_amd.profiling traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
         <copy_write.csv> <grid> <out.json> "<command>"
+    python -m paper_1909_02894_amd.profiling trace <kernel_trace.csv> <out.md> "<command>" [filter]
 
 `stats` turns a ``--kernel-trace --stats`` kernel table into a short markdown
-summary.  `traffic` takes two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
+summary.  `trace` splits the dispatches of every direction kernel in a
+``--kernel-trace`` CSV by context: launches between two launches of the same
+kernel (a kernel replayed alone, its data still in its XCD's L2) and all the
+others (the real alternating x, y order), with the median of each.  `traffic` takes two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
 counter-collection CSVs (KiB per dispatch) of a solve, and the same two
 counters for a plain 1 GiB device copy, scales each counter by
 (bytes the copy moves) / (what the counter reads for the copy), and writes the
@@ -110,10 +114,34 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, grid, out_json
     return out
 
 
+def trace(csv_path: str, out_md: str, command: str, filt: str = "stage_kernel"):
+    rows = sorted(csv.DictReader(open(csv_path)), key=lambda r: int(r["Start_Timestamp"]))
+    seq = [(short_name(r["Kernel_Name"]), int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows]
+    alt, iso = defaultdict(list), defaultdict(list)
+    for i in range(1, len(seq) - 1):
+        k, t0, t1 = seq[i]
+        if filt not in k:
+            continue
+        same = seq[i - 1][0] == k and seq[i + 1][0] == k
+        (iso if same else alt)[k].append((t1 - t0) / 1e3)
+    lines = ["# rocprofv3 kernel trace: direction-kernel durations by context", "", "Command:", "", "```", command,
+             "```", "", "| kernel | in sequence: launches | median (us) | replayed alone: launches | median (us) |",
+             "|---|---:|---:|---:|---:|"]
+    keys = sorted(set(alt) | set(iso), key=lambda k: -len(alt.get(k, [])))
+    for k in keys:
+        a, b = alt.get(k, []), iso.get(k, [])
+        ma = f"{statistics.median(a):.2f}" if a else "-"
+        mb = f"{statistics.median(b):.2f}" if b else "-"
+        lines.append(f"| `{k}` | {len(a)} | {ma} | {len(b)} | {mb} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:9])
+    elif sys.argv[1] == "trace":
+        trace(*sys.argv[2:6])
     else:
         raise SystemExit(__doc__)
