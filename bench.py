@@ -121,6 +121,8 @@ def bench_batch(D, W, count=256, steps=1000):
         s.set_initial_spinor(W.initial_spinor(sp))
         b.add(s)
         solvers.append(s)
+    b.autotune(5)                   # schedule per (direction, n), states restored
+    sched = {str(n): [b.schedule(n, 0), b.schedule(n, 1)] for n in (128, 256, 512)}
     b.run([steps] * count)          # builds and replays the graph
     b.sync()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -136,7 +138,7 @@ def bench_batch(D, W, count=256, steps=1000):
     hist = {n: sum(1 for sp in specs if sp.n1 == n) for n in (128, 256, 512)}
     b.close()
     return {"value": pts * steps / (ms * 1e-3), "unit": "grid-point*steps/s", "dtype": "f32",
-            "solves": count, "steps": steps, "grid_sizes": hist, "ms": ms, "finite": fin,
+            "solves": count, "steps": steps, "grid_sizes": hist, "ms": ms, "finite": fin, "schedules": sched,
             "step_roofline": {"bound": "hbm", "achieved": round(algo / (ms * 1e-3) / 1e9, 1),
                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -5,5 +5,5 @@
 namespace dirac {
 static BatchKernelRegistrar reg_batch_f32_x(1, 0,
     reinterpret_cast<const void*>(&batch_stage_kernel<float, false>),
-    [](int logn) { return batch_smem_for_logn<float, false>(logn); });
+    [](int logn, int s) { return batch_smem_for<float, false>(logn, s); });
 }  // namespace dirac

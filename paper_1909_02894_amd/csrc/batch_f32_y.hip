@@ -5,5 +5,5 @@
 namespace dirac {
 static BatchKernelRegistrar reg_batch_f32_y(1, 1,
     reinterpret_cast<const void*>(&batch_stage_kernel<float, true>),
-    [](int logn) { return batch_smem_for_logn<float, true>(logn); });
+    [](int logn, int s) { return batch_smem_for<float, true>(logn, s); });
 }  // namespace dirac

@@ -5,5 +5,5 @@
 namespace dirac {
 static BatchKernelRegistrar reg_batch_f64_x(0, 0,
     reinterpret_cast<const void*>(&batch_stage_kernel<double, false>),
-    [](int logn) { return batch_smem_for_logn<double, false>(logn); });
+    [](int logn, int s) { return batch_smem_for<double, false>(logn, s); });
 }  // namespace dirac

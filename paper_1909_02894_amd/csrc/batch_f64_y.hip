@@ -5,5 +5,5 @@
 namespace dirac {
 static BatchKernelRegistrar reg_batch_f64_y(0, 1,
     reinterpret_cast<const void*>(&batch_stage_kernel<double, true>),
-    [](int logn) { return batch_smem_for_logn<double, true>(logn); });
+    [](int logn, int s) { return batch_smem_for<double, true>(logn, s); });
 }  // namespace dirac

@@ -5,11 +5,13 @@
 // is still active at step k; the workgroup -> (solve, tile) map is a binary
 // search in the per-direction tile prefix of the solves, which are ordered by
 // their step counts (longest first), so the active solves are always a prefix.
-// All batch schedules use 256-thread workgroups with both spinor components in
-// a thread: radix R = 4 for n <= 64, else 8, and L = 256 / (n / R) lines per
-// tile, for n up to 2048.  The per-line arithmetic is that of the
-// single-solve direction kernel with the same radix, so a solve's result is the
-// same bit for bit alone or in any mix.
+// All batch schedules use 256-thread workgroups.  Per (direction, n) the batch
+// picks one of up to four schedules (radix R in {8, 4}, both components in a
+// thread or one per lane), with L = 256 / ((n / R) (2 / components)) lines per
+// tile, for n up to 2048; schedule 0 (R = 4 for n <= 64, else 8, both
+// components) is the default and the others are chosen by the batch autotuner.
+// The per-line arithmetic is that of the single-solve direction kernel with the
+// same radix, so a solve's result is the same bit for bit alone or in any mix.
 #pragma once
 #include "stage_kernels.hpp"
 
@@ -26,6 +28,7 @@ struct BatchDesc {
     int n1, n2;
     int logn[2];      // log2 of the transform length per direction
     int mode;         // 0 flat, 1 flat + layer, 2 curved
+    int sched[2];     // batch schedule per direction
     int steps;        // steps of this solve in the current run
     cpx<T> e0u;
 };
@@ -40,20 +43,39 @@ struct BatchPhase {
 };
 
 __host__ __device__ constexpr int batch_radix(int n) { return n <= 64 ? 4 : 8; }
-__host__ __device__ constexpr int batch_lines(int n) { return 256 / (n / batch_radix(n)); }
-constexpr int kBatchCPT = 2;
 constexpr int kBatchThreads = 256;
+constexpr int kBatchSchedules = 4;
 
+// Schedule s for transform length n: radix and components per thread.
+__host__ __device__ constexpr int bsched_radix(int n, int s) {
+    return (s < 2) == (batch_radix(n) == 8) ? 8 : 4;
+}
+__host__ __device__ constexpr int bsched_cpt(int s) { return (s & 1) ? 1 : 2; }
+__host__ __device__ constexpr int bsched_threads_per_line(int n, int s) {
+    return (n / bsched_radix(n, s)) * (bsched_cpt(s) == 1 ? 2 : 1);
+}
+__host__ __device__ constexpr bool bsched_valid(int n, int s) {
+    return s >= 0 && s < kBatchSchedules && n % bsched_radix(n, s) == 0 && n / bsched_radix(n, s) >= 2 &&
+           bsched_threads_per_line(n, s) <= kBatchThreads && kBatchThreads % bsched_threads_per_line(n, s) == 0 &&
+           n % (bsched_radix(n, s) * bsched_radix(n, s)) == 0;
+}
+__host__ __device__ constexpr int bsched_lines(int n, int s) { return kBatchThreads / bsched_threads_per_line(n, s); }
+__host__ __device__ constexpr int batch_lines(int n) { return bsched_lines(n, 0); }
+
+template <typename T, bool COLS, int N, int S>
+__host__ __device__ constexpr size_t batch_smem_bytes_s() {
+    return (LineFFT<T, N, bsched_radix(N, S), bsched_lines(N, S), COLS, bsched_cpt(S)>::LDS_ELEMS +
+            TwStage<T, N>::ELEMS) * sizeof(cpx<T>);
+}
 template <typename T, bool COLS, int N>
 __host__ __device__ constexpr size_t batch_smem_bytes() {
-    return (LineFFT<T, N, batch_radix(N), batch_lines(N), COLS, kBatchCPT>::LDS_ELEMS + TwStage<T, N>::ELEMS) *
-           sizeof(cpx<T>);
+    return batch_smem_bytes_s<T, COLS, N, 0>();
 }
 
-template <typename T, bool COLS, int N>
+template <typename T, bool COLS, int N, int S>
 __device__ __forceinline__ void batch_tile(const BatchDesc<T>& d, int tile, int k, char* smem) {
-    constexpr int R = batch_radix(N), L = batch_lines(N);
-    using F = LineFFT<T, N, R, L, COLS, kBatchCPT>;
+    constexpr int R = bsched_radix(N, S), L = bsched_lines(N, S), CPT = bsched_cpt(S);
+    using F = LineFFT<T, N, R, L, COLS, CPT>;
     static_assert(F::NT == kBatchThreads, "batch schedules use 256-thread workgroups");
     cpx<T>* lds = reinterpret_cast<cpx<T>*>(smem);
     cpx<T>* twl = lds + F::LDS_ELEMS;
@@ -70,9 +92,19 @@ __device__ __forceinline__ void batch_tile(const BatchDesc<T>& d, int tile, int 
     p.e_pre = COLS ? 0 : (k == 0 ? 1 : 2);
     p.e_post = COLS ? (k == d.steps - 1 ? 1 : 0) : 0;
     p.e0u = d.e0u;
-    if (d.mode == 0) stage_tile<T, N, R, L, COLS, 0, kBatchCPT>(p, tile, lds, twl);
-    else if (d.mode == 1) stage_tile<T, N, R, L, COLS, 1, kBatchCPT>(p, tile, lds, twl);
-    else stage_tile<T, N, R, L, COLS, 2, kBatchCPT>(p, tile, lds, twl);
+    if (d.mode == 0) stage_tile<T, N, R, L, COLS, 0, CPT>(p, tile, lds, twl);
+    else if (d.mode == 1) stage_tile<T, N, R, L, COLS, 1, CPT>(p, tile, lds, twl);
+    else stage_tile<T, N, R, L, COLS, 2, CPT>(p, tile, lds, twl);
+}
+
+// Dispatch on the solve's schedule (schedules not valid for N fall back to 0;
+// the host never selects them).
+template <typename T, bool COLS, int N>
+__device__ __forceinline__ void batch_tile_any(const BatchDesc<T>& d, int tile, int k, char* smem, int s) {
+    if constexpr (bsched_valid(N, 1)) { if (s == 1) { batch_tile<T, COLS, N, 1>(d, tile, k, smem); return; } }
+    if constexpr (bsched_valid(N, 2)) { if (s == 2) { batch_tile<T, COLS, N, 2>(d, tile, k, smem); return; } }
+    if constexpr (bsched_valid(N, 3)) { if (s == 3) { batch_tile<T, COLS, N, 3>(d, tile, k, smem); return; } }
+    batch_tile<T, COLS, N, 0>(d, tile, k, smem);
 }
 
 template <typename T, bool COLS>
@@ -87,24 +119,33 @@ __global__ void __launch_bounds__(kBatchThreads) batch_stage_kernel(BatchPhase<T
     }
     const BatchDesc<T> d = ph.desc[lo];
     const int tile = t - ph.prefix[lo];
+    const int s = d.sched[COLS ? 1 : 0];
     switch (d.logn[COLS ? 1 : 0]) {
-        case 4: batch_tile<T, COLS, 16>(d, tile, ph.k, smem); break;
-        case 5: batch_tile<T, COLS, 32>(d, tile, ph.k, smem); break;
-        case 6: batch_tile<T, COLS, 64>(d, tile, ph.k, smem); break;
-        case 7: batch_tile<T, COLS, 128>(d, tile, ph.k, smem); break;
-        case 8: batch_tile<T, COLS, 256>(d, tile, ph.k, smem); break;
-        case 9: batch_tile<T, COLS, 512>(d, tile, ph.k, smem); break;
-        case 10: batch_tile<T, COLS, 1024>(d, tile, ph.k, smem); break;
-        default: batch_tile<T, COLS, 2048>(d, tile, ph.k, smem); break;
+        case 4: batch_tile_any<T, COLS, 16>(d, tile, ph.k, smem, s); break;
+        case 5: batch_tile_any<T, COLS, 32>(d, tile, ph.k, smem, s); break;
+        case 6: batch_tile_any<T, COLS, 64>(d, tile, ph.k, smem, s); break;
+        case 7: batch_tile_any<T, COLS, 128>(d, tile, ph.k, smem, s); break;
+        case 8: batch_tile_any<T, COLS, 256>(d, tile, ph.k, smem, s); break;
+        case 9: batch_tile_any<T, COLS, 512>(d, tile, ph.k, smem, s); break;
+        case 10: batch_tile_any<T, COLS, 1024>(d, tile, ph.k, smem, s); break;
+        default: batch_tile_any<T, COLS, 2048>(d, tile, ph.k, smem, s); break;
     }
 }
 
+template <typename T, bool COLS, int N>
+constexpr size_t batch_smem_n(int s) {
+    return (s == 1 && bsched_valid(N, 1)) ? batch_smem_bytes_s<T, COLS, N, (bsched_valid(N, 1) ? 1 : 0)>()
+         : (s == 2 && bsched_valid(N, 2)) ? batch_smem_bytes_s<T, COLS, N, (bsched_valid(N, 2) ? 2 : 0)>()
+         : (s == 3 && bsched_valid(N, 3)) ? batch_smem_bytes_s<T, COLS, N, (bsched_valid(N, 3) ? 3 : 0)>()
+         : batch_smem_bytes_s<T, COLS, N, 0>();
+}
+
 template <typename T, bool COLS>
-constexpr size_t batch_smem_for_logn(int logn) {
-    return logn == 4 ? batch_smem_bytes<T, COLS, 16>() : logn == 5 ? batch_smem_bytes<T, COLS, 32>()
-         : logn == 6 ? batch_smem_bytes<T, COLS, 64>() : logn == 7 ? batch_smem_bytes<T, COLS, 128>()
-         : logn == 8 ? batch_smem_bytes<T, COLS, 256>() : logn == 9 ? batch_smem_bytes<T, COLS, 512>()
-         : logn == 10 ? batch_smem_bytes<T, COLS, 1024>() : batch_smem_bytes<T, COLS, 2048>();
+constexpr size_t batch_smem_for(int logn, int s) {
+    return logn == 4 ? batch_smem_n<T, COLS, 16>(s) : logn == 5 ? batch_smem_n<T, COLS, 32>(s)
+         : logn == 6 ? batch_smem_n<T, COLS, 64>(s) : logn == 7 ? batch_smem_n<T, COLS, 128>(s)
+         : logn == 8 ? batch_smem_n<T, COLS, 256>(s) : logn == 9 ? batch_smem_n<T, COLS, 512>(s)
+         : logn == 10 ? batch_smem_n<T, COLS, 1024>(s) : batch_smem_n<T, COLS, 2048>(s);
 }
 
 }  // namespace dirac

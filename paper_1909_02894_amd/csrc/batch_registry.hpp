@@ -6,13 +6,13 @@ namespace dirac {
 
 struct BatchKernel {
     const void* fn = nullptr;
-    size_t (*smem)(int logn) = nullptr;
+    size_t (*smem)(int logn, int sched) = nullptr;
 };
 
 BatchKernel& batch_kernel(int prec, int dir);
 
 struct BatchKernelRegistrar {
-    BatchKernelRegistrar(int prec, int dir, const void* fn, size_t (*smem)(int)) {
+    BatchKernelRegistrar(int prec, int dir, const void* fn, size_t (*smem)(int, int)) {
         batch_kernel(prec, dir).fn = fn;
         batch_kernel(prec, dir).smem = smem;
     }

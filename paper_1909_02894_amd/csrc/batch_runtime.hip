@@ -49,6 +49,7 @@ struct dirac_batch {
     int graph_half = -1;
     uint64_t version = 0;
     uint64_t graph_version = ~0ull;
+    int sched[2][12] = {};          // batch schedule per (direction, log2 n)
 };
 
 static dirac_status bhip(hipError_t e, const char* what) {
@@ -71,7 +72,7 @@ static void batch_drop_graph(dirac_batch* b) {
 }
 
 template <typename T>
-static void fill_desc(BatchDesc<T>& d, const dirac_solver* s, int steps) {
+static void fill_desc(BatchDesc<T>& d, const dirac_solver* s, int steps, const int (&sched)[2][12]) {
     char* base = s->base;
     d.psi = reinterpret_cast<T*>(base + s->lay.psi);
     d.a = s->curved ? reinterpret_cast<const T*>(base + s->lay.a) : nullptr;
@@ -86,12 +87,14 @@ static void fill_desc(BatchDesc<T>& d, const dirac_solver* s, int steps) {
     d.logn[0] = __builtin_ctz((unsigned)s->g.n1);
     d.logn[1] = __builtin_ctz((unsigned)s->g.n2);
     d.mode = s->curved ? 2 : (s->pml ? 1 : 0);
+    d.sched[0] = sched[0][d.logn[0]];
+    d.sched[1] = sched[1][d.logn[1]];
     d.steps = steps;
     d.e0u = cpx<T>{(T)s->e0u_re, (T)s->e0u_im};
 }
 
-static int tiles_of(int n_line, int n_lines) {
-    const int L = batch_lines(n_line);
+static int tiles_of(int n_line, int n_lines, int sched) {
+    const int L = bsched_lines(n_line, sched);
     return (n_lines + L - 1) / L;
 }
 
@@ -206,8 +209,9 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
             const dirac_solver* s = b->slots[act[q]];
             const int nl = d == 0 ? s->g.n1 : s->g.n2;
             const int lines = d == 0 ? s->g.n2 : s->g.n1;
-            prefix[d][q + 1] = prefix[d][q] + tiles_of(nl, lines);
-            smem[d] = std::max(smem[d], batch_kernel(b->prec, d).smem(__builtin_ctz((unsigned)nl)));
+            const int lg = __builtin_ctz((unsigned)nl);
+            prefix[d][q + 1] = prefix[d][q] + tiles_of(nl, lines, b->sched[d][lg]);
+            smem[d] = std::max(smem[d], batch_kernel(b->prec, d).smem(lg, b->sched[d][lg]));
         }
     }
     if (!reuse) {
@@ -217,8 +221,10 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
         char* hs = b->host_stage[h];
         for (int q = 0; q < na; ++q) {
             const dirac_solver* s = b->slots[act[q]];
-            if (b->prec == DIRAC_FP64) fill_desc(reinterpret_cast<BatchDesc<double>*>(hs)[q], s, (int)steps[act[q]]);
-            else fill_desc(reinterpret_cast<BatchDesc<float>*>(hs)[q], s, (int)steps[act[q]]);
+            if (b->prec == DIRAC_FP64)
+                fill_desc(reinterpret_cast<BatchDesc<double>*>(hs)[q], s, (int)steps[act[q]], b->sched);
+            else
+                fill_desc(reinterpret_cast<BatchDesc<float>*>(hs)[q], s, (int)steps[act[q]], b->sched);
         }
         std::memcpy(hs + desc_bytes, prefix[0].data(), (na + 1) * sizeof(int));
         std::memcpy(hs + desc_bytes + (b->capacity + 1) * sizeof(int), prefix[1].data(), (na + 1) * sizeof(int));
@@ -280,6 +286,124 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
     }
     for (int i : act) b->slots[i]->step += steps[i];
     return DIRAC_OK;
+}
+
+static bool bsched_valid_host(int n, int sc) {
+    return sc >= 0 && sc < kBatchSchedules && bsched_valid(n, sc);
+}
+
+dirac_status dirac_batch_get_schedule(const dirac_batch* b, int32_t n, int32_t dir, dirac_schedule* out) {
+    if (!b || !out || dir < 0 || dir > 1 || n < 16 || n > 2048 || (n & (n - 1))) return fail(DIRAC_E_ARG, "bad arguments");
+    const int sc = b->sched[dir][__builtin_ctz((unsigned)n)];
+    out->radix = bsched_radix(n, sc);
+    out->lines_per_wg = bsched_lines(n, sc);
+    out->components_per_thread = bsched_cpt(sc);
+    return DIRAC_OK;
+}
+
+dirac_status dirac_batch_set_schedule(dirac_batch* b, int32_t n, int32_t dir, const dirac_schedule* sch) {
+    if (!b || !sch || dir < 0 || dir > 1 || n < 16 || n > 2048 || (n & (n - 1))) return fail(DIRAC_E_ARG, "bad arguments");
+    for (int sc = 0; sc < kBatchSchedules; ++sc) {
+        if (bsched_valid_host(n, sc) && bsched_radix(n, sc) == sch->radix && bsched_cpt(sc) == sch->components_per_thread &&
+            (sch->lines_per_wg == 0 || sch->lines_per_wg == bsched_lines(n, sc))) {
+            b->sched[dir][__builtin_ctz((unsigned)n)] = sc;
+            ++b->version;
+            batch_drop_graph(b);
+            return DIRAC_OK;
+        }
+    }
+    return fail(DIRAC_E_ARG, "no batch schedule with radix %d, %d components per thread for n = %d", sch->radix,
+                sch->components_per_thread, n);
+}
+
+int32_t dirac_batch_schedule_count(int32_t n) {
+    if (n < 16 || n > 2048 || (n & (n - 1))) return 0;
+    int c = 0;
+    for (int sc = 0; sc < kBatchSchedules; ++sc) c += bsched_valid_host(n, sc) ? 1 : 0;
+    return c;
+}
+
+// Coordinate search: for every (direction, n) present, time each valid
+// schedule on `reps` steps of the whole batch (direct launches, events on the
+// batch stream) and keep the fastest; states and step counters are restored.
+dirac_status dirac_batch_autotune(dirac_batch* b, int32_t reps) {
+    if (!b || reps < 1 || reps > 10000) return fail(DIRAC_E_ARG, "bad arguments");
+    std::vector<int> occ;
+    for (int i = 0; i < b->capacity; ++i)
+        if (b->slots[i]) {
+            if (!b->slots[i]->has_state) return fail(DIRAC_E_STATE, "slot %d has no state", i);
+            occ.push_back(i);
+        }
+    if (occ.empty()) return DIRAC_OK;
+    const bool graph_was = b->use_graph;
+    b->use_graph = false;
+    batch_drop_graph(b);
+    const size_t sz = b->prec == DIRAC_FP32 ? 4 : 8;
+    for (int i : occ) {
+        dirac_solver* s = b->slots[i];
+        const size_t bytes = (size_t)s->g.n1 * s->g.n2 * 4 * sz;
+        BTRY(hipMemcpyAsync(s->base + s->lay.scratch, s->base + s->lay.psi, bytes, hipMemcpyDeviceToDevice, b->stream),
+             "save state");
+    }
+    std::vector<int64_t> steps(b->capacity, 0);
+    for (int i : occ) steps[i] = reps;
+    hipEvent_t ev[2];
+    BTRY(hipEventCreate(&ev[0]), "hipEventCreate");
+    BTRY(hipEventCreate(&ev[1]), "hipEventCreate");
+    dirac_status result = DIRAC_OK;
+    auto timed_run = [&](float& ms) -> dirac_status {
+        BTRY(hipEventRecord(ev[0], b->stream), "hipEventRecord");
+        dirac_status r = dirac_batch_run(b, steps.data());
+        if (r != DIRAC_OK) return r;
+        BTRY(hipEventRecord(ev[1], b->stream), "hipEventRecord");
+        BTRY(hipEventSynchronize(ev[1]), "hipEventSynchronize");
+        BTRY(hipEventElapsedTime(&ms, ev[0], ev[1]), "hipEventElapsedTime");
+        return DIRAC_OK;
+    };
+    float warm = 0;
+    result = timed_run(warm);
+    for (int d = 0; d < 2 && result == DIRAC_OK; ++d) {
+        for (int lg = 4; lg <= 11 && result == DIRAC_OK; ++lg) {
+            bool present = false;
+            for (int i : occ) present |= __builtin_ctz((unsigned)(d == 0 ? b->slots[i]->g.n1 : b->slots[i]->g.n2)) == lg;
+            if (!present) continue;
+            const int n = 1 << lg;
+            int best = b->sched[d][lg];
+            float best_ms = 1e30f;
+            for (int sc = 0; sc < kBatchSchedules && result == DIRAC_OK; ++sc) {
+                if (!bsched_valid_host(n, sc)) continue;
+                b->sched[d][lg] = sc;
+                ++b->version;
+                float ms = 0;
+                result = timed_run(ms);
+                if (result == DIRAC_OK && ms < best_ms) { best_ms = ms; best = sc; }
+            }
+            b->sched[d][lg] = best;
+            ++b->version;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    for (int i : occ) {
+        dirac_solver* s = b->slots[i];
+        const size_t bytes = (size_t)s->g.n1 * s->g.n2 * 4 * sz;
+        BTRY(hipMemcpyAsync(s->base + s->lay.psi, s->base + s->lay.scratch, bytes, hipMemcpyDeviceToDevice, b->stream),
+             "restore state");
+    }
+    BTRY(hipStreamSynchronize(b->stream), "synchronise");
+    // every timed run advanced the step counters; put them back
+    int runs = 1;
+    for (int d = 0; d < 2; ++d)
+        for (int lg = 4; lg <= 11; ++lg) {
+            bool present = false;
+            for (int i : occ) present |= __builtin_ctz((unsigned)(d == 0 ? b->slots[i]->g.n1 : b->slots[i]->g.n2)) == lg;
+            if (present)
+                for (int sc = 0; sc < kBatchSchedules; ++sc) runs += bsched_valid_host(1 << lg, sc) ? 1 : 0;
+        }
+    if (result == DIRAC_OK)
+        for (int i : occ) b->slots[i]->step -= (int64_t)runs * reps;
+    b->use_graph = graph_was;
+    return result;
 }
 
 dirac_status dirac_batch_sync(dirac_batch* b) {

@@ -137,6 +137,10 @@ SIGNATURES = {
     "dirac_batch_sync": (C.c_int32, [_vp]),
     "dirac_batch_set_graph": (C.c_int32, [_vp, C.c_int32]),
     "dirac_batch_destroy": (C.c_int32, [_vp]),
+    "dirac_batch_schedule_count": (C.c_int32, [C.c_int32]),
+    "dirac_batch_get_schedule": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.POINTER(Schedule)]),
+    "dirac_batch_set_schedule": (C.c_int32, [_vp, C.c_int32, C.c_int32, C.POINTER(Schedule)]),
+    "dirac_batch_autotune": (C.c_int32, [_vp, C.c_int32]),
     "dirac3_footprint_bytes": (C.c_size_t, [C.POINTER(Grid3), C.POINTER(Metric3), C.POINTER(Pml), C.c_int32]),
     "dirac3_create": (C.c_int32, [C.POINTER(Grid3), C.POINTER(Metric3), C.POINTER(Pml), C.c_int32, _vp,
                                   C.c_size_t, _vp, C.POINTER(_vp)]),
@@ -526,6 +530,18 @@ class Batch:
 
     def set_graph(self, use_graph: bool):
         _check(lib.dirac_batch_set_graph(self.h, int(use_graph)))
+
+    def schedule(self, n: int, direction: int):
+        s = Schedule()
+        _check(lib.dirac_batch_get_schedule(self.h, n, direction, C.byref(s)))
+        return (s.radix, s.lines_per_wg, s.components_per_thread)
+
+    def set_schedule(self, n: int, direction: int, radix: int, components: int, lines: int = 0):
+        s = Schedule(radix, lines, components)
+        _check(lib.dirac_batch_set_schedule(self.h, n, direction, C.byref(s)))
+
+    def autotune(self, reps: int = 5):
+        _check(lib.dirac_batch_autotune(self.h, reps))
 
     def close(self):
         if self.h is not None and self.h.value:

@@ -40,11 +40,14 @@ def mixed_specs():
     return specs
 
 
-def single_path(D, spec, prec, steps):
+def single_path(D, spec, prec, steps, radix=None):
     s = D.Solver.from_spec(spec, precision=prec)
     for d, n in ((0, spec.n1), (1, spec.n2)):
-        r = batch_radix(n)
-        lines, cpt = [(l, c) for (rr, l, c) in D.schedules(n, prec, d) if rr == r][0]
+        r = batch_radix(n) if radix is None else radix[(n, d)]
+        match = [(l, c) for (rr, l, c) in D.schedules(n, prec, d) if rr == r]
+        if not match:
+            return None                          # no single-solve schedule with this radix
+        lines, cpt = match[0]
         s.set_schedule(d, r, lines, cpt)
     s.set_initial_spinor(W.initial_spinor(spec))
     s.step_n(steps)
@@ -178,3 +181,49 @@ def test_full_batch_workload_sampled(D):
         ob = s.observables()
         assert ob["finite"] == 1 and ob["step"] == 1000
     b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_every_batch_schedule_and_the_tuner(D, prec):
+    # every valid (radix, components) schedule of every size gives the bits of
+    # the single-solve kernel with that radix; the tuner restores the states
+    specs = mixed_specs()
+    steps = [5, 6, 3, 6, 2, 5, 4, 6, 4]
+    sizes = sorted({(sp.n1, 0) for sp in specs} | {(sp.n2, 1) for sp in specs})
+    for variant in range(4):
+        b = D.Batch(precision=prec, capacity=16)
+        radix = {}
+        for n, d in sizes:
+            cands = []
+            for r in (8, 4):
+                for c in (2, 1):
+                    try:
+                        b.set_schedule(n, d, r, c)
+                        cands.append((r, c))
+                    except D.DiracError:
+                        pass
+            assert len(cands) == D.lib.dirac_batch_schedule_count(n) and cands
+            r, c = cands[variant % len(cands)]
+            b.set_schedule(n, d, r, c)
+            assert b.schedule(n, d)[0] == r and b.schedule(n, d)[2] == c
+            radix[(n, d)] = r
+        solvers = []
+        for sp in specs:
+            s = D.Solver.from_spec(sp, precision=prec, stream=b.stream)
+            s.set_initial_spinor(W.initial_spinor(sp))
+            b.add(s)
+            solvers.append(s)
+        if variant == 3:
+            b.autotune(2)
+            radix = {(n, d): b.schedule(n, d)[0] for n, d in sizes}
+            assert all(s.observables()["step"] == 0 for s in solvers)
+        b.run(steps)
+        b.sync()
+        for sp, s, st in zip(specs, solvers, steps):
+            got, ref = s.get_spinor(), single_path(D, sp, prec, st, radix)
+            if ref is not None:
+                assert np.array_equal(got, ref), (variant, sp.n1, sp.n2)
+            else:
+                orc = O.run(W.initial_spinor(sp), O.build_tables(oracle_problem(sp)), st)
+                assert O.rel_l2(got, orc) < (1e-11 if prec == 0 else 2e-5), (variant, sp.n1, sp.n2)
+        b.close()
