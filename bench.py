@@ -42,7 +42,7 @@ def bytes_per_point(kind: str, dir_: int, precision: int) -> int:
     return state + (4 * sz + sz if dir_ == 0 else sz)
 
 
-def load_traffic(name: str):
+def load_traffic(name: str, instantiation: str | None = None):
     """HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
     (profiles/traffic.json), or None when absent or taken on other kernel sources."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
@@ -55,7 +55,13 @@ def load_traffic(name: str):
     from paper_1909_02894_amd.profiling import kernel_sources_digest
     if d.get("kernel_sources") != kernel_sources_digest():
         return None
-    return d.get("kernels", {}).get(name)
+    ent = d.get("kernels", {}).get(name)
+    if ent is None:
+        return None
+    rec = ent.get("by_instantiation", {}).get(instantiation) if instantiation else None
+    if rec is None:
+        return None
+    return dict(rec, instantiation=instantiation)
 
 
 def time_solve(D, spec, precision, steps, warmup, timed_steps, scheme=0):
@@ -99,7 +105,11 @@ def roofline_for(spec, kind, precision, r):
     byt = bytes_per_point(kind, dom, precision) * N
     achieved = byt / (avg[dom] * 1e-3) / 1e9
     name = f"{'x' if dom == 0 else 'y'}_stage_{'f64' if precision == 0 else 'f32'}_{spec.n1}x{spec.n2}_{kind}"
-    tr = load_traffic(name)
+    rr, ll, cc = r["sched"][dom]
+    mode = {"flat": 0, "flat_pml": 1, "curved": 2}[kind]
+    inst = (f"stage_kernel<{'double' if precision == 0 else 'float'}, {spec.n1 if dom == 0 else spec.n2}, {rr}, "
+            f"{ll}, {'true' if dom == 1 else 'false'}, {mode}, {cc}>")
+    tr = load_traffic(name, inst)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
             "kernel": name, "avg_launch_us": round(avg[dom] * 1e3, 3),

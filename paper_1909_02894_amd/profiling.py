@@ -98,18 +98,21 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, grid, out_json
            "calibration": {"copy_kernel": short_name(k0), "copy_bytes_each_way": COPY_BYTES,
                            "fetch_scale": f_scale, "write_scale": w_scale},
            "kernels": {}}
-    # several instantiations can map to one name (the autotuner tries them all);
-    # keep the one dispatched most often, i.e. the schedule the timed run used
-    best = {}
+    # several instantiations (schedules) map to one name -- the autotuner runs
+    # them all; keep each one, and mark the one dispatched most often
     for k in fe:
         name = bench_name(k, grid)
-        if name and k in wr and (name not in best or len(fe[k]) > len(fe[best[name]])):
-            best[name] = k
-    for name, k in best.items():
-        fb = statistics.median(fe[k]) * f_scale
-        wb = statistics.median(wr[k]) * w_scale
-        out["kernels"][name] = {"fetch_bytes": round(fb), "write_bytes": round(wb), "bytes": round(fb + wb),
-                                "dispatches": len(fe[k]), "instantiation": short_name(k)}
+        if not name or k not in wr:
+            continue
+        rec = {"fetch_bytes": round(statistics.median(fe[k]) * f_scale),
+               "write_bytes": round(statistics.median(wr[k]) * w_scale), "dispatches": len(fe[k])}
+        rec["bytes"] = rec["fetch_bytes"] + rec["write_bytes"]
+        ent = out["kernels"].setdefault(name, {"by_instantiation": {}})
+        ent["by_instantiation"][short_name(k)] = rec
+    for name, ent in out["kernels"].items():
+        top = max(ent["by_instantiation"].items(), key=lambda kv: kv[1]["dispatches"])
+        ent.update(top[1])
+        ent["instantiation"] = top[0]
     json.dump(out, open(out_json, "w"), indent=1)
     return out
 
