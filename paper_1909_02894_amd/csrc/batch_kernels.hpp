@@ -33,10 +33,13 @@ struct BatchDesc {
     cpx<T> e0u;
 };
 
+// One launch: the tiles of every active solve of one size group (one
+// transform length n along the phase's direction, hence one schedule).
 template <typename T>
 struct BatchPhase {
-    const BatchDesc<T>* desc;   // ordered by steps, longest first
-    const int* prefix;          // tile prefix of this direction (nactive + 1 entries used)
+    const BatchDesc<T>* desc;   // all solves of the run
+    const int* index;           // the group's solves (desc indices), longest run first
+    const int* prefix;          // tile prefix over the group (nactive + 1 entries used)
     int nactive;
     int total_tiles;
     int k;                      // step index within the run
@@ -97,18 +100,12 @@ __device__ __forceinline__ void batch_tile(const BatchDesc<T>& d, int tile, int 
     else stage_tile<T, N, R, L, COLS, 2, CPT>(p, tile, lds, twl);
 }
 
-// Dispatch on the solve's schedule (schedules not valid for N fall back to 0;
-// the host never selects them).
-template <typename T, bool COLS, int N>
-__device__ __forceinline__ void batch_tile_any(const BatchDesc<T>& d, int tile, int k, char* smem, int s) {
-    if constexpr (bsched_valid(N, 1)) { if (s == 1) { batch_tile<T, COLS, N, 1>(d, tile, k, smem); return; } }
-    if constexpr (bsched_valid(N, 2)) { if (s == 2) { batch_tile<T, COLS, N, 2>(d, tile, k, smem); return; } }
-    if constexpr (bsched_valid(N, 3)) { if (s == 3) { batch_tile<T, COLS, N, 3>(d, tile, k, smem); return; } }
-    batch_tile<T, COLS, N, 0>(d, tile, k, smem);
-}
-
-template <typename T, bool COLS>
-__global__ void __launch_bounds__(kBatchThreads) batch_stage_kernel(BatchPhase<T> ph) {
+// Phase kernel of one size group: the workgroup -> (solve, tile) map is a
+// binary search in the group's tile prefix.  One instantiation per (n,
+// schedule) keeps each kernel's register allocation to what its own schedule
+// needs (a kernel covering every size would take the largest).
+template <typename T, bool COLS, int N, int S>
+__global__ void __launch_bounds__(kBatchThreads) batch_group_kernel(BatchPhase<T> ph) {
     extern __shared__ __align__(16) char smem[];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     if (t >= ph.total_tiles) return;
@@ -117,35 +114,8 @@ __global__ void __launch_bounds__(kBatchThreads) batch_stage_kernel(BatchPhase<T
         const int mid = (lo + hi) >> 1;
         if (ph.prefix[mid] <= t) lo = mid; else hi = mid;
     }
-    const BatchDesc<T> d = ph.desc[lo];
-    const int tile = t - ph.prefix[lo];
-    const int s = d.sched[COLS ? 1 : 0];
-    switch (d.logn[COLS ? 1 : 0]) {
-        case 4: batch_tile_any<T, COLS, 16>(d, tile, ph.k, smem, s); break;
-        case 5: batch_tile_any<T, COLS, 32>(d, tile, ph.k, smem, s); break;
-        case 6: batch_tile_any<T, COLS, 64>(d, tile, ph.k, smem, s); break;
-        case 7: batch_tile_any<T, COLS, 128>(d, tile, ph.k, smem, s); break;
-        case 8: batch_tile_any<T, COLS, 256>(d, tile, ph.k, smem, s); break;
-        case 9: batch_tile_any<T, COLS, 512>(d, tile, ph.k, smem, s); break;
-        case 10: batch_tile_any<T, COLS, 1024>(d, tile, ph.k, smem, s); break;
-        default: batch_tile_any<T, COLS, 2048>(d, tile, ph.k, smem, s); break;
-    }
-}
-
-template <typename T, bool COLS, int N>
-constexpr size_t batch_smem_n(int s) {
-    return (s == 1 && bsched_valid(N, 1)) ? batch_smem_bytes_s<T, COLS, N, (bsched_valid(N, 1) ? 1 : 0)>()
-         : (s == 2 && bsched_valid(N, 2)) ? batch_smem_bytes_s<T, COLS, N, (bsched_valid(N, 2) ? 2 : 0)>()
-         : (s == 3 && bsched_valid(N, 3)) ? batch_smem_bytes_s<T, COLS, N, (bsched_valid(N, 3) ? 3 : 0)>()
-         : batch_smem_bytes_s<T, COLS, N, 0>();
-}
-
-template <typename T, bool COLS>
-constexpr size_t batch_smem_for(int logn, int s) {
-    return logn == 4 ? batch_smem_n<T, COLS, 16>(s) : logn == 5 ? batch_smem_n<T, COLS, 32>(s)
-         : logn == 6 ? batch_smem_n<T, COLS, 64>(s) : logn == 7 ? batch_smem_n<T, COLS, 128>(s)
-         : logn == 8 ? batch_smem_n<T, COLS, 256>(s) : logn == 9 ? batch_smem_n<T, COLS, 512>(s)
-         : logn == 10 ? batch_smem_n<T, COLS, 1024>(s) : batch_smem_n<T, COLS, 2048>(s);
+    const BatchDesc<T> d = ph.desc[ph.index[lo]];
+    batch_tile<T, COLS, N, S>(d, t - ph.prefix[lo], ph.k, smem);
 }
 
 }  // namespace dirac

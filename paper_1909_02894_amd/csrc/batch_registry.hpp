@@ -1,4 +1,6 @@
-// batch_registry.hpp -- the batch phase kernels per (precision, direction).
+// batch_registry.hpp -- the batch phase kernels per (precision, direction,
+// transform length, schedule), registered by the translation units that
+// instantiate them.
 #pragma once
 #include <stddef.h>
 
@@ -6,15 +8,16 @@ namespace dirac {
 
 struct BatchKernel {
     const void* fn = nullptr;
-    size_t (*smem)(int logn, int sched) = nullptr;
+    size_t smem = 0;           // dynamic LDS bytes of one workgroup
 };
 
-BatchKernel& batch_kernel(int prec, int dir);
+// logn in [4, 11], sched in [0, 4)
+BatchKernel& batch_kernel(int prec, int dir, int logn, int sched);
 
 struct BatchKernelRegistrar {
-    BatchKernelRegistrar(int prec, int dir, const void* fn, size_t (*smem)(int, int)) {
-        batch_kernel(prec, dir).fn = fn;
-        batch_kernel(prec, dir).smem = smem;
+    BatchKernelRegistrar(int prec, int dir, int logn, int sched, const void* fn, size_t smem) {
+        batch_kernel(prec, dir, logn, sched).fn = fn;
+        batch_kernel(prec, dir, logn, sched).smem = smem;
     }
 };
 

@@ -15,15 +15,20 @@
 
 namespace dirac {
 
-BatchKernel& batch_kernel(int prec, int dir) {
-    static BatchKernel k[2][2];
-    return k[prec][dir];
+BatchKernel& batch_kernel(int prec, int dir, int logn, int sched) {
+    static BatchKernel k[2][2][8][kBatchSchedules];
+    return k[prec][dir][logn - 4][sched];
 }
 
 static size_t align256b(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Per direction: the solves' desc indices grouped by size (capacity ints) and
+// the groups' tile prefixes (capacity + 8 ints: one extra entry per group).
+static size_t batch_dir_ints(int capacity) { return 2 * (size_t)capacity + 8; }
+
 static size_t batch_half_bytes(int capacity) {
-    return align256b((size_t)capacity * sizeof(BatchDesc<double>)) + align256b(2 * ((size_t)capacity + 1) * sizeof(int));
+    return align256b((size_t)capacity * sizeof(BatchDesc<double>)) +
+           align256b(2 * batch_dir_ints(capacity) * sizeof(int));
 }
 
 }  // namespace dirac
@@ -98,6 +103,14 @@ static int tiles_of(int n_line, int n_lines, int sched) {
     return (n_lines + L - 1) / L;
 }
 
+// The solves of one direction that share a transform length, longest run first.
+struct BatchGroup {
+    int logn;
+    std::vector<int> members;      // positions in the run's desc array
+    std::vector<int> prefix;       // tile prefix, members.size() + 1 entries
+    int index_off, prefix_off;     // offsets (ints) in the direction's device arrays
+};
+
 extern "C" {
 
 size_t dirac_batch_footprint_bytes(int32_t capacity) {
@@ -115,7 +128,8 @@ dirac_status dirac_batch_create(int32_t prec, int32_t capacity, void* device_buf
     if (bytes < dirac_batch_footprint_bytes(capacity))
         return fail(DIRAC_E_SIZE, "batch buffer of %zu bytes < footprint %zu", bytes, dirac_batch_footprint_bytes(capacity));
     for (int d = 0; d < 2; ++d)
-        if (!batch_kernel(prec, d).fn) return fail(DIRAC_E_DEVICE, "batch kernels not compiled");
+        for (int lg = 4; lg <= 11; ++lg)
+            if (!batch_kernel(prec, d, lg, 0).fn) return fail(DIRAC_E_DEVICE, "batch kernels not compiled");
     dirac_batch* b = new (std::nothrow) dirac_batch();
     if (!b) return fail(DIRAC_E_NOMEM, "host allocation failed");
     b->prec = prec;
@@ -137,7 +151,11 @@ dirac_status dirac_batch_create(int32_t prec, int32_t capacity, void* device_buf
         return fail(DIRAC_E_DEVICE, "event creation failed");
     }
     for (int d = 0; d < 2; ++d)
-        (void)hipFuncSetAttribute(batch_kernel(prec, d).fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        for (int lg = 4; lg <= 11; ++lg)
+            for (int sc = 0; sc < kBatchSchedules; ++sc)
+                if (batch_kernel(prec, d, lg, sc).fn)
+                    (void)hipFuncSetAttribute(batch_kernel(prec, d, lg, sc).fn,
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     *out = b;
     return DIRAC_OK;
 }
@@ -200,18 +218,35 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
     int h = reuse ? b->graph_half : b->which;
     char* dev = b->base + (size_t)h * b->half;
     const size_t desc_bytes = align256b((size_t)b->capacity * sizeof(BatchDesc<double>));
-    int* dprefix = reinterpret_cast<int*>(dev + desc_bytes);
-    std::vector<int> prefix[2];
-    size_t smem[2] = {0, 0};
+    int* dints = reinterpret_cast<int*>(dev + desc_bytes);
+    const size_t dir_ints = batch_dir_ints(b->capacity);
+    // size groups per direction; act is ordered longest run first, and a stable
+    // grouping keeps that order inside each group
+    std::vector<BatchGroup> groups[2];
     for (int d = 0; d < 2; ++d) {
-        prefix[d].assign(na + 1, 0);
-        for (int q = 0; q < na; ++q) {
-            const dirac_solver* s = b->slots[act[q]];
-            const int nl = d == 0 ? s->g.n1 : s->g.n2;
-            const int lines = d == 0 ? s->g.n2 : s->g.n1;
-            const int lg = __builtin_ctz((unsigned)nl);
-            prefix[d][q + 1] = prefix[d][q] + tiles_of(nl, lines, b->sched[d][lg]);
-            smem[d] = std::max(smem[d], batch_kernel(b->prec, d).smem(lg, b->sched[d][lg]));
+        for (int lg = 4; lg <= 11; ++lg) {
+            BatchGroup g{};
+            g.logn = lg;
+            for (int q = 0; q < na; ++q) {
+                const dirac_solver* s = b->slots[act[q]];
+                if (__builtin_ctz((unsigned)(d == 0 ? s->g.n1 : s->g.n2)) == lg) g.members.push_back(q);
+            }
+            if (g.members.empty()) continue;
+            g.prefix.assign(g.members.size() + 1, 0);
+            for (size_t m = 0; m < g.members.size(); ++m) {
+                const dirac_solver* s = b->slots[act[g.members[m]]];
+                const int nl = d == 0 ? s->g.n1 : s->g.n2;
+                const int lines = d == 0 ? s->g.n2 : s->g.n1;
+                g.prefix[m + 1] = g.prefix[m] + tiles_of(nl, lines, b->sched[d][lg]);
+            }
+            groups[d].push_back(std::move(g));
+        }
+        int io = 0, po = (int)b->capacity;
+        for (auto& g : groups[d]) {
+            g.index_off = io;
+            g.prefix_off = po;
+            io += (int)g.members.size();
+            po += (int)g.members.size() + 1;
         }
     }
     if (!reuse) {
@@ -226,55 +261,80 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
             else
                 fill_desc(reinterpret_cast<BatchDesc<float>*>(hs)[q], s, (int)steps[act[q]], b->sched);
         }
-        std::memcpy(hs + desc_bytes, prefix[0].data(), (na + 1) * sizeof(int));
-        std::memcpy(hs + desc_bytes + (b->capacity + 1) * sizeof(int), prefix[1].data(), (na + 1) * sizeof(int));
+        int* hints = reinterpret_cast<int*>(hs + desc_bytes);
+        for (int d = 0; d < 2; ++d) {
+            int* di = hints + d * dir_ints;
+            for (const auto& g : groups[d]) {
+                std::memcpy(di + g.index_off, g.members.data(), g.members.size() * sizeof(int));
+                std::memcpy(di + g.prefix_off, g.prefix.data(), g.prefix.size() * sizeof(int));
+            }
+        }
         BTRY(hipMemcpyAsync(dev, hs, b->half, hipMemcpyHostToDevice, b->stream), "upload batch descriptors");
         BTRY(hipEventRecord(b->stage_done[h], b->stream), "record staging event");
         b->which ^= 1;
     }
 
     const int64_t qmax = steps[act[0]];
-    auto phase_params = [&](int d, int64_t k, BatchPhase<double>& ph) {
-        int nactive = na;
-        while (nactive > 0 && steps[act[nactive - 1]] <= k) --nactive;
-        ph.desc = reinterpret_cast<const BatchDesc<double>*>(dev);
-        ph.prefix = dprefix + (d == 0 ? 0 : b->capacity + 1);
-        ph.nactive = nactive;
-        ph.total_tiles = prefix[d][nactive];
-        ph.k = (int)k;
+    // the launches of phase (step k, direction d): one per size group with work
+    struct GroupLaunch { const void* fn; size_t smem; BatchPhase<double> ph; };
+    auto phase_launches = [&](int d, int64_t k, std::vector<GroupLaunch>& out) {
+        out.clear();
+        for (const auto& g : groups[d]) {
+            int nactive = (int)g.members.size();
+            while (nactive > 0 && steps[act[g.members[nactive - 1]]] <= k) --nactive;
+            if (nactive == 0) continue;
+            const int sc = b->sched[d][g.logn];
+            GroupLaunch L;
+            L.fn = batch_kernel(b->prec, d, g.logn, sc).fn;
+            L.smem = batch_kernel(b->prec, d, g.logn, sc).smem;
+            L.ph.desc = reinterpret_cast<const BatchDesc<double>*>(dev);
+            L.ph.index = dints + d * dir_ints + g.index_off;
+            L.ph.prefix = dints + d * dir_ints + g.prefix_off;
+            L.ph.nactive = nactive;
+            L.ph.total_tiles = g.prefix[nactive];
+            L.ph.k = (int)k;
+            out.push_back(L);
+        }
     };
     // BatchPhase<T> has the same layout for both T (pointers and ints only).
     static_assert(sizeof(BatchPhase<double>) == sizeof(BatchPhase<float>), "phase layout");
 
+    std::vector<GroupLaunch> gl;
     if (!b->use_graph) {
         for (int64_t k = 0; k < qmax; ++k) {
             for (int d = 0; d < 2; ++d) {
-                BatchPhase<double> ph;
-                phase_params(d, k, ph);
-                void* args[] = {&ph};
-                BTRY(hipLaunchKernel(batch_kernel(b->prec, d).fn, dim3(ph.total_tiles), dim3(kBatchThreads), args,
-                                     smem[d], b->stream), "launch batch phase");
+                phase_launches(d, k, gl);
+                for (auto& L : gl) {
+                    void* args[] = {&L.ph};
+                    BTRY(hipLaunchKernel(L.fn, dim3(L.ph.total_tiles), dim3(kBatchThreads), args, L.smem, b->stream),
+                         "launch batch phase");
+                }
             }
         }
     } else {
         if (!reuse) {
             BTRY(hipGraphCreate(&b->graph, 0), "hipGraphCreate");
-            hipGraphNode_t prev = nullptr;
+            // the group launches of one phase are independent; each depends on
+            // every launch of the previous phase
+            std::vector<hipGraphNode_t> prev, cur;
             for (int64_t k = 0; k < qmax; ++k) {
                 for (int d = 0; d < 2; ++d) {
-                    BatchPhase<double> ph;
-                    phase_params(d, k, ph);
-                    void* args[] = {&ph};
-                    hipKernelNodeParams kp{};
-                    kp.func = const_cast<void*>(batch_kernel(b->prec, d).fn);
-                    kp.gridDim = dim3(ph.total_tiles);
-                    kp.blockDim = dim3(kBatchThreads);
-                    kp.sharedMemBytes = (unsigned)smem[d];
-                    kp.kernelParams = args;
-                    hipGraphNode_t node;
-                    BTRY(hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp),
-                         "hipGraphAddKernelNode");
-                    prev = node;
+                    phase_launches(d, k, gl);
+                    cur.clear();
+                    for (auto& L : gl) {
+                        void* args[] = {&L.ph};
+                        hipKernelNodeParams kp{};
+                        kp.func = const_cast<void*>(L.fn);
+                        kp.gridDim = dim3(L.ph.total_tiles);
+                        kp.blockDim = dim3(kBatchThreads);
+                        kp.sharedMemBytes = (unsigned)L.smem;
+                        kp.kernelParams = args;
+                        hipGraphNode_t node;
+                        BTRY(hipGraphAddKernelNode(&node, b->graph, prev.empty() ? nullptr : prev.data(), prev.size(),
+                                                   &kp), "hipGraphAddKernelNode");
+                        cur.push_back(node);
+                    }
+                    prev.swap(cur);
                 }
             }
             BTRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");

@@ -53,14 +53,31 @@ __device__ __forceinline__ cpx<double> csqrt_d(cpx<double> z) {
     return {0.5 * fabs(z.im) / t, copysign(t, z.im)};
 }
 
+// C = cosh r = sum_k z^k / (2k)!, D = sinh r / r = sum_k z^k / (2k+1)!, z = r^2,
+// the first K terms in Horner form with constant coefficients.
+template <int K>
+__device__ __forceinline__ void em_series(cpx<double> z, cpx<double>& C, cpx<double>& D) {
+    cpx<double> c{1.0, 0.0}, d{1.0, 0.0};
+#pragma unroll
+    for (int k = K - 1; k >= 1; --k) {
+        const double fc = 1.0 / ((2.0 * k - 1.0) * (2.0 * k)), fd = 1.0 / ((2.0 * k) * (2.0 * k + 1.0));
+        const cpx<double> zc = cmul_d(z, c), zd = cmul_d(z, d);
+        c = cpx<double>{1.0 + fc * zc.re, fc * zc.im};
+        d = cpx<double>{1.0 + fd * zd.re, fd * zd.im};
+    }
+    C = c;
+    D = d;
+}
+
 __device__ __forceinline__ Mat2 em_exponential(const double (&q)[6], double fA, double fV) {
     const cpx<double> ux{q[0], q[3] * fA}, uy{q[1], q[4] * fA}, uz{0.0, -q[2]};
     const cpx<double> s2 = cmul_d(ux, ux) + cmul_d(uy, uy) + cmul_d(uz, uz);
     cpx<double> C, D;
-    if (hypot(s2.re, s2.im) < 1e-8) {
-        const cpx<double> s4 = cmul_d(s2, s2);
-        C = cpx<double>{1.0 + s2.re / 2.0 + s4.re / 24.0, s2.im / 2.0 + s4.im / 24.0};
-        D = cpx<double>{1.0 + s2.re / 6.0 + s4.re / 120.0, s2.im / 6.0 + s4.im / 120.0};
+    const double a2 = s2.re * s2.re + s2.im * s2.im;       // |u.u|^2
+    if (a2 < 1e-8) {
+        em_series<4>(s2, C, D);                              // |u.u| < 1e-4: next term < 3e-21
+    } else if (a2 < 0.0625) {
+        em_series<9>(s2, C, D);                              // |u.u| < 1/4: next term < 1e-21
     } else {
         const cpx<double> r = csqrt_d(s2);
         double sn, cs;
