@@ -269,6 +269,11 @@ def cpu_baseline(spec, steps):
             "seconds": round(dt, 2)}
 
 
+def progress(msg: str):
+    """One line on stderr before each GPU stage, so a failing run names its stage."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -301,6 +306,7 @@ def main():
     spec = W.curved_bump(n=512, seed=1909, steps=args.steps)
     K = args.steps
     timed = min(K, 500)
+    progress(f"headline: curved 512x512 FP64, {K} steps")
     r64 = time_solve(D, spec, D.FP64, K, args.warmup, timed)
     N = spec.n1 * spec.n2
     value = N * K / (r64["ms"] * 1e-3)
@@ -324,38 +330,49 @@ def main():
     }
     variants = {}
     if not args.skip_variants:
+        progress("variant: same workload FP32")
         r32 = time_solve(D, spec, D.FP32, K, args.warmup, timed)
         variants["fp32_same_workload"] = {
             "value": N * K / (r32["ms"] * 1e-3), "ms_per_step": r32["ms"] / K, "dtype": "f32",
             "roofline": roofline_for(spec, "curved", D.FP32, r32),
             "schedule": {"x": r32["sched"][0], "y": r32["sched"][1]}}
         big = W.flat_small(n=4096, steps=200)
+        progress("variant: flat 4096x4096 FP32")
         rb = time_solve(D, big, D.FP32, 200, 10, 100)
         variants["fp32_flat_4096"] = {
             "value": big.n1 * big.n2 * 200 / (rb["ms"] * 1e-3), "ms_per_step": rb["ms"] / 200, "dtype": "f32",
             "note": "flat 4096x4096 packet solve, 256 MiB state (beyond the Infinity Cache)",
             "roofline": roofline_for(big, "flat", D.FP32, rb),
             "schedule": {"x": rb["sched"][0], "y": rb["sched"][1]}}
+        progress("variant: second-order directional step FP64")
         rc = time_solve(D, spec, D.FP64, 500, args.warmup, 100, scheme=D.SCHEME_EXP_SPLIT_2BIS)
         variants["step2bis_corrected_fp64"] = {
             "value": N * 500 / (rc["ms"] * 1e-3), "ms_per_step": rc["ms"] / 500, "dtype": "f64",
             "note": "second-order directional step (three inverse transforms per direction), same workload",
             "x_avg_us": round(rc["kernel_us"][0], 3), "y_avg_us": round(rc["kernel_us"][1], 3)}
+        progress("variant: Scheme I")
         variants["scheme1_cn_gmres"] = bench_cn(D, spec)
+        progress("variant: potentials")
         variants["em_potentials_fp64"] = bench_em(D, W, spec)
+        progress("variant: 3-D 256^3 FP32")
         variants["fp32_3d_flat_256"] = bench_3d(D, W, 256, D.FP32, False)
+        progress("variant: 3-D 128^3 FP64")
         variants["fp64_3d_curved_128"] = bench_3d(D, W, 128, D.FP64, True)
+        progress("variant: batch of 256 solves")
         bt = bench_batch(D, W)
         variants["batch_256_mixed"] = bt
         # serving at ~0.7x the measured batch capacity
         mean_work = np.mean([n * n for n in (64, 128, 256, 512, 1024)]) * (200 + 5000) / 2.0
         rate = 0.7 * bt["value"] / mean_work
+        progress("variant: serving, 288 GB budget")
         variants["serve_poisson"] = bench_serve(100, rate, 288 << 30)
+        progress("variant: serving, 2 GB budget")
         variants["serve_poisson_2GB"] = bench_serve(40, rate, 2 << 30, seed=5001)
         out["latency"] = {"p50_s": variants["serve_poisson"]["p50_s"], "p99_s": variants["serve_poisson"]["p99_s"],
                           "source": "serve_poisson"}
     out["variants"] = variants
     if not args.skip_cpu:
+        progress("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

@@ -314,13 +314,12 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
     } else {
         if (!reuse) {
             BTRY(hipGraphCreate(&b->graph, 0), "hipGraphCreate");
-            // the group launches of one phase are independent; each depends on
-            // every launch of the previous phase
-            std::vector<hipGraphNode_t> prev, cur;
+            // one chain: the group launches of a phase follow each other (they are
+            // independent, but a graph with parallel branches is not used here)
+            hipGraphNode_t prev = nullptr;
             for (int64_t k = 0; k < qmax; ++k) {
                 for (int d = 0; d < 2; ++d) {
                     phase_launches(d, k, gl);
-                    cur.clear();
                     for (auto& L : gl) {
                         void* args[] = {&L.ph};
                         hipKernelNodeParams kp{};
@@ -330,11 +329,10 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
                         kp.sharedMemBytes = (unsigned)L.smem;
                         kp.kernelParams = args;
                         hipGraphNode_t node;
-                        BTRY(hipGraphAddKernelNode(&node, b->graph, prev.empty() ? nullptr : prev.data(), prev.size(),
-                                                   &kp), "hipGraphAddKernelNode");
-                        cur.push_back(node);
+                        BTRY(hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp),
+                             "hipGraphAddKernelNode");
+                        prev = node;
                     }
-                    prev.swap(cur);
                 }
             }
             BTRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");

@@ -351,7 +351,11 @@ hipError_t launch3(Launch3& L, hipStream_t st) {
 }
 
 void drop_graph3(dirac3_solver* s) {
-    if (s->gexec) { (void)hipGraphExecDestroy(s->gexec); s->gexec = nullptr; }
+    if (s->gexec) {
+        (void)hipStreamSynchronize(s->stream);   // a replay may still be in flight
+        (void)hipGraphExecDestroy(s->gexec);
+        s->gexec = nullptr;
+    }
     if (s->graph) { (void)hipGraphDestroy(s->graph); s->graph = nullptr; }
 }
 

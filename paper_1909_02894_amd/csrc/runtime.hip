@@ -376,8 +376,13 @@ static hipError_t do_launch(Launch& L, hipStream_t st) {
     return hipLaunchKernel(L.fn, L.grid, L.block, args, 0, st);
 }
 
+// The stream is synchronised first: a replay of the graph may still be in flight.
 static void drop_graph(dirac_solver* s) {
-    if (s->gexec) { (void)hipGraphExecDestroy(s->gexec); s->gexec = nullptr; }
+    if (s->gexec) {
+        (void)hipStreamSynchronize(s->stream);
+        (void)hipGraphExecDestroy(s->gexec);
+        s->gexec = nullptr;
+    }
     if (s->graph) { (void)hipGraphDestroy(s->graph); s->graph = nullptr; }
 }
 
@@ -729,6 +734,7 @@ dirac_status dirac_get_spinor(dirac_solver* s, double* psi_host_out) {
 
 dirac_status dirac_destroy(dirac_solver* s) {
     if (!s) return fail(DIRAC_E_ARG, "null solver");
+    (void)hipStreamSynchronize(s->stream);      // nothing of this solve may be in flight
     drop_graph(s);
     for (auto& ev : s->events) (void)hipEventDestroy(ev);
     delete s;
