@@ -49,4 +49,6 @@ BGK(2048, 1)
 BGK(2048, 2)
 BGK(2048, 3)
 
+static BatchMultiRegistrar breg_multi(1, 1, reinterpret_cast<const void*>(&batch_multi_kernel<float, true>));
+
 }  // namespace dirac

@@ -49,4 +49,6 @@ BGK(2048, 1)
 BGK(2048, 2)
 BGK(2048, 3)
 
+static BatchMultiRegistrar breg_multi(0, 0, reinterpret_cast<const void*>(&batch_multi_kernel<double, false>));
+
 }  // namespace dirac

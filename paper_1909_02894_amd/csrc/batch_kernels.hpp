@@ -65,6 +65,23 @@ __host__ __device__ constexpr bool bsched_valid(int n, int s) {
 __host__ __device__ constexpr int bsched_lines(int n, int s) { return kBatchThreads / bsched_threads_per_line(n, s); }
 __host__ __device__ constexpr int batch_lines(int n) { return bsched_lines(n, 0); }
 
+constexpr int kBatchMaxGroups = 8;
+
+// One launch covering several size groups (used when some group is too small
+// to fill the GPU on its own): group g owns tiles [start[g], start[g+1]).
+template <typename T>
+struct BatchMultiPhase {
+    const BatchDesc<T>* desc;
+    const int* index[kBatchMaxGroups];
+    const int* prefix[kBatchMaxGroups];
+    int nactive[kBatchMaxGroups];
+    int logn[kBatchMaxGroups];
+    int sched[kBatchMaxGroups];
+    int start[kBatchMaxGroups + 1];
+    int ngroups;
+    int k;
+};
+
 template <typename T, bool COLS, int N, int S>
 __host__ __device__ constexpr size_t batch_smem_bytes_s() {
     return (LineFFT<T, N, bsched_radix(N, S), bsched_lines(N, S), COLS, bsched_cpt(S)>::LDS_ELEMS +
@@ -116,6 +133,45 @@ __global__ void __launch_bounds__(kBatchThreads) batch_group_kernel(BatchPhase<T
     }
     const BatchDesc<T> d = ph.desc[ph.index[lo]];
     batch_tile<T, COLS, N, S>(d, t - ph.prefix[lo], ph.k, smem);
+}
+
+template <typename T, bool COLS, int N>
+__device__ __forceinline__ void batch_tile_sched(const BatchDesc<T>& d, int tile, int k, char* smem, int s) {
+    if constexpr (bsched_valid(N, 1)) { if (s == 1) { batch_tile<T, COLS, N, 1>(d, tile, k, smem); return; } }
+    if constexpr (bsched_valid(N, 2)) { if (s == 2) { batch_tile<T, COLS, N, 2>(d, tile, k, smem); return; } }
+    if constexpr (bsched_valid(N, 3)) { if (s == 3) { batch_tile<T, COLS, N, 3>(d, tile, k, smem); return; } }
+    batch_tile<T, COLS, N, 0>(d, tile, k, smem);
+}
+
+// Phase kernel over several size groups: find the group by its tile range,
+// then the solve by a binary search in the group's prefix.
+template <typename T, bool COLS>
+__global__ void __launch_bounds__(kBatchThreads) batch_multi_kernel(BatchMultiPhase<T> ph) {
+    extern __shared__ __align__(16) char smem[];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t >= ph.start[ph.ngroups]) return;
+    int g = 0;
+    while (g + 1 < ph.ngroups && t >= ph.start[g + 1]) ++g;
+    const int tl = t - ph.start[g];
+    const int* prefix = ph.prefix[g];
+    int lo = 0, hi = ph.nactive[g];
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= tl) lo = mid; else hi = mid;
+    }
+    const BatchDesc<T> d = ph.desc[ph.index[g][lo]];
+    const int tile = tl - prefix[lo];
+    const int s = ph.sched[g];
+    switch (ph.logn[g]) {
+        case 4: batch_tile_sched<T, COLS, 16>(d, tile, ph.k, smem, s); break;
+        case 5: batch_tile_sched<T, COLS, 32>(d, tile, ph.k, smem, s); break;
+        case 6: batch_tile_sched<T, COLS, 64>(d, tile, ph.k, smem, s); break;
+        case 7: batch_tile_sched<T, COLS, 128>(d, tile, ph.k, smem, s); break;
+        case 8: batch_tile_sched<T, COLS, 256>(d, tile, ph.k, smem, s); break;
+        case 9: batch_tile_sched<T, COLS, 512>(d, tile, ph.k, smem, s); break;
+        case 10: batch_tile_sched<T, COLS, 1024>(d, tile, ph.k, smem, s); break;
+        default: batch_tile_sched<T, COLS, 2048>(d, tile, ph.k, smem, s); break;
+    }
 }
 
 }  // namespace dirac

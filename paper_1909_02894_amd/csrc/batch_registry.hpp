@@ -13,6 +13,12 @@ struct BatchKernel {
 
 // logn in [4, 11], sched in [0, 4)
 BatchKernel& batch_kernel(int prec, int dir, int logn, int sched);
+// the kernel that covers several size groups in one launch
+const void*& batch_multi_kernel_fn(int prec, int dir);
+
+struct BatchMultiRegistrar {
+    BatchMultiRegistrar(int prec, int dir, const void* fn) { batch_multi_kernel_fn(prec, dir) = fn; }
+};
 
 struct BatchKernelRegistrar {
     BatchKernelRegistrar(int prec, int dir, int logn, int sched, const void* fn, size_t smem) {

@@ -20,6 +20,16 @@ BatchKernel& batch_kernel(int prec, int dir, int logn, int sched) {
     return k[prec][dir][logn - 4][sched];
 }
 
+const void*& batch_multi_kernel_fn(int prec, int dir) {
+    static const void* f[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    return f[prec][dir];
+}
+
+// A size group launched on its own should fill the GPU: at least this many
+// 256-thread tiles (four per compute unit); otherwise the phase's groups share
+// one launch of the multi-group kernel.
+constexpr int kMinGroupTiles = 1024;
+
 static size_t align256b(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Per direction: the solves' desc indices grouped by size (capacity ints) and
@@ -127,9 +137,11 @@ dirac_status dirac_batch_create(int32_t prec, int32_t capacity, void* device_buf
     if (!device_buffer) return fail(DIRAC_E_ARG, "null device buffer");
     if (bytes < dirac_batch_footprint_bytes(capacity))
         return fail(DIRAC_E_SIZE, "batch buffer of %zu bytes < footprint %zu", bytes, dirac_batch_footprint_bytes(capacity));
-    for (int d = 0; d < 2; ++d)
+    for (int d = 0; d < 2; ++d) {
         for (int lg = 4; lg <= 11; ++lg)
             if (!batch_kernel(prec, d, lg, 0).fn) return fail(DIRAC_E_DEVICE, "batch kernels not compiled");
+        if (!batch_multi_kernel_fn(prec, d)) return fail(DIRAC_E_DEVICE, "batch kernels not compiled");
+    }
     dirac_batch* b = new (std::nothrow) dirac_batch();
     if (!b) return fail(DIRAC_E_NOMEM, "host allocation failed");
     b->prec = prec;
@@ -156,6 +168,9 @@ dirac_status dirac_batch_create(int32_t prec, int32_t capacity, void* device_buf
                 if (batch_kernel(prec, d, lg, sc).fn)
                     (void)hipFuncSetAttribute(batch_kernel(prec, d, lg, sc).fn,
                                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    for (int d = 0; d < 2; ++d)
+        (void)hipFuncSetAttribute(batch_multi_kernel_fn(prec, d), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
     *out = b;
     return DIRAC_OK;
 }
@@ -275,29 +290,65 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
     }
 
     const int64_t qmax = steps[act[0]];
-    // the launches of phase (step k, direction d): one per size group with work
-    struct GroupLaunch { const void* fn; size_t smem; BatchPhase<double> ph; };
+    // the launches of phase (step k, direction d): one per size group with
+    // work, or -- when some group is too small to fill the GPU alone -- one
+    // launch of the multi-group kernel over all of them
+    struct GroupLaunch {
+        const void* fn;
+        size_t smem;
+        int tiles;
+        bool multi;
+        BatchPhase<double> ph;
+        BatchMultiPhase<double> mph;
+    };
     auto phase_launches = [&](int d, int64_t k, std::vector<GroupLaunch>& out) {
         out.clear();
+        int min_tiles = 1 << 30;
         for (const auto& g : groups[d]) {
             int nactive = (int)g.members.size();
             while (nactive > 0 && steps[act[g.members[nactive - 1]]] <= k) --nactive;
             if (nactive == 0) continue;
             const int sc = b->sched[d][g.logn];
-            GroupLaunch L;
+            GroupLaunch L{};
             L.fn = batch_kernel(b->prec, d, g.logn, sc).fn;
             L.smem = batch_kernel(b->prec, d, g.logn, sc).smem;
+            L.multi = false;
             L.ph.desc = reinterpret_cast<const BatchDesc<double>*>(dev);
             L.ph.index = dints + d * dir_ints + g.index_off;
             L.ph.prefix = dints + d * dir_ints + g.prefix_off;
             L.ph.nactive = nactive;
             L.ph.total_tiles = g.prefix[nactive];
             L.ph.k = (int)k;
+            L.tiles = L.ph.total_tiles;
+            L.mph.logn[0] = g.logn;       // kept for the merge below
+            L.mph.sched[0] = sc;
+            min_tiles = std::min(min_tiles, L.tiles);
             out.push_back(L);
         }
+        if (out.size() > 1 && min_tiles < kMinGroupTiles) {
+            GroupLaunch M{};
+            M.fn = batch_multi_kernel_fn(b->prec, d);
+            M.multi = true;
+            M.mph.desc = reinterpret_cast<const BatchDesc<double>*>(dev);
+            M.mph.ngroups = (int)out.size();
+            M.mph.k = (int)k;
+            M.mph.start[0] = 0;
+            for (size_t g = 0; g < out.size(); ++g) {
+                M.mph.index[g] = out[g].ph.index;
+                M.mph.prefix[g] = out[g].ph.prefix;
+                M.mph.nactive[g] = out[g].ph.nactive;
+                M.mph.logn[g] = out[g].mph.logn[0];
+                M.mph.sched[g] = out[g].mph.sched[0];
+                M.mph.start[g + 1] = M.mph.start[g] + out[g].tiles;
+                M.smem = std::max(M.smem, out[g].smem);
+            }
+            M.tiles = M.mph.start[out.size()];
+            out.assign(1, M);
+        }
     };
-    // BatchPhase<T> has the same layout for both T (pointers and ints only).
+    // BatchPhase<T> / BatchMultiPhase<T> have the same layout for both T.
     static_assert(sizeof(BatchPhase<double>) == sizeof(BatchPhase<float>), "phase layout");
+    static_assert(sizeof(BatchMultiPhase<double>) == sizeof(BatchMultiPhase<float>), "phase layout");
 
     std::vector<GroupLaunch> gl;
     if (!b->use_graph) {
@@ -305,8 +356,8 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
             for (int d = 0; d < 2; ++d) {
                 phase_launches(d, k, gl);
                 for (auto& L : gl) {
-                    void* args[] = {&L.ph};
-                    BTRY(hipLaunchKernel(L.fn, dim3(L.ph.total_tiles), dim3(kBatchThreads), args, L.smem, b->stream),
+                    void* args[] = {L.multi ? static_cast<void*>(&L.mph) : static_cast<void*>(&L.ph)};
+                    BTRY(hipLaunchKernel(L.fn, dim3(L.tiles), dim3(kBatchThreads), args, L.smem, b->stream),
                          "launch batch phase");
                 }
             }
@@ -321,10 +372,10 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
                 for (int d = 0; d < 2; ++d) {
                     phase_launches(d, k, gl);
                     for (auto& L : gl) {
-                        void* args[] = {&L.ph};
+                        void* args[] = {L.multi ? static_cast<void*>(&L.mph) : static_cast<void*>(&L.ph)};
                         hipKernelNodeParams kp{};
                         kp.func = const_cast<void*>(L.fn);
-                        kp.gridDim = dim3(L.ph.total_tiles);
+                        kp.gridDim = dim3(L.tiles);
                         kp.blockDim = dim3(kBatchThreads);
                         kp.sharedMemBytes = (unsigned)L.smem;
                         kp.kernelParams = args;
