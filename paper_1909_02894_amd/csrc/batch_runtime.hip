@@ -93,7 +93,7 @@ static void fill_desc(BatchDesc<T>& d, const dirac_solver* s, int steps, const i
     d.a = s->curved ? reinterpret_cast<const T*>(base + s->lay.a) : nullptr;
     d.E = s->curved ? reinterpret_cast<const T*>(base + s->lay.E) : nullptr;
     for (int ax = 0; ax < 2; ++ax) {
-        d.inv_s[ax] = s->pml ? reinterpret_cast<const T*>(base + s->lay.inv_s[ax]) : nullptr;
+        d.inv_s[ax] = reinterpret_cast<const T*>(base + s->lay.inv_s[ax]);   // ones without a layer
         d.K[ax] = reinterpret_cast<const cpx<T>*>(base + s->lay.K[ax]);
         d.tw[ax] = reinterpret_cast<const cpx<T>*>(base + s->lay.tw[ax]);
     }

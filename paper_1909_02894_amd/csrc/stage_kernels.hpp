@@ -24,12 +24,13 @@ struct StageParams {
     T* psi;                      // state, 4 T per point, row pitch n1 points
     const T* a;                  // a(x) per point, or null (a = 1)
     const T* E;                  // half-step exponential per point (e0 re, im, e1 re, im), or null
-    const T* inv_s;              // 1/S along the line direction (n entries), or null (no layer)
+    const T* inv_s;              // 1/S along the line direction (n entries; ones without a layer)
     const cpx<T>* K;             // symbol per mode, already scaled by 1/n
     const cpx<T>* tw;            // exp(-2 pi i k / n), k < n
     int n1;                      // points per row
     int nlines;                  // lines of this direction
-    int e_pre;                   // Step-1 exponentials applied before the transform (0, 1, 2)
+    int e_pre;                   // Step-1 exponentials applied before the transform: 1 or 2 in
+                                 // direction-x launches (which load E up front), 0 in direction y
     int e_post;                  // Step-5 exponential applied after the blend (0, 1)
     cpx<T> e0u;                  // uniform e0 when E is null (flat: e^{-i dt m c^2 / 2})
 };
@@ -53,8 +54,34 @@ struct ObsParams {
     double a1, a2, h1, h2;
 };
 
+// Global-memory access through address-space-1 pointers.  Pointers that reach
+// a kernel inside a descriptor table (the batch engine) are otherwise generic
+// and compile to flat instructions, whose completion is tracked by the memory
+// and the LDS counters together, so every LDS wait would also wait for memory.
+// Only scalar and clang vector element types are loaded this way: a struct
+// copy goes through a generic reference again.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) { return *(const __attribute__((address_space(1))) T*)p; }
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) { *(__attribute__((address_space(1))) T*)p = v; }
+__device__ __forceinline__ cpx<float> gld(const cpx<float>* p) {
+    const f2v v = gld(reinterpret_cast<const f2v*>(p));
+    return {v.x, v.y};
+}
+__device__ __forceinline__ cpx<double> gld(const cpx<double>* p) {
+    const d2v v = gld(reinterpret_cast<const d2v*>(p));
+    return {v.x, v.y};
+}
+
 // Point access with 32-bit byte offsets (every supported state is < 2 GiB), so
 // addresses are formed as a scalar base plus a 32-bit vector offset.
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, uint32_t elem) {
+    return gld(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + elem * (uint32_t)sizeof(T)));
+}
 template <typename T>
 __device__ __forceinline__ const T* at(const T* base, uint32_t elem) {
     return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + elem * (uint32_t)sizeof(T));
@@ -64,24 +91,18 @@ __device__ __forceinline__ const T* at(const T* base, uint32_t elem) {
 template <typename T>
 __device__ __forceinline__ cpx<T> load_comp(const T* p, uint32_t idx, int c) {
     const char* b = reinterpret_cast<const char*>(p) + idx * (uint32_t)(4 * sizeof(T)) + c * (uint32_t)(2 * sizeof(T));
-    if constexpr (sizeof(T) == 8) {
-        const double2 a = *reinterpret_cast<const double2*>(b);
-        return {(T)a.x, (T)a.y};
-    } else {
-        const float2 a = *reinterpret_cast<const float2*>(b);
-        return {(T)a.x, (T)a.y};
-    }
+    return gld(reinterpret_cast<const cpx<T>*>(b));
 }
 // Both components of a point in one access (16 B for FP32) or two (FP64).
 template <typename T>
 __device__ __forceinline__ void load_point(const T* p, uint32_t idx, cpx<T>& u, cpx<T>& v) {
     const char* b = reinterpret_cast<const char*>(p) + idx * (uint32_t)(4 * sizeof(T));
     if constexpr (sizeof(T) == 8) {
-        const double2 A = reinterpret_cast<const double2*>(b)[0], B = reinterpret_cast<const double2*>(b)[1];
+        const d2v A = gld(reinterpret_cast<const d2v*>(b)), B = gld(reinterpret_cast<const d2v*>(b) + 1);
         u = {(T)A.x, (T)A.y};
         v = {(T)B.x, (T)B.y};
     } else {
-        const float4 A = *reinterpret_cast<const float4*>(b);
+        const f4v A = gld(reinterpret_cast<const f4v*>(b));
         u = {(T)A.x, (T)A.y};
         v = {(T)A.z, (T)A.w};
     }
@@ -90,17 +111,17 @@ template <typename T>
 __device__ __forceinline__ void store_point(T* p, uint32_t idx, cpx<T> u, cpx<T> v) {
     char* b = reinterpret_cast<char*>(p) + idx * (uint32_t)(4 * sizeof(T));
     if constexpr (sizeof(T) == 8) {
-        reinterpret_cast<double2*>(b)[0] = make_double2(u.re, u.im);
-        reinterpret_cast<double2*>(b)[1] = make_double2(v.re, v.im);
+        gst(reinterpret_cast<d2v*>(b), d2v{u.re, u.im});
+        gst(reinterpret_cast<d2v*>(b) + 1, d2v{v.re, v.im});
     } else {
-        *reinterpret_cast<float4*>(b) = make_float4(u.re, u.im, v.re, v.im);
+        gst(reinterpret_cast<f4v*>(b), f4v{u.re, u.im, v.re, v.im});
     }
 }
 template <typename T>
 __device__ __forceinline__ void store_comp(T* p, uint32_t idx, int c, cpx<T> v) {
     char* b = reinterpret_cast<char*>(p) + idx * (uint32_t)(4 * sizeof(T)) + c * (uint32_t)(2 * sizeof(T));
-    if constexpr (sizeof(T) == 8) *reinterpret_cast<double2*>(b) = make_double2(v.re, v.im);
-    else *reinterpret_cast<float2*>(b) = make_float2(v.re, v.im);
+    if constexpr (sizeof(T) == 8) gst(reinterpret_cast<d2v*>(b), d2v{v.re, v.im});
+    else gst(reinterpret_cast<f2v*>(b), f2v{v.re, v.im});
 }
 
 // Workgroup -> tile map that keeps neighbouring tiles on one XCD.  Workgroups
@@ -141,8 +162,13 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     const typename F::Coord c = F::coord(threadIdx.x);
     const int line = tile * L + c.l;
     const bool valid = line < p.nlines;
+    // loads read a clamped line (always in bounds, results unused past the
+    // last line) so that they carry no branches; stores are guarded
+    const int lline = valid ? line : p.nlines - 1;
     const uint32_t n1 = (uint32_t)p.n1;
-    auto gidx = [&](int pos) -> uint32_t { return COLS ? (uint32_t)pos * n1 + line : (uint32_t)line * n1 + pos; };
+    auto gidx = [&](int ln, int pos) -> uint32_t {
+        return COLS ? (uint32_t)pos * n1 + ln : (uint32_t)ln * n1 + pos;
+    };
     // v[cc][r] <- f(own, other, component, r) for every carried component
     auto mix = [&](cpx<T> (&a)[CPT][R], auto&& f) {
 #pragma unroll
@@ -158,49 +184,31 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
         }
     };
 
+    // Every global load of the tile is issued in one branch-free block before
+    // the first use of any of them, so the tile pays one memory latency:
+    // state, Step-1 exponential, twiddles, symbols and blend weights.
     cpx<T> v[CPT][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const uint32_t q = gidx(c.j + r * P);
-        if constexpr (CPT == 1) {
-            v[0][r] = valid ? load_comp(p.psi, q, c.comp) : cpx<T>{0, 0};
-        } else {
-            v[0][r] = v[1][r] = cpx<T>{0, 0};
-            if (valid) load_point(p.psi, q, v[0][r], v[1][r]);
-        }
-    }
-    const cpx<T>* tw = p.tw;
-    if constexpr (TS::ON) {
-        for (int k = threadIdx.x; k < N; k += F::NT) twl[k] = p.tw[k];
-        tw = twl;
-    }
-    cpx<T> kk[PF ? R : 1];
-    T bb[PF && BLEND ? R : 1];
-    auto blend_weight = [&](int r) -> T {
-        T b = T(1);
-        if constexpr (MODE == 2) b = valid ? *at(p.a, gidx(c.j + r * P)) : T(0);
-        if (MODE == 1 || p.inv_s) b *= p.inv_s[c.j + r * P];
-        return b;
-    };
-    if constexpr (PF) {
-#pragma unroll
-        for (int s = 0; s < R; ++s) kk[s] = p.K[c.j + s * P];
-        if constexpr (BLEND) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) bb[r] = blend_weight(r);
-        }
+        const uint32_t q = gidx(lline, c.j + r * P);
+        if constexpr (CPT == 1) v[0][r] = load_comp(p.psi, q, c.comp);
+        else load_point(p.psi, q, v[0][r], v[1][r]);
     }
     // Step 1 (and Step 5 of the previous step): row `comp` of
     // E = [[e0, e1], [conj e1, conj e0]]: A own + B other with A = e0, B = e1 for
-    // component 0 and their conjugates for component 1.
+    // component 0 and their conjugates for component 1.  Direction-x launches
+    // always open with Step 1 (e_pre is 1 or 2), so they load E up front and
+    // apply it once unconditionally.
+    constexpr bool PRELOAD_E = MODE == 2 && !COLS;
+    cpx<T> e0[MODE == 2 ? R : 1], e1[MODE == 2 ? R : 1];
+    auto loadE = [&]() {
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) load_point(p.E, gidx(lline, c.j + r * P), e0[r], e1[r]);
+        }
+    };
     auto applyE = [&](int times) {
         if constexpr (MODE == 2) {
-            cpx<T> e0[R], e1[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                e0[r] = e1[r] = cpx<T>{0, 0};
-                if (valid) load_point(p.E, gidx(c.j + r * P), e0[r], e1[r]);
-            }
             for (int t = 0; t < times; ++t)
                 mix(v, [&](cpx<T> own, cpx<T> other, int comp, int r) {
                     const T sg = comp ? T(-1) : T(1);
@@ -213,7 +221,50 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
                 });
         }
     };
-    if (p.e_pre > 0) applyE(p.e_pre);
+    if constexpr (PRELOAD_E) loadE();
+    const cpx<T>* tw = p.tw;
+    constexpr int TWI = TS::ON ? (N + F::NT - 1) / F::NT : 1;
+    cpx<T> twv[TWI];
+    if constexpr (TS::ON) {
+#pragma unroll
+        for (int i = 0; i < TWI; ++i) {
+            const int k = threadIdx.x + i * F::NT;
+            twv[i] = gld(p.tw + (N % F::NT == 0 || k < N ? k : N - 1));
+        }
+    }
+    // blend weight b = a(x) / S(x^i) (MODE 2) or 1 / S(x^i) (MODE 1); the 1/S
+    // table is always present in blended modes (ones without a layer)
+    cpx<T> kk[PF ? R : 1];
+    T bb[BLEND ? R : 1];
+    auto blend_weights = [&]() {
+        if constexpr (BLEND) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T sv = gld(p.inv_s + c.j + r * P);
+                bb[r] = MODE == 2 ? ld_at(p.a, gidx(lline, c.j + r * P)) * sv : sv;
+            }
+        }
+    };
+    if constexpr (PF) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) kk[s] = gld(p.K + c.j + s * P);
+        blend_weights();
+    }
+    if constexpr (TS::ON) {
+#pragma unroll
+        for (int i = 0; i < TWI; ++i) {
+            const int k = threadIdx.x + i * F::NT;
+            if (N % F::NT == 0 || k < N) twl[k] = twv[i];
+        }
+        tw = twl;
+    }
+    if constexpr (PRELOAD_E) {
+        applyE(1);                                 // e_pre is 1 or 2 here
+        if (p.e_pre > 1) applyE(1);
+    } else if (p.e_pre > 0) {
+        loadE();
+        applyE(p.e_pre);
+    }
     cpx<T> old[BLEND ? CPT : 1][BLEND ? R : 1];
     if constexpr (BLEND) {
 #pragma unroll
@@ -226,7 +277,7 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     mix(v, [&](cpx<T> own, cpx<T> other, int comp, int s) {
         cpx<T> k;
         if constexpr (PF) k = kk[s];
-        else k = p.K[c.j + s * P];                     // (cos, sin) / n
+        else k = gld(p.K + c.j + s * P);               // (cos, sin) / n
         if constexpr (!COLS) {                         // K_x = cos I - i sin sigma_x
             return scal(k.re, own) + mul_mi(scal(k.im, other));
         } else {                                       // K_y = [[cos, -sin], [sin, cos]]
@@ -236,20 +287,22 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     F::template fft<true>(v, lds, c, tw);
 
     if constexpr (BLEND) {
+        if constexpr (!PF) blend_weights();
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            T b;
-            if constexpr (PF) b = bb[r];
-            else b = blend_weight(r);
+            const T b = bb[r];
 #pragma unroll
             for (int cc = 0; cc < CPT; ++cc) v[cc][r] = scal(b, v[cc][r]) + scal(T(1) - b, old[cc][r]);
         }
     }
-    if (p.e_post) applyE(1);
+    if (p.e_post) {
+        loadE();
+        applyE(1);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!valid) break;
-        const uint32_t q = gidx(c.j + r * P);
+        const uint32_t q = gidx(line, c.j + r * P);
         if constexpr (CPT == 1) store_comp(p.psi, q, c.comp, v[0][r]);
         else store_point(p.psi, q, v[0][r], v[1][r]);
     }
