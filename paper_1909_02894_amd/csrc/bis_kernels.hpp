@@ -49,29 +49,54 @@ __global__ void __launch_bounds__(bis_threads(N)) bis_stage_kernel(BisParams<T> 
     const typename F::Coord c = F::coord(threadIdx.x);
     const int line = xcd_tile(blockIdx.x, gridDim.x) * L + c.l;
     const bool valid = line < p.nlines;
+    const int lline = valid ? line : p.nlines - 1;     // loads: clamped, branch-free
     const uint32_t n1 = (uint32_t)p.n1;
-    auto gidx = [&](int pos) -> uint32_t { return COLS ? (uint32_t)pos * n1 + line : (uint32_t)line * n1 + pos; };
+    auto gidx = [&](int ln, int pos) -> uint32_t {
+        return COLS ? (uint32_t)pos * n1 + ln : (uint32_t)ln * n1 + pos;
+    };
 
+    // every global load of the tile goes out before the first wait
     cpx<T> v[2][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        v[0][r] = v[1][r] = cpx<T>{0, 0};
-        if (valid) load_point(p.psi, gidx(c.j + r * P), v[0][r], v[1][r]);
-    }
+    for (int r = 0; r < R; ++r) load_point(p.psi, gidx(lline, c.j + r * P), v[0][r], v[1][r]);
+    // Step 1 / Step 5: row comp of E = [[e0, e1], [conj e1, conj e0]];
+    // direction-x launches always open with Step 1 and load E up front
+    constexpr bool PRELOAD_E = MODE == 2 && !COLS;
+    cpx<T> e0[MODE == 2 ? R : 1], e1[MODE == 2 ? R : 1];
+    auto loadE = [&]() {
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) load_point(p.E, gidx(lline, c.j + r * P), e0[r], e1[r]);
+        }
+    };
+    if constexpr (PRELOAD_E) loadE();
     const cpx<T>* tw = p.tw;
+    cpx<T> twv[TS::ON ? F::TW_ITER : 1];
+    if constexpr (TS::ON) F::tw_load(twv, p.tw, threadIdx.x);
+    T b[R], k2[R], k1[R], dsym[R];
+    cpx<T> ksym[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int pos = c.j + r * P;
+        const T s = gld(p.inv_s + pos);            // ones without a layer
+        T a = T(1), da = T(0);
+        if constexpr (MODE == 2) {
+            const uint32_t q = gidx(lline, pos);
+            a = ld_at(p.a, q);
+            da = ld_at(bp.da, 2 * q + dir);
+        }
+        b[r] = a * s;
+        k2[r] = bp.hh * (b[r] * (T(1) - b[r]));
+        k1[r] = bp.hh * (b[r] * (da * s));
+        dsym[r] = gld(bp.D + pos);
+        ksym[r] = gld(p.K + pos);
+    }
     if constexpr (TS::ON) {
-        for (int k = threadIdx.x; k < N; k += F::NT) twl[k] = p.tw[k];
+        F::tw_store(twv, twl, threadIdx.x);
         tw = twl;
     }
-    // Step 1 / Step 5: row comp of E = [[e0, e1], [conj e1, conj e0]]
     auto applyE = [&](int times) {
         if constexpr (MODE == 2) {
-            cpx<T> e0[R], e1[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                e0[r] = e1[r] = cpx<T>{0, 0};
-                if (valid) load_point(p.E, gidx(c.j + r * P), e0[r], e1[r]);
-            }
             for (int t = 0; t < times; ++t) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -90,37 +115,31 @@ __global__ void __launch_bounds__(bis_threads(N)) bis_stage_kernel(BisParams<T> 
             }
         }
     };
-    if (p.e_pre > 0) applyE(p.e_pre);
+    if constexpr (PRELOAD_E) {
+        applyE(1);                             // e_pre is 1 or 2 here
+        if (p.e_pre > 1) applyE(1);
+    } else if (p.e_pre > 0) {
+        loadE();
+        applyE(p.e_pre);
+    }
     cpx<T> old[2][R];
-    T b[R], k2[R], k1[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         old[0][r] = v[0][r];
         old[1][r] = v[1][r];
-        const int pos = c.j + r * P;
-        const T s = p.inv_s ? p.inv_s[pos] : T(1);
-        T a = T(1), da = T(0);
-        if (MODE == 2 && valid) {
-            const uint32_t q = gidx(pos);
-            a = *at(p.a, q);
-            da = *at(bp.da, 2 * q + dir);
-        }
-        b[r] = a * s;
-        k2[r] = bp.hh * (b[r] * (T(1) - b[r]));
-        k1[r] = bp.hh * (b[r] * (da * s));
     }
 
-    F::template fft<false>(v, lds, c, tw);
+    F::template fft<false, TS::ON>(v, lds, c, tw);
     cpx<T> acc[2][R], t[2][R];
     // b (1 - b) (c dt)^2 / 2 * F^-1[xi^2 psi_hat]
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-        const T d = bp.D[c.j + s * P];
+        const T d = dsym[s];
         const T w2 = bp.n * d * d;
         t[0][s] = scal(w2, v[0][s]);
         t[1][s] = scal(w2, v[1][s]);
     }
-    F::template fft<true>(t, lds, c, tw);
+    F::template fft<true, TS::ON>(t, lds, c, tw);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         acc[0][r] = scal(k2[r], t[0][r]);
@@ -130,11 +149,11 @@ __global__ void __launch_bounds__(bis_threads(N)) bis_stage_kernel(BisParams<T> 
         // + b b' (c dt)^2 / 2 * F^-1[i xi psi_hat]
 #pragma unroll
         for (int s = 0; s < R; ++s) {
-            const T d = bp.D[c.j + s * P];
+            const T d = dsym[s];
             t[0][s] = mul_i(scal(d, v[0][s]));
             t[1][s] = mul_i(scal(d, v[1][s]));
         }
-        F::template fft<true>(t, lds, c, tw);
+        F::template fft<true, TS::ON>(t, lds, c, tw);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             acc[0][r] = acc[0][r] + scal(k1[r], t[0][r]);
@@ -144,7 +163,7 @@ __global__ void __launch_bounds__(bis_threads(N)) bis_stage_kernel(BisParams<T> 
     // Xi = F^-1[K psi_hat]
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-        const cpx<T> k = p.K[c.j + s * P];
+        const cpx<T> k = ksym[s];
         const cpx<T> a0 = v[0][s], a1 = v[1][s];
         if constexpr (!COLS) {                 // K_x = cos I - i sin sigma_x
             v[0][s] = scal(k.re, a0) + mul_mi(scal(k.im, a1));
@@ -154,17 +173,20 @@ __global__ void __launch_bounds__(bis_threads(N)) bis_stage_kernel(BisParams<T> 
             v[1][s] = scal(k.re, a1) + scal(k.im, a0);
         }
     }
-    F::template fft<true>(v, lds, c, tw);
+    F::template fft<true, TS::ON>(v, lds, c, tw);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc)
             v[cc][r] = scal(b[r], v[cc][r]) + scal(T(1) - b[r], old[cc][r]) + acc[cc][r];
     }
-    if (p.e_post) applyE(1);
+    if (p.e_post) {
+        loadE();
+        applyE(1);
+    }
     if (!valid) return;
 #pragma unroll
-    for (int r = 0; r < R; ++r) store_point(p.psi, gidx(c.j + r * P), v[0][r], v[1][r]);
+    for (int r = 0; r < R; ++r) store_point(p.psi, gidx(line, c.j + r * P), v[0][r], v[1][r]);
 }
 
 }  // namespace dirac

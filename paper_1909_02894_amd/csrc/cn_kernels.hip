@@ -33,7 +33,9 @@ __global__ void __launch_bounds__((N / cn_radix(N)) * cn_lines(N)) cn_apply_kern
     auto gidx = [&](int pos) -> uint32_t { return COLS ? (uint32_t)pos * n1 + line : (uint32_t)line * n1 + pos; };
     const cpx<T>* tw = p.tw;
     if constexpr (TS::ON) {
-        for (int k = threadIdx.x; k < N; k += F::NT) twl[k] = p.tw[k];
+        cpx<double> twv[F::TW_ITER];
+        F::tw_load(twv, p.tw, threadIdx.x);
+        F::tw_store(twv, twl, threadIdx.x);
         tw = twl;
     }
     cpx<T> v[2][R], in[2][R];
@@ -44,14 +46,14 @@ __global__ void __launch_bounds__((N / cn_radix(N)) * cn_lines(N)) cn_apply_kern
         in[0][r] = v[0][r];
         in[1][r] = v[1][r];
     }
-    F::template fft<false>(v, lds, c, tw);
+    F::template fft<false, TS::ON>(v, lds, c, tw);
 #pragma unroll
     for (int s = 0; s < R; ++s) {
         const T d = p.D[c.j + s * P];
         v[0][s] = mul_i(scal(d, v[0][s]));
         v[1][s] = mul_i(scal(d, v[1][s]));
     }
-    F::template fft<true>(v, lds, c, tw);
+    F::template fft<true, TS::ON>(v, lds, c, tw);
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; ++r) {

@@ -24,7 +24,7 @@ struct D3Params {
     T* psi;                 // 8 T per point
     const T* a;             // a(x) per point, or null (flat)
     const T* E;             // exponential record per point (D3_EREC T), or null (flat)
-    const T* inv_s;         // 1/S along the line direction, or null
+    const T* inv_s;         // 1/S along the line direction (ones without a layer)
     const cpx<T>* K;        // (cos, sin)(c dt xi) / n
     const cpx<T>* tw;       // exp(-2 pi i k / n)
     int n1, n2;
@@ -120,8 +120,10 @@ __global__ void __launch_bounds__(d3_threads<T>(N)) d3_stage_kernel(D3Params<T> 
         if (valid) load_point4(p.psi, gidx(c.j + r * P), u[0][r], u[1][r], w[0][r], w[1][r]);
     }
     const cpx<T>* tw = p.tw;
-    if constexpr (TS::ON) {
-        for (int k = threadIdx.x; k < N; k += F::NT) twl[k] = p.tw[k];
+    if constexpr (TS::ON) {                    // unrolled: no wait between the loads
+        cpx<T> twv[F::TW_ITER];
+        F::tw_load(twv, p.tw, threadIdx.x);
+        F::tw_store(twv, twl, threadIdx.x);
         tw = twl;
     }
     auto applyE = [&](int times) {
@@ -160,8 +162,8 @@ __global__ void __launch_bounds__(d3_threads<T>(N)) d3_stage_kernel(D3Params<T> 
             ow[0][r] = w[0][r]; ow[1][r] = w[1][r];
         }
     }
-    F::template fft<false>(u, lds, c, tw);
-    F::template fft<false>(w, lds, c, tw);
+    F::template fft<false, TS::ON>(u, lds, c, tw);
+    F::template fft<false, TS::ON>(w, lds, c, tw);
 #pragma unroll
     for (int s = 0; s < R; ++s) {
         const cpx<T> k = p.K[c.j + s * P];
@@ -184,15 +186,14 @@ __global__ void __launch_bounds__(d3_threads<T>(N)) d3_stage_kernel(D3Params<T> 
             w[1][s] = scal(cs, b1) + mul_i(scal(sn, a1));
         }
     }
-    F::template fft<true>(u, lds, c, tw);
-    F::template fft<true>(w, lds, c, tw);
+    F::template fft<true, TS::ON>(u, lds, c, tw);
+    F::template fft<true, TS::ON>(w, lds, c, tw);
     if constexpr (BLEND) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int pos = c.j + r * P;
-            T b = T(1);
-            if constexpr (MODE == 2) b = valid ? *at(p.a, gidx(pos)) : T(0);
-            if (p.inv_s) b *= p.inv_s[pos];
+            T b = gld(p.inv_s + pos);              // ones without a layer
+            if constexpr (MODE == 2) b = (valid ? ld_at(p.a, gidx(pos)) : T(0)) * b;
             const T ob = T(1) - b;
             u[0][r] = scal(b, u[0][r]) + scal(ob, ou[0][r]);
             u[1][r] = scal(b, u[1][r]) + scal(ob, ou[1][r]);

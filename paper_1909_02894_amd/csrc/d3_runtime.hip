@@ -309,7 +309,7 @@ D3Params<T> d3_params(const dirac3_solver* s, int dir, int e_pre, int e_post) {
     p.psi = reinterpret_cast<T*>(b + s->lay.psi);
     p.a = s->curved ? reinterpret_cast<const T*>(b + s->lay.a) : nullptr;
     p.E = s->curved ? reinterpret_cast<const T*>(b + s->lay.E) : nullptr;
-    p.inv_s = s->pml ? reinterpret_cast<const T*>(b + s->lay.inv_s[dir]) : nullptr;
+    p.inv_s = reinterpret_cast<const T*>(b + s->lay.inv_s[dir]);     // ones without a layer
     p.K = reinterpret_cast<const cpx<T>*>(b + s->lay.K[dir]);
     p.tw = reinterpret_cast<const cpx<T>*>(b + s->lay.tw[dir]);
     p.n1 = s->g.n1;

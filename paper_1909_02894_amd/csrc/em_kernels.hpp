@@ -108,11 +108,12 @@ template <typename T>
 __device__ __forceinline__ void load_record(const T* rec, uint32_t idx, double (&q)[6], double& a) {
     const char* b = reinterpret_cast<const char*>(rec) + idx * (uint32_t)(8 * sizeof(T));
     if constexpr (sizeof(T) == 8) {
-        const double2 r0 = reinterpret_cast<const double2*>(b)[0], r1 = reinterpret_cast<const double2*>(b)[1];
-        const double2 r2 = reinterpret_cast<const double2*>(b)[2], r3 = reinterpret_cast<const double2*>(b)[3];
+        const d2v* r = reinterpret_cast<const d2v*>(b);
+        const d2v r0 = gld(r), r1 = gld(r + 1), r2 = gld(r + 2), r3 = gld(r + 3);
         q[0] = r0.x; q[1] = r0.y; q[2] = r1.x; q[3] = r1.y; q[4] = r2.x; q[5] = r2.y; a = r3.x;
     } else {
-        const float4 r0 = reinterpret_cast<const float4*>(b)[0], r1 = reinterpret_cast<const float4*>(b)[1];
+        const f4v* r = reinterpret_cast<const f4v*>(b);
+        const f4v r0 = gld(r), r1 = gld(r + 1);
         q[0] = r0.x; q[1] = r0.y; q[2] = r0.z; q[3] = r0.w; q[4] = r1.x; q[5] = r1.y; a = r1.z;
     }
 }
@@ -139,34 +140,44 @@ __global__ void __launch_bounds__(em_threads(N)) em_stage_kernel(EmParams<T> ep)
     const typename F::Coord c = F::coord(threadIdx.x);
     const int line = xcd_tile(blockIdx.x, gridDim.x) * L + c.l;
     const bool valid = line < p.nlines;
+    const int lline = valid ? line : p.nlines - 1;     // loads: clamped, branch-free
     const uint32_t n1 = (uint32_t)p.n1;
-    auto gidx = [&](int pos) -> uint32_t { return COLS ? (uint32_t)pos * n1 + line : (uint32_t)line * n1 + pos; };
+    auto gidx = [&](int ln, int pos) -> uint32_t {
+        return COLS ? (uint32_t)pos * n1 + ln : (uint32_t)ln * n1 + pos;
+    };
 
-    cpx<T> v[2][R], old[2][R];
+    // every global load of the tile goes out before the first wait
+    cpx<T> v[2][R], old[2][R], ksym[R];
+    double q[R][6], a[R];
     T b[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        v[0][r] = v[1][r] = cpx<T>{0, 0};
-        const int pos = c.j + r * P;
-        double q[6] = {0, 0, 0, 0, 0, 0}, a = 0.0;
-        if (valid) {
-            load_point(p.psi, gidx(pos), v[0][r], v[1][r]);
-            load_record(ep.rec, gidx(pos), q, a);
-        }
-        for (int k = 0; k < p.e_pre; ++k) apply_mat(em_exponential(q, ep.fA[k], ep.fV[k]), v[0][r], v[1][r]);
-        b[r] = (T)a * (p.inv_s ? p.inv_s[pos] : T(1));
+        const uint32_t g = gidx(lline, c.j + r * P);
+        load_point(p.psi, g, v[0][r], v[1][r]);
+        load_record(ep.rec, g, q[r], a[r]);
+    }
+    const cpx<T>* tw = p.tw;
+    cpx<T> twv[TS::ON ? F::TW_ITER : 1];
+    if constexpr (TS::ON) F::tw_load(twv, p.tw, threadIdx.x);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        b[r] = (T)a[r] * gld(p.inv_s + c.j + r * P);       // ones without a layer
+        ksym[r] = gld(p.K + c.j + r * P);
+    }
+    if constexpr (TS::ON) {
+        F::tw_store(twv, twl, threadIdx.x);
+        tw = twl;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        for (int k = 0; k < p.e_pre; ++k) apply_mat(em_exponential(q[r], ep.fA[k], ep.fV[k]), v[0][r], v[1][r]);
         old[0][r] = v[0][r];
         old[1][r] = v[1][r];
     }
-    const cpx<T>* tw = p.tw;
-    if constexpr (TS::ON) {
-        for (int k = threadIdx.x; k < N; k += F::NT) twl[k] = p.tw[k];
-        tw = twl;
-    }
-    F::template fft<false>(v, lds, c, tw);
+    F::template fft<false, TS::ON>(v, lds, c, tw);
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-        const cpx<T> k = p.K[c.j + s * P];
+        const cpx<T> k = ksym[s];
         const cpx<T> a0 = v[0][s], a1 = v[1][s];
         if constexpr (!COLS) {                 // K_x = cos I - i sin sigma_x
             v[0][s] = scal(k.re, a0) + mul_mi(scal(k.im, a1));
@@ -176,17 +187,17 @@ __global__ void __launch_bounds__(em_threads(N)) em_stage_kernel(EmParams<T> ep)
             v[1][s] = scal(k.re, a1) + scal(k.im, a0);
         }
     }
-    F::template fft<true>(v, lds, c, tw);
+    F::template fft<true, TS::ON>(v, lds, c, tw);
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const uint32_t g = gidx(c.j + r * P);
+        const uint32_t g = gidx(line, c.j + r * P);
         cpx<T> u = scal(b[r], v[0][r]) + scal(T(1) - b[r], old[0][r]);
         cpx<T> w = scal(b[r], v[1][r]) + scal(T(1) - b[r], old[1][r]);
         if (p.e_post) {
-            double q[6], a;
-            load_record(ep.rec, g, q, a);
-            apply_mat(em_exponential(q, ep.fA[2], ep.fV[2]), u, w);
+            double qe[6], ae;
+            load_record(ep.rec, g, qe, ae);
+            apply_mat(em_exponential(qe, ep.fA[2], ep.fV[2]), u, w);
         }
         store_point(p.psi, g, u, w);
     }

@@ -67,6 +67,28 @@ __device__ __forceinline__ cpx<T> rot16(cpx<T> v) {
     }
 }
 
+// Global-memory access through address-space-1 pointers.  Pointers that reach
+// a kernel inside a descriptor table (the batch engine) are otherwise generic
+// and compile to flat instructions, whose completion is tracked by the memory
+// and the LDS counters together, so every LDS wait would also wait for memory.
+// Only scalar and clang vector element types are loaded this way: a struct
+// copy goes through a generic reference again.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) { return *(const __attribute__((address_space(1))) T*)p; }
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) { *(__attribute__((address_space(1))) T*)p = v; }
+__device__ __forceinline__ cpx<float> gld(const cpx<float>* p) {
+    const f2v v = gld(reinterpret_cast<const f2v*>(p));
+    return {v.x, v.y};
+}
+__device__ __forceinline__ cpx<double> gld(const cpx<double>* p) {
+    const d2v v = gld(reinterpret_cast<const d2v*>(p));
+    return {v.x, v.y};
+}
+
 __host__ __device__ constexpr int bitrev(int i, int R) {
     int r = 0;
     for (int b = 1; b < R; b <<= 1) { r = (r << 1) | (i & 1); i >>= 1; }
@@ -192,8 +214,55 @@ struct LineFFT {
     }
     __device__ static __forceinline__ int slot(const Coord& c, int cc) { return CPT == 1 ? c.comp : cc; }
 
-    // Exchange after pass PASS-1 and compute pass PASS (PASS >= 1).
-    template <bool INV, int PASS>
+    // Per-pass twiddle layout (for tables staged in LDS).  Pass p >= 1 reads
+    // W_N^{r k N / (Ns Rp)} for k = jj mod Ns and r = 1..Rp-1; the plain table
+    // W_N^m read at m = r k N / (Ns Rp) puts the distinct k of a wave a multiple
+    // of 32 banks apart (up to 8-way conflicts).  Stored per pass as
+    // [k][r - 1] instead, neighbouring k sit Rp - 1 (odd) entries apart, so a
+    // wave's reads fall on distinct banks.  Entry count: sum_p Ns_p (Rp - 1) < N.
+    __host__ __device__ static constexpr int tw_off(int p) {
+        int o = 0;
+        for (int q = 1; q < p; ++q) o += ns_of(q) * (radix_of(q) - 1);
+        return o;
+    }
+    static constexpr int TW_ENTRIES = NPASS > 1 ? tw_off(NPASS) : 1;
+    static_assert(TW_ENTRIES <= N, "the per-pass layout fits an N-entry stage");
+    static constexpr int TW_ITER = (TW_ENTRIES + NT - 1) / NT;
+    template <int PASS>
+    __device__ static __forceinline__ int tw_src(int e) {
+        if constexpr (PASS >= NPASS) {
+            return 0;
+        } else {
+            constexpr int Rp = radix_of(PASS), Ns = ns_of(PASS), off = tw_off(PASS);
+            if (e < off + Ns * (Rp - 1)) {
+                const int q = e - off;
+                return (q % (Rp - 1) + 1) * (q / (Rp - 1)) * (N / (Ns * Rp));
+            }
+            return tw_src<PASS + 1>(e);
+        }
+    }
+    // Gather the per-pass layout from the plain table tw[m] = exp(-2 pi i m / N):
+    // tw_load issues the loads (thread t takes entries t + i NT), tw_store
+    // writes them to LDS once they have arrived.
+    __device__ static __forceinline__ void tw_load(cpx<T> (&reg)[TW_ITER], const cpx<T>* tw, int t) {
+#pragma unroll
+        for (int i = 0; i < TW_ITER; ++i) {
+            const int e = t + i * NT;
+            const int src = tw_src<1>(TW_ENTRIES % NT == 0 || e < TW_ENTRIES ? e : TW_ENTRIES - 1);
+            reg[i] = gld(tw + src);
+        }
+    }
+    __device__ static __forceinline__ void tw_store(const cpx<T> (&reg)[TW_ITER], cpx<T>* twl, int t) {
+#pragma unroll
+        for (int i = 0; i < TW_ITER; ++i) {
+            const int e = t + i * NT;
+            if (TW_ENTRIES % NT == 0 || e < TW_ENTRIES) twl[e] = reg[i];
+        }
+    }
+
+    // Exchange after pass PASS-1 and compute pass PASS (PASS >= 1).  PP: tw is
+    // the per-pass layout (else the plain table).
+    template <bool INV, bool PP, int PASS>
     __device__ static __forceinline__ void pass(cpx<T> (&v)[CPT][R], cpx<T>* lds, const Coord& c,
                                                 const cpx<T>* __restrict__ tw) {
         constexpr int Rq = radix_of(PASS - 1), Nq = ns_of(PASS - 1);
@@ -225,7 +294,7 @@ struct LineFFT {
             const int k = jj % Ns;
 #pragma unroll
             for (int r = 1; r < Rp; ++r) {
-                const cpx<T> w = tw[r * k * (N / (Ns * Rp))];
+                const cpx<T> w = PP ? tw[tw_off(PASS) + k * (Rp - 1) + (r - 1)] : tw[r * k * (N / (Ns * Rp))];
 #pragma unroll
                 for (int cc = 0; cc < CPT; ++cc)
                     v[cc][t * Rp + r] = INV ? cmulc(v[cc][t * Rp + r], w) : cmul(v[cc][t * Rp + r], w);
@@ -233,18 +302,19 @@ struct LineFFT {
 #pragma unroll
             for (int cc = 0; cc < CPT; ++cc) dft<T, Rp, INV>(&v[cc][t * Rp]);
         }
-        if constexpr (PASS + 1 < NPASS) pass<INV, PASS + 1>(v, lds, c, tw);
+        if constexpr (PASS + 1 < NPASS) pass<INV, PP, PASS + 1>(v, lds, c, tw);
     }
 
     // Transform the components this thread carries.  Entry: v[cc][r] = position
     // j + r P.  Exit: v[cc][s] = mode (forward) / position (inverse) j + s P.
-    // tw[k] = exp(-2 pi i k / N); the inverse uses conjugates and is unnormalised.
-    template <bool INV>
+    // tw: the plain table tw[m] = exp(-2 pi i m / N) (PP = false) or its
+    // per-pass layout (PP = true); the inverse uses conjugates and is unnormalised.
+    template <bool INV, bool PP = false>
     __device__ static __forceinline__ void fft(cpx<T> (&v)[CPT][R], cpx<T>* lds, const Coord& c,
                                                const cpx<T>* __restrict__ tw) {
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) dft<T, R, INV>(v[cc]);
-        if constexpr (NPASS > 1) pass<INV, 1>(v, lds, c, tw);
+        if constexpr (NPASS > 1) pass<INV, PP, 1>(v, lds, c, tw);
     }
 };
 

@@ -54,28 +54,6 @@ struct ObsParams {
     double a1, a2, h1, h2;
 };
 
-// Global-memory access through address-space-1 pointers.  Pointers that reach
-// a kernel inside a descriptor table (the batch engine) are otherwise generic
-// and compile to flat instructions, whose completion is tracked by the memory
-// and the LDS counters together, so every LDS wait would also wait for memory.
-// Only scalar and clang vector element types are loaded this way: a struct
-// copy goes through a generic reference again.
-typedef float f2v __attribute__((ext_vector_type(2)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef double d2v __attribute__((ext_vector_type(2)));
-template <typename T>
-__device__ __forceinline__ T gld(const T* p) { return *(const __attribute__((address_space(1))) T*)p; }
-template <typename T>
-__device__ __forceinline__ void gst(T* p, T v) { *(__attribute__((address_space(1))) T*)p = v; }
-__device__ __forceinline__ cpx<float> gld(const cpx<float>* p) {
-    const f2v v = gld(reinterpret_cast<const f2v*>(p));
-    return {v.x, v.y};
-}
-__device__ __forceinline__ cpx<double> gld(const cpx<double>* p) {
-    const d2v v = gld(reinterpret_cast<const d2v*>(p));
-    return {v.x, v.y};
-}
-
 // Point access with 32-bit byte offsets (every supported state is < 2 GiB), so
 // addresses are formed as a scalar base plus a 32-bit vector offset.
 template <typename T>
@@ -223,15 +201,8 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     };
     if constexpr (PRELOAD_E) loadE();
     const cpx<T>* tw = p.tw;
-    constexpr int TWI = TS::ON ? (N + F::NT - 1) / F::NT : 1;
-    cpx<T> twv[TWI];
-    if constexpr (TS::ON) {
-#pragma unroll
-        for (int i = 0; i < TWI; ++i) {
-            const int k = threadIdx.x + i * F::NT;
-            twv[i] = gld(p.tw + (N % F::NT == 0 || k < N ? k : N - 1));
-        }
-    }
+    cpx<T> twv[TS::ON ? F::TW_ITER : 1];
+    if constexpr (TS::ON) F::tw_load(twv, p.tw, threadIdx.x);
     // blend weight b = a(x) / S(x^i) (MODE 2) or 1 / S(x^i) (MODE 1); the 1/S
     // table is always present in blended modes (ones without a layer)
     cpx<T> kk[PF ? R : 1];
@@ -251,11 +222,7 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
         blend_weights();
     }
     if constexpr (TS::ON) {
-#pragma unroll
-        for (int i = 0; i < TWI; ++i) {
-            const int k = threadIdx.x + i * F::NT;
-            if (N % F::NT == 0 || k < N) twl[k] = twv[i];
-        }
+        F::tw_store(twv, twl, threadIdx.x);
         tw = twl;
     }
     if constexpr (PRELOAD_E) {
@@ -273,7 +240,7 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
             for (int r = 0; r < R; ++r) old[cc][r] = v[cc][r];
     }
 
-    F::template fft<false>(v, lds, c, tw);
+    F::template fft<false, TS::ON>(v, lds, c, tw);
     mix(v, [&](cpx<T> own, cpx<T> other, int comp, int s) {
         cpx<T> k;
         if constexpr (PF) k = kk[s];
@@ -284,7 +251,7 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
             return scal(k.re, own) - scal(comp ? -k.im : k.im, other);
         }
     });
-    F::template fft<true>(v, lds, c, tw);
+    F::template fft<true, TS::ON>(v, lds, c, tw);
 
     if constexpr (BLEND) {
         if constexpr (!PF) blend_weights();
