@@ -259,6 +259,16 @@ dirac_status dirac_schedule_get(int32_t n, int32_t precision, int32_t direction,
 dirac_status dirac_get_schedule(const dirac_solver* s, int32_t direction, dirac_schedule* out);
 dirac_status dirac_set_schedule(dirac_solver* s, int32_t direction, const dirac_schedule* sch);
 
+/* State stores of the direction kernels: 0 = ordinary stores (the default),
+ * 1 = device-scope write-through stores, which send each line to memory at
+ * once instead of leaving it dirty in the XCD's L2 until the kernel ends.
+ * Write-through pays on small grids whose kernels are latency-bound and loses
+ * on large streaming ones; dirac_autotune measures both and keeps the faster.
+ * Results are bitwise the same either way.  Scheme II's plain and printed
+ * directional steps without potentials only (else DIRAC_E_ARG). */
+dirac_status dirac_set_store_mode(dirac_solver* s, int32_t write_through);
+dirac_status dirac_get_store_mode(const dirac_solver* s, int32_t* write_through);
+
 /* Launch mode of dirac_step_n: 0 = one kernel launch per stage, 1 = replay a
  * HIP graph of 2 * graph_chunk stage kernels (default, chunk 32). */
 dirac_status dirac_set_launch_mode(dirac_solver* s, int32_t use_graph, int32_t graph_chunk);
@@ -283,8 +293,10 @@ dirac_status dirac_time_directions(dirac_solver* s, int32_t reps, double* us_out
 
 /* Autotuner: time every compiled schedule of both directions on this solver's
  * own buffers (the state is saved and restored, so the solve is unchanged),
- * keep the fastest per (n, precision, direction, grid shape) in a process-wide
- * cache and apply it.  reps = timed steps per candidate (>= 1). */
+ * then both store modes with the chosen schedules; keep the fastest per (n,
+ * precision, direction, grid shape) in a process-wide cache and apply it.
+ * reps = timed steps per candidate, in [1, 4096]; candidates run as in
+ * dirac_step_n's graph mode. */
 dirac_status dirac_autotune(dirac_solver* s, int32_t reps);
 
 /* Save / load the tuning cache as a text file (one line per entry). */
@@ -294,12 +306,14 @@ dirac_status dirac_tune_cache_load(const char* path);
 /* --- batched solves ------------------------------------------------------------ */
 
 /* A batch advances many independent solves of mixed grid sizes together: every
- * step of a run is two kernel launches (direction x, then y) that each cover all
- * tiles of all solves still running, recorded once into a HIP graph and
- * replayed.  Solves keep their own device buffers (created with
+ * step of a run is two phases (direction x, then y); a phase covers all tiles
+ * of all solves still running, with one kernel launch per transform length
+ * present (each its own compiled schedule), or one launch over all of them when
+ * some length has too few tiles to fill the GPU.  A run is recorded once into
+ * a HIP graph and replayed.  Solves keep their own device buffers (created with
  * dirac_create_metric, same precision as the batch, n1 and n2 <= 2048); the
  * batch only holds descriptor tables in its own caller-given device buffer.
- * Radix per grid size is fixed (4 for n <= 64, else 8), so a solve's result is
+ * A solve's result depends on the radix of the schedules only, so it is
  * bitwise the same alone in a batch, in any mix, and in the single-solve path
  * with the same radix (dirac_set_schedule). */
 typedef struct dirac_batch dirac_batch;

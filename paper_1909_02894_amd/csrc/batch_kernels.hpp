@@ -112,6 +112,7 @@ __device__ __forceinline__ void batch_tile(const BatchDesc<T>& d, int tile, int 
     p.e_pre = COLS ? 0 : (k == 0 ? 1 : 2);
     p.e_post = COLS ? (k == d.steps - 1 ? 1 : 0) : 0;
     p.e0u = d.e0u;
+    p.wt = 0;
     if (d.mode == 0) stage_tile<T, N, R, L, COLS, 0, CPT>(p, tile, lds, twl);
     else if (d.mode == 1) stage_tile<T, N, R, L, COLS, 1, CPT>(p, tile, lds, twl);
     else stage_tile<T, N, R, L, COLS, 2, CPT>(p, tile, lds, twl);

@@ -68,13 +68,13 @@ template <typename T>
 __device__ __forceinline__ void store_point4(T* p, uint32_t idx, cpx<T> u0, cpx<T> u1, cpx<T> w0, cpx<T> w1) {
     char* b = reinterpret_cast<char*>(p) + idx * (uint32_t)(8 * sizeof(T));
     if constexpr (sizeof(T) == 8) {
-        double2* q = reinterpret_cast<double2*>(b);
-        q[0] = make_double2(u0.re, u0.im); q[1] = make_double2(u1.re, u1.im);
-        q[2] = make_double2(w0.re, w0.im); q[3] = make_double2(w1.re, w1.im);
+        d2v* q = reinterpret_cast<d2v*>(b);
+        gst(q, d2v{u0.re, u0.im}); gst(q + 1, d2v{u1.re, u1.im});
+        gst(q + 2, d2v{w0.re, w0.im}); gst(q + 3, d2v{w1.re, w1.im});
     } else {
-        float4* q = reinterpret_cast<float4*>(b);
-        q[0] = make_float4(u0.re, u0.im, u1.re, u1.im);
-        q[1] = make_float4(w0.re, w0.im, w1.re, w1.im);
+        f4v* q = reinterpret_cast<f4v*>(b);
+        gst(q, f4v{u0.re, u0.im, u1.re, u1.im});
+        gst(q + 1, f4v{w0.re, w0.im, w1.re, w1.im});
     }
 }
 // (C, -D w, D g_x, D g_y, D g_z)

@@ -80,6 +80,19 @@ template <typename T>
 __device__ __forceinline__ T gld(const T* p) { return *(const __attribute__((address_space(1))) T*)p; }
 template <typename T>
 __device__ __forceinline__ void gst(T* p, T v) { *(__attribute__((address_space(1))) T*)p = v; }
+// Device-scope write-through store (global_store ... sc1, in 8-byte pieces): the
+// line goes to memory at once instead of sitting dirty in this XCD's L2 until
+// the end-of-dispatch writeback.
+template <typename T>
+__device__ __forceinline__ void gst_wt(T* p, T v) {
+    static_assert(sizeof(T) % 8 == 0, "8-byte pieces");
+    typedef __attribute__((address_space(1))) unsigned long long g64;
+    g64* q = (g64*)p;
+    unsigned long long w[sizeof(T) / 8];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) __hip_atomic_store(q + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ cpx<float> gld(const cpx<float>* p) {
     const f2v v = gld(reinterpret_cast<const f2v*>(p));
     return {v.x, v.y};
@@ -177,10 +190,14 @@ struct LineFFT {
     // LDS layout, padded against bank conflicts: rows keep each (line, component)
     // run contiguous with one pad element after every R elements (the first
     // exchange writes with stride R); columns interleave the L lines of a position
-    // and add one pad element every 16.
+    // and add COL_PAD pad elements every 16.  The first exchange of a column
+    // tile writes element (R j + s) L + l from lane (j, l): with 16 / R pads per
+    // 16 elements, neighbouring j land L R + L elements apart, so the lanes of
+    // one access cover distinct banks (one pad suffices for a single line).
     static constexpr int ROW_STRIDE = N + N / R;
     static constexpr int COL_RAW = 2 * N * L;
-    static constexpr int LDS_ELEMS = (NPASS > 1) ? (COLS ? COL_RAW + COL_RAW / 16 : L * 2 * ROW_STRIDE) : 1;
+    static constexpr int COL_PAD = (L == 1 || R >= 16) ? 1 : 16 / R;
+    static constexpr int LDS_ELEMS = (NPASS > 1) ? (COLS ? COL_RAW + (COL_RAW / 16) * COL_PAD : L * 2 * ROW_STRIDE) : 1;
     static_assert(CPT == 1 || CPT == 2, "components per thread");
     static_assert(N % R == 0, "R must divide N");
     static_assert(NPASS == 1 ? N == R : E >= 2, "schedule needs radix-R first and last passes");
@@ -195,7 +212,7 @@ struct LineFFT {
     __device__ static __forceinline__ int lidx(int l, int comp, int pos) {
         if constexpr (COLS) {
             const int a = (comp * N + pos) * L + l;
-            return a + a / 16;
+            return a + (a / 16) * COL_PAD;
         } else {
             return (l * 2 + comp) * ROW_STRIDE + pos + pos / R;
         }

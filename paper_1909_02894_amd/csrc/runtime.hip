@@ -235,11 +235,19 @@ struct TuneKey {
         return std::tie(prec, n, dir, other, mode) < std::tie(o.prec, o.n, o.dir, o.other, o.mode);
     }
 };
-struct TuneVal { int radix, lines, cpt; double ms; };
+struct TuneVal { int radix, lines, cpt; double ms; int wt; };
 static std::map<TuneKey, TuneVal>& tune_cache() { static std::map<TuneKey, TuneVal> c; return c; }
 static std::mutex& tune_mutex() { static std::mutex m; return m; }
 
 int solver_mode(const dirac_solver* s) { return (s->curved ? 2 : 0) + (s->pml ? 1 : 0); }
+
+// Store mode the autotuner measured fastest for this shape (kept with the
+// direction-x entry), else ordinary stores.
+bool pick_store_mode(int prec, int n1, int n2, int mode) {
+    std::lock_guard<std::mutex> lk(tune_mutex());
+    auto it = tune_cache().find(TuneKey{prec, n1, 0, n2, mode});
+    return it != tune_cache().end() && it->second.wt != 0;
+}
 
 const KernelEntry* pick_entry(int prec, int n, int dir, int other, int mode) {
     {
@@ -270,6 +278,7 @@ StageParams<T> stage_params(const dirac_solver* s, int dir, int e_pre, int e_pos
     p.e_pre = e_pre;
     p.e_post = e_post;
     p.e0u = cpx<T>{(T)s->e0u_re, (T)s->e0u_im};
+    p.wt = s->store_wt ? 1 : 0;
     return p;
 }
 
@@ -617,6 +626,7 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
     const int mode = solver_mode(s);
     s->sched[0] = pick_entry(prec, g->n1, 0, g->n2, mode);
     s->sched[1] = pick_entry(prec, g->n2, 1, g->n1, mode);
+    s->store_wt = pick_store_mode(prec, g->n1, g->n2, mode);
     *out = s;
     return DIRAC_OK;
 }
@@ -785,6 +795,22 @@ dirac_status dirac_set_schedule(dirac_solver* s, int32_t dir, const dirac_schedu
     return DIRAC_OK;
 }
 
+dirac_status dirac_set_store_mode(dirac_solver* s, int32_t write_through) {
+    if (!s || (write_through != 0 && write_through != 1)) return fail(DIRAC_E_ARG, "bad arguments");
+    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || s->has_em)
+        return fail(DIRAC_E_ARG, "the store mode applies to Scheme II's plain and printed directional steps "
+                                 "without potentials only");
+    s->store_wt = write_through != 0;
+    drop_graph(s);
+    return DIRAC_OK;
+}
+
+dirac_status dirac_get_store_mode(const dirac_solver* s, int32_t* write_through) {
+    if (!s || !write_through) return fail(DIRAC_E_ARG, "bad arguments");
+    *write_through = s->store_wt ? 1 : 0;
+    return DIRAC_OK;
+}
+
 dirac_status dirac_set_launch_mode(dirac_solver* s, int32_t use_graph, int32_t chunk) {
     if (!s || chunk < 1 || chunk > 4096) return fail(DIRAC_E_ARG, "bad arguments");
     s->use_graph = use_graph != 0;
@@ -889,7 +915,7 @@ dirac_status dirac_time_directions(dirac_solver* s, int32_t reps, double* us_out
 }
 
 dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
-    if (!s || reps < 1) return fail(DIRAC_E_ARG, "bad arguments");
+    if (!s || reps < 1 || reps > 4096) return fail(DIRAC_E_ARG, "bad arguments");
     if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || s->has_em)
         return fail(DIRAC_E_ARG, "schedules apply to Scheme II's plain and printed directional steps without "
                                  "potentials only");
@@ -904,31 +930,66 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
     const int mode = solver_mode(s);
     dirac_status result = DIRAC_OK;
+    // Candidates are timed as they run: reps + 1 steps whose middle reps - 1
+    // (y, x) pairs replay one HIP graph (direct launches of small grids would
+    // time the host's launch rate, not the kernels).  The first pass builds the
+    // graph and warms up; the second is timed.
+    const bool use_graph0 = s->use_graph;
+    const int chunk0 = s->graph_chunk;
+    s->use_graph = true;
+    s->graph_chunk = std::max(1, reps);
+    auto time_steps = [&](float& ms) -> dirac_status {
+        drop_graph(s);
+        dirac_status r = enqueue_steps(s, reps + 1, true);
+        if (r != DIRAC_OK) return r;
+        hipEventRecord(e0, s->stream);
+        if ((r = enqueue_steps(s, reps + 1, true)) != DIRAC_OK) return r;
+        hipEventRecord(e1, s->stream);
+        if (hipEventSynchronize(e1) != hipSuccess) return fail(DIRAC_E_DEVICE, "autotune sync");
+        ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        return DIRAC_OK;
+    };
+    s->store_wt = false;
+    double dir_ms[2] = {0, 0};
     for (int dir = 0; dir < 2 && result == DIRAC_OK; ++dir) {
         const int n = dir == 0 ? s->g.n1 : s->g.n2;
-        const int other = dir == 0 ? s->g.n2 : s->g.n1;
         const KernelEntry* best = s->sched[dir];
         double best_ms = 1e300;
         for (const auto& e : kernel_registry()) {
             if (e.prec != s->prec || e.n != n || e.dir != dir) continue;
             s->sched[dir] = &e;
-            // warm-up then timed
-            if ((result = enqueue_steps(s, 2, false)) != DIRAC_OK) break;
-            hipEventRecord(e0, s->stream);
-            if ((result = enqueue_steps(s, reps, false)) != DIRAC_OK) break;
-            hipEventRecord(e1, s->stream);
-            if (hipEventSynchronize(e1) != hipSuccess) { result = fail(DIRAC_E_DEVICE, "autotune sync"); break; }
             float ms = 0;
-            hipEventElapsedTime(&ms, e0, e1);
+            if ((result = time_steps(ms)) != DIRAC_OK) break;
             if (ms < best_ms) { best_ms = ms; best = &e; }
         }
         s->sched[dir] = best;
+        dir_ms[dir] = best_ms;
+    }
+    // then the store mode with the chosen schedules
+    if (result == DIRAC_OK) {
+        float ms_wb = 0, ms_wt = 0;
+        if ((result = time_steps(ms_wb)) == DIRAC_OK) {
+            s->store_wt = true;
+            if ((result = time_steps(ms_wt)) == DIRAC_OK) s->store_wt = ms_wt < ms_wb;
+        }
+        if (result != DIRAC_OK) s->store_wt = false;
+    }
+    if (result == DIRAC_OK) {
         std::lock_guard<std::mutex> lk(tune_mutex());
-        tune_cache()[TuneKey{s->prec, n, dir, other, mode}] = TuneVal{best->radix, best->lines, best->cpt, best_ms / reps};
+        for (int dir = 0; dir < 2; ++dir) {
+            const int n = dir == 0 ? s->g.n1 : s->g.n2;
+            const int other = dir == 0 ? s->g.n2 : s->g.n1;
+            const KernelEntry* best = s->sched[dir];
+            tune_cache()[TuneKey{s->prec, n, dir, other, mode}] =
+                TuneVal{best->radix, best->lines, best->cpt, dir_ms[dir] / reps, s->store_wt ? 1 : 0};
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     drop_graph(s);
+    s->use_graph = use_graph0;
+    s->graph_chunk = chunk0;
     HIP_TRY(hipMemcpyAsync(b + s->lay.psi, b + s->lay.scratch, bytes, hipMemcpyDeviceToDevice, s->stream), "restore state");
     HIP_TRY(hipStreamSynchronize(s->stream), "synchronise");
     s->step = step0;
@@ -940,10 +1001,10 @@ dirac_status dirac_tune_cache_save(const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return fail(DIRAC_E_ARG, "cannot open %s", path);
     std::lock_guard<std::mutex> lk(tune_mutex());
-    std::fprintf(f, "# prec n dir other mode radix lines components ms_per_step\n");
+    std::fprintf(f, "# prec n dir other mode radix lines components ms_per_step write_through\n");
     for (const auto& kv : tune_cache())
-        std::fprintf(f, "%d %d %d %d %d %d %d %d %.6g\n", kv.first.prec, kv.first.n, kv.first.dir, kv.first.other,
-                     kv.first.mode, kv.second.radix, kv.second.lines, kv.second.cpt, kv.second.ms);
+        std::fprintf(f, "%d %d %d %d %d %d %d %d %.6g %d\n", kv.first.prec, kv.first.n, kv.first.dir, kv.first.other,
+                     kv.first.mode, kv.second.radix, kv.second.lines, kv.second.cpt, kv.second.ms, kv.second.wt);
     std::fclose(f);
     return DIRAC_OK;
 }
@@ -958,9 +1019,10 @@ dirac_status dirac_tune_cache_load(const char* path) {
         if (line[0] == '#') continue;
         TuneKey k{};
         TuneVal v{};
-        if (std::sscanf(line, "%d %d %d %d %d %d %d %d %lf", &k.prec, &k.n, &k.dir, &k.other, &k.mode, &v.radix,
-                        &v.lines, &v.cpt, &v.ms) == 9)
-            tune_cache()[k] = v;
+        const int got = std::sscanf(line, "%d %d %d %d %d %d %d %d %lf %d", &k.prec, &k.n, &k.dir, &k.other,
+                                    &k.mode, &v.radix, &v.lines, &v.cpt, &v.ms, &v.wt);
+        if (got == 9) v.wt = 0;      // files written before the store-mode column
+        if (got >= 9) tune_cache()[k] = v;
     }
     std::fclose(f);
     return DIRAC_OK;

@@ -61,6 +61,7 @@ struct dirac_solver {
     int64_t step = 0;
     bool has_state = false;
     const dirac::KernelEntry* sched[2] = {nullptr, nullptr};
+    bool store_wt = false;     // write-through state stores in the direction kernels
     bool use_graph = true;
     int graph_chunk = 32;
     hipGraph_t graph = nullptr;

@@ -33,6 +33,7 @@ struct StageParams {
                                  // direction-x launches (which load E up front), 0 in direction y
     int e_post;                  // Step-5 exponential applied after the blend (0, 1)
     cpx<T> e0u;                  // uniform e0 when E is null (flat: e^{-i dt m c^2 / 2})
+    int wt;                      // 1: write-through state stores (lines of n <= 1024)
 };
 
 struct ObsParams {
@@ -85,21 +86,24 @@ __device__ __forceinline__ void load_point(const T* p, uint32_t idx, cpx<T>& u, 
         v = {(T)A.z, (T)A.w};
     }
 }
-template <typename T>
+// WT: device-scope write-through stores (gst_wt) instead of ordinary ones.
+template <typename T, bool WT = false>
 __device__ __forceinline__ void store_point(T* p, uint32_t idx, cpx<T> u, cpx<T> v) {
     char* b = reinterpret_cast<char*>(p) + idx * (uint32_t)(4 * sizeof(T));
+    auto st = [](auto* q, auto x) { if constexpr (WT) gst_wt(q, x); else gst(q, x); };
     if constexpr (sizeof(T) == 8) {
-        gst(reinterpret_cast<d2v*>(b), d2v{u.re, u.im});
-        gst(reinterpret_cast<d2v*>(b) + 1, d2v{v.re, v.im});
+        st(reinterpret_cast<d2v*>(b), d2v{u.re, u.im});
+        st(reinterpret_cast<d2v*>(b) + 1, d2v{v.re, v.im});
     } else {
-        gst(reinterpret_cast<f4v*>(b), f4v{u.re, u.im, v.re, v.im});
+        st(reinterpret_cast<f4v*>(b), f4v{u.re, u.im, v.re, v.im});
     }
 }
-template <typename T>
+template <typename T, bool WT = false>
 __device__ __forceinline__ void store_comp(T* p, uint32_t idx, int c, cpx<T> v) {
     char* b = reinterpret_cast<char*>(p) + idx * (uint32_t)(4 * sizeof(T)) + c * (uint32_t)(2 * sizeof(T));
-    if constexpr (sizeof(T) == 8) gst(reinterpret_cast<d2v*>(b), d2v{v.re, v.im});
-    else gst(reinterpret_cast<f2v*>(b), f2v{v.re, v.im});
+    auto st = [](auto* q, auto x) { if constexpr (WT) gst_wt(q, x); else gst(q, x); };
+    if constexpr (sizeof(T) == 8) st(reinterpret_cast<d2v*>(b), d2v{v.re, v.im});
+    else st(reinterpret_cast<f2v*>(b), f2v{v.re, v.im});
 }
 
 // Workgroup -> tile map that keeps neighbouring tiles on one XCD.  Workgroups
@@ -266,12 +270,24 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
         loadE();
         applyE(1);
     }
+    if (!valid) return;
+    // write-through stores exist for the shorter lines only: they pay on
+    // small latency-bound grids, and the extra store path perturbs the code
+    // of the long-line kernels (measured 18% slower at n = 4096 unexecuted)
+    if (N <= 1024 && p.wt) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        if (!valid) break;
-        const uint32_t q = gidx(line, c.j + r * P);
-        if constexpr (CPT == 1) store_comp(p.psi, q, c.comp, v[0][r]);
-        else store_point(p.psi, q, v[0][r], v[1][r]);
+        for (int r = 0; r < R; ++r) {
+            const uint32_t q = gidx(line, c.j + r * P);
+            if constexpr (CPT == 1) store_comp<T, true>(p.psi, q, c.comp, v[0][r]);
+            else store_point<T, true>(p.psi, q, v[0][r], v[1][r]);
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint32_t q = gidx(line, c.j + r * P);
+            if constexpr (CPT == 1) store_comp(p.psi, q, c.comp, v[0][r]);
+            else store_point(p.psi, q, v[0][r], v[1][r]);
+        }
     }
 }
 

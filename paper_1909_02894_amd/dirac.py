@@ -124,6 +124,8 @@ SIGNATURES = {
     "dirac_get_schedule": (C.c_int32, [_vp, C.c_int32, C.POINTER(Schedule)]),
     "dirac_set_schedule": (C.c_int32, [_vp, C.c_int32, C.POINTER(Schedule)]),
     "dirac_set_launch_mode": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
+    "dirac_set_store_mode": (C.c_int32, [_vp, C.c_int32]),
+    "dirac_get_store_mode": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
     "dirac_step_n_timed": (C.c_int32, [_vp, C.c_int64, _dp, C.POINTER(C.c_int64)]),
     "dirac_autotune": (C.c_int32, [_vp, C.c_int32]),
     "dirac_time_directions": (C.c_int32, [_vp, C.c_int32, _dp]),
@@ -372,6 +374,15 @@ class Solver:
 
     def set_launch_mode(self, use_graph: bool, chunk: int = 32):
         _check(lib.dirac_set_launch_mode(self.h, int(use_graph), chunk))
+
+    def store_mode(self) -> int:
+        """1 if the direction kernels store the state write-through, else 0."""
+        v = C.c_int32()
+        _check(lib.dirac_get_store_mode(self.h, C.byref(v)))
+        return v.value
+
+    def set_store_mode(self, write_through: bool):
+        _check(lib.dirac_set_store_mode(self.h, int(bool(write_through))))
 
     def step_n_timed(self, n):
         ms = (C.c_double * 2)()

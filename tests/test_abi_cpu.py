@@ -72,6 +72,8 @@ def test_null_handles_are_rejected():
     assert D.lib.dirac_step_n(None, 1) == -1
     assert D.lib.dirac_observables(None, None) == -1
     assert D.lib.dirac_destroy(None) == -1
+    assert D.lib.dirac_set_store_mode(None, 1) == -1
+    assert D.lib.dirac_get_store_mode(None, None) == -1
 
 
 def test_every_size_and_precision_has_kernels():

@@ -218,6 +218,38 @@ def test_every_schedule_agrees(D):
                 assert np.array_equal(out, out2)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_write_through_stores_are_bitwise(D, prec):
+    # the store mode changes where a line is written back, never a value: every
+    # schedule, graph replay and direct launches, both modes
+    spec = W.curved_bump(n=256, steps=12, m=0.5)
+    psi0 = W.initial_spinor(spec)
+    ref = None
+    for (r, lines, cpt) in D.schedules(256, prec, 0):
+        for wt in (0, 1):
+            for graph in (True, False):
+                s = D.Solver.from_spec(spec, precision=prec)
+                s.set_schedule(0, r, lines, cpt)
+                s.set_store_mode(wt)
+                assert s.store_mode() == wt
+                s.set_launch_mode(graph, 4)
+                s.set_initial_spinor(psi0)
+                s.step_n(12)
+                out = s.get_spinor()
+                if ref is None:
+                    ref = (r, out)
+                elif ref[0] == r:
+                    assert np.array_equal(out, ref[1]), (r, lines, cpt, wt, graph)
+                s.close()
+    s = D.Solver.from_spec(spec, precision=prec)
+    s.set_initial_spinor(psi0)
+    s.autotune(4)
+    assert s.store_mode() in (0, 1)
+    s.step_n(12)
+    _, o = oracle_run(spec, 12)
+    assert O.rel_l2(s.get_spinor(), o[12]) < (TOL64 if prec == 0 else 2e-5)
+
+
 def test_fp32_flat_against_exact_propagator(D):
     spec = W.flat_small(n=256, steps=1000)
     _, g = gpu_run(D, spec, 1000, precision=1, checkpoints=(100,))
