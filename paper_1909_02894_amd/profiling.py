@@ -6,7 +6,8 @@
     python -m paper_1909_02894_amd.profiling trace <kernel_trace.csv> <out.md> "<command>" [filter]
 
 `stats` turns a ``--kernel-trace --stats`` kernel table into a short markdown
-summary.  `trace` splits the dispatches of every direction kernel in a
+summary.  `trace` splits the dispatches of every direction kernel (those whose name
+matches the filter regex) in a
 ``--kernel-trace`` CSV by context: launches between two launches of the same
 kernel (a kernel replayed alone, its data still in its XCD's L2) and all the
 others (the real alternating x, y order), with the median of each.  `traffic` takes two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
@@ -117,13 +118,13 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, grid, out_json
     return out
 
 
-def trace(csv_path: str, out_md: str, command: str, filt: str = "stage_kernel"):
+def trace(csv_path: str, out_md: str, command: str, filt: str = r"stage_kernel|batch_group_kernel|batch_multi_kernel"):
     rows = sorted(csv.DictReader(open(csv_path)), key=lambda r: int(r["Start_Timestamp"]))
     seq = [(short_name(r["Kernel_Name"]), int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows]
     alt, iso = defaultdict(list), defaultdict(list)
     for i in range(1, len(seq) - 1):
         k, t0, t1 = seq[i]
-        if filt not in k:
+        if not re.search(filt, k):
             continue
         same = seq[i - 1][0] == k and seq[i + 1][0] == k
         (iso if same else alt)[k].append((t1 - t0) / 1e3)
