@@ -72,7 +72,7 @@ def time_solve(D, spec, precision, steps, warmup, timed_steps, scheme=0):
     s.set_initial_spinor_device(psi0)
     torch.cuda.synchronize()
     if scheme != D.SCHEME_EXP_SPLIT_2BIS:
-        s.autotune(20)               # warm-up part 1: pick the fastest compiled schedules
+        s.autotune(200)              # warm-up part 1: pick the fastest compiled schedules and store mode
     s.step_n(warmup)
     torch.cuda.synchronize()
     st = s.stream
@@ -282,7 +282,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--skip-variants", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=120)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (counter calibration)")
     args = ap.parse_args()
