@@ -241,6 +241,11 @@ static std::mutex& tune_mutex() { static std::mutex m; return m; }
 
 int solver_mode(const dirac_solver* s) { return (s->curved ? 2 : 0) + (s->pml ? 1 : 0); }
 
+// The direction kernels carry the write-through store path for lines of at
+// most this many points (stage_tile).
+constexpr int kStoreWtMaxN = 1024;
+bool store_wt_compiled(const dirac_solver* s) { return s->g.n1 <= kStoreWtMaxN && s->g.n2 <= kStoreWtMaxN; }
+
 // Store mode the autotuner measured fastest for this shape (kept with the
 // direction-x entry), else ordinary stores.
 bool pick_store_mode(int prec, int n1, int n2, int mode) {
@@ -626,7 +631,7 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
     const int mode = solver_mode(s);
     s->sched[0] = pick_entry(prec, g->n1, 0, g->n2, mode);
     s->sched[1] = pick_entry(prec, g->n2, 1, g->n1, mode);
-    s->store_wt = pick_store_mode(prec, g->n1, g->n2, mode);
+    s->store_wt = store_wt_compiled(s) && pick_store_mode(prec, g->n1, g->n2, mode);
     *out = s;
     return DIRAC_OK;
 }
@@ -800,6 +805,8 @@ dirac_status dirac_set_store_mode(dirac_solver* s, int32_t write_through) {
     if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || s->has_em)
         return fail(DIRAC_E_ARG, "the store mode applies to Scheme II's plain and printed directional steps "
                                  "without potentials only");
+    if (write_through && !store_wt_compiled(s))
+        return fail(DIRAC_E_ARG, "write-through stores are compiled for n1, n2 <= %d only", kStoreWtMaxN);
     s->store_wt = write_through != 0;
     drop_graph(s);
     return DIRAC_OK;
@@ -967,7 +974,7 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
         dir_ms[dir] = best_ms;
     }
     // then the store mode with the chosen schedules
-    if (result == DIRAC_OK) {
+    if (result == DIRAC_OK && store_wt_compiled(s)) {
         float ms_wb = 0, ms_wt = 0;
         if ((result = time_steps(ms_wb)) == DIRAC_OK) {
             s->store_wt = true;

@@ -241,6 +241,11 @@ def test_write_through_stores_are_bitwise(D, prec):
                 elif ref[0] == r:
                     assert np.array_equal(out, ref[1]), (r, lines, cpt, wt, graph)
                 s.close()
+    big = D.Solver.from_spec(W.flat_small(n=2048, steps=1), precision=prec)
+    with pytest.raises(D.DiracError):
+        big.set_store_mode(1)                  # compiled for n <= 1024 only
+    assert big.store_mode() == 0
+    big.close()
     s = D.Solver.from_spec(spec, precision=prec)
     s.set_initial_spinor(psi0)
     s.autotune(4)
