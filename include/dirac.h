@@ -309,8 +309,8 @@ dirac_status dirac_tune_cache_load(const char* path);
 /* A batch advances many independent solves of mixed grid sizes together: every
  * step of a run is two phases (direction x, then y); a phase covers all tiles
  * of all solves still running, with one kernel launch per transform length
- * present (each its own compiled schedule), or one launch over all of them when
- * some length has too few tiles to fill the GPU.  A run is recorded once into
+ * present (each its own compiled schedule); lengths with too few tiles to fill
+ * the GPU alone share one launch.  A run is recorded once into
  * a HIP graph and replayed.  Solves keep their own device buffers (created with
  * dirac_create_metric, same precision as the batch, n1 and n2 <= 2048); the
  * batch only holds descriptor tables in its own caller-given device buffer.

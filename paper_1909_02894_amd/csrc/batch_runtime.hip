@@ -26,8 +26,8 @@ const void*& batch_multi_kernel_fn(int prec, int dir) {
 }
 
 // A size group launched on its own should fill the GPU: at least this many
-// 256-thread tiles (four per compute unit); otherwise the phase's groups share
-// one launch of the multi-group kernel.
+// 256-thread tiles (four per compute unit); the smaller groups of a phase
+// share one launch of the multi-group kernel.
 constexpr int kMinGroupTiles = 1024;
 
 static size_t align256b(size_t x) { return (x + 255) & ~size_t(255); }
@@ -303,7 +303,6 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
     };
     auto phase_launches = [&](int d, int64_t k, std::vector<GroupLaunch>& out) {
         out.clear();
-        int min_tiles = 1 << 30;
         for (const auto& g : groups[d]) {
             int nactive = (int)g.members.size();
             while (nactive > 0 && steps[act[g.members[nactive - 1]]] <= k) --nactive;
@@ -322,28 +321,32 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
             L.tiles = L.ph.total_tiles;
             L.mph.logn[0] = g.logn;       // kept for the merge below
             L.mph.sched[0] = sc;
-            min_tiles = std::min(min_tiles, L.tiles);
             out.push_back(L);
         }
-        if (out.size() > 1 && min_tiles < kMinGroupTiles) {
+        // groups too small to fill the GPU alone share one multi-group launch;
+        // the others keep their own kernels (lower register counts)
+        std::vector<GroupLaunch> small, keep;
+        for (auto& L : out) (L.tiles < kMinGroupTiles ? small : keep).push_back(L);
+        if (small.size() > 1) {
             GroupLaunch M{};
             M.fn = batch_multi_kernel_fn(b->prec, d);
             M.multi = true;
             M.mph.desc = reinterpret_cast<const BatchDesc<double>*>(dev);
-            M.mph.ngroups = (int)out.size();
+            M.mph.ngroups = (int)small.size();
             M.mph.k = (int)k;
             M.mph.start[0] = 0;
-            for (size_t g = 0; g < out.size(); ++g) {
-                M.mph.index[g] = out[g].ph.index;
-                M.mph.prefix[g] = out[g].ph.prefix;
-                M.mph.nactive[g] = out[g].ph.nactive;
-                M.mph.logn[g] = out[g].mph.logn[0];
-                M.mph.sched[g] = out[g].mph.sched[0];
-                M.mph.start[g + 1] = M.mph.start[g] + out[g].tiles;
-                M.smem = std::max(M.smem, out[g].smem);
+            for (size_t g = 0; g < small.size(); ++g) {
+                M.mph.index[g] = small[g].ph.index;
+                M.mph.prefix[g] = small[g].ph.prefix;
+                M.mph.nactive[g] = small[g].ph.nactive;
+                M.mph.logn[g] = small[g].mph.logn[0];
+                M.mph.sched[g] = small[g].mph.sched[0];
+                M.mph.start[g + 1] = M.mph.start[g] + small[g].tiles;
+                M.smem = std::max(M.smem, small[g].smem);
             }
-            M.tiles = M.mph.start[out.size()];
-            out.assign(1, M);
+            M.tiles = M.mph.start[small.size()];
+            keep.push_back(M);
+            out.swap(keep);
         }
     };
     // BatchPhase<T> / BatchMultiPhase<T> have the same layout for both T.
