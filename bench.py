@@ -42,6 +42,16 @@ def bytes_per_point(kind: str, dir_: int, precision: int) -> int:
     return state + (4 * sz + sz if dir_ == 0 else sz)
 
 
+def variant_roofline(npts: int, bytes_xy, us_xy, note: str):
+    """HBM roofline of a variant's dominant direction kernel: algorithmic bytes
+    per point (x, y) times the points of one launch over its measured duration."""
+    dom = 0 if us_xy[0] >= us_xy[1] else 1
+    ach = bytes_xy[dom] * npts / (us_xy[dom] * 1e-6) / 1e9
+    return {"bound": "hbm", "kernel": "xy"[dom] + "_stage", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_point": bytes_xy[dom],
+            "avg_launch_us": round(us_xy[dom], 3), "note": note}
+
+
 def load_traffic(name: str, instantiation: str | None = None):
     """HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
     (profiles/traffic.json), or None when absent or taken on other kernel sources."""
@@ -240,7 +250,10 @@ def bench_em(D, W, spec, steps=500):
     return {"value": spec.n1 * spec.n2 * steps / (ms * 1e-3), "unit": "grid-point*steps/s", "dtype": "f64",
             "ms_per_step": ms / steps, "note": "Gaussian scalar potential and a uniform laser-like vector "
             "potential pulse; exponential rebuilt per point and step", "x_avg_us": round(1e3 * kms[0] / cnt[0], 3),
-            "y_avg_us": round(1e3 * kms[1] / cnt[1], 3)}
+            "y_avg_us": round(1e3 * kms[1] / cnt[1], 3),
+            "roofline": variant_roofline(spec.n1 * spec.n2, (128, 128), [1e3 * kms[d] / cnt[d] for d in (0, 1)],
+                                         "state r/w 64 + the 64-byte point record in both directions; the x "
+                                         "kernel is ALU-bound (FP64 exponential per point, twice)")}
 
 
 def bench_serve(count, rate, budget, quantum=64, seed=5000):
@@ -351,7 +364,9 @@ def main():
         variants["step2bis_corrected_fp64"] = {
             "value": N * 500 / (rc["ms"] * 1e-3), "ms_per_step": rc["ms"] / 500, "dtype": "f64",
             "note": "second-order directional step (three inverse transforms per direction), same workload",
-            "x_avg_us": round(rc["kernel_us"][0], 3), "y_avg_us": round(rc["kernel_us"][1], 3)}
+            "x_avg_us": round(rc["kernel_us"][0], 3), "y_avg_us": round(rc["kernel_us"][1], 3),
+            "roofline": variant_roofline(N, (120, 88), rc["kernel_us"],
+                                         "x: state r/w 64 + E 32 + a 8 + gradient pair 16 B/pt; y: 64 + 8 + 16")}
         progress("variant: Scheme I")
         variants["scheme1_cn_gmres"] = bench_cn(D, spec)
         progress("variant: potentials")
