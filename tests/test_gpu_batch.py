@@ -158,6 +158,28 @@ def test_sixteen_seeded_solves_cover_every_size(D):
     b.close()
 
 
+def test_large_group_beside_merged_small_groups(D):
+    # one size group big enough for its own launch (a 2048-point solve: 2048
+    # tiles per phase) beside two small groups that share a multi-group launch;
+    # every solve keeps the bits of the single-solve path with the batch radix
+    specs = [W.curved_bump(n=2048, seed=4100, steps=0)]
+    specs += [W.curved_bump(n=n, seed=4101 + i, steps=0) for i, n in enumerate((64, 128, 64))]
+    steps = [3, 5, 2, 4]
+    b = D.Batch(precision=D.FP32, capacity=8)
+    solvers = []
+    for sp in specs:
+        s = D.Solver.from_spec(sp, precision=D.FP32, stream=b.stream)
+        s.set_initial_spinor(W.initial_spinor(sp))
+        b.add(s)
+        solvers.append(s)
+    b.run(steps + [0] * 4)
+    b.sync()
+    for sp, s, k in zip(specs, solvers, steps):
+        ref = single_path(D, sp, D.FP32, k)
+        assert ref is not None and np.array_equal(s.get_spinor(), ref), (sp.n1, k)
+    b.close()
+
+
 def test_full_batch_workload_sampled(D):
     # the full 256-solve, 1000-step FP32 batch as bench.py runs it (one graph);
     # the 128x128 solves among them are checked against the oracle at 1000 steps
