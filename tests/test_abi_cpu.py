@@ -202,3 +202,23 @@ def test_3d_footprint_and_validation():
     assert status(dt=-1.0) == -1
     assert status() == -1 and "null device buffer" in D.last_error()
     assert D.lib.dirac3_step_n(None, 1) == -1
+
+
+def test_tune_cache_round_trip(tmp_path):
+    # the cache file keeps schedules and the store mode; files written before
+    # the store-mode column load with ordinary stores
+    from paper_1909_02894_amd import dirac as D
+    src = tmp_path / "in.txt"
+    src.write_text("# prec n dir other mode radix lines components ms_per_step write_through\n"
+                   "0 512 0 512 3 8 1 2 0.0121 1\n"
+                   "0 512 1 512 3 8 2 1 0.0123 1\n"
+                   "1 256 0 256 2 4 1 1 0.005\n")
+    D.tune_cache_load(str(src))
+    out = tmp_path / "out.txt"
+    D.tune_cache_save(str(out))
+    rows = {tuple(l.split()[:5]): l.split()[5:] for l in out.read_text().splitlines() if not l.startswith("#")}
+    assert rows[("0", "512", "0", "512", "3")][:3] == ["8", "1", "2"] and rows[("0", "512", "0", "512", "3")][-1] == "1"
+    assert rows[("0", "512", "1", "512", "3")][-1] == "1"
+    assert rows[("1", "256", "0", "256", "2")][:3] == ["4", "1", "1"] and rows[("1", "256", "0", "256", "2")][-1] == "0"
+    with pytest.raises(D.DiracError):
+        D.tune_cache_load(str(tmp_path / "missing.txt"))
