@@ -340,7 +340,7 @@ def main():
         "config": {"workload": "curved bump 512x512, seed 1909, 32-point type-I layer, m=0, dt=0.01, FP64",
                    "grid": [spec.n1, spec.n2], "bump_A": round(spec.bump_A, 6), "bump_s": round(spec.bump_s, 6),
                    "k0": [round(k, 6) for k in spec.k0],
-                   "schedule": {"x": r64["sched"][0], "y": r64["sched"][1], "write_through": r64["write_through"]}},
+                   "schedule": {"x": r64["sched"][0], "y": r64["sched"][1], "write_through_mask": r64["write_through"]}},
         "roofline": roofline_for(spec, "curved", D.FP64, r64),
     }
     variants = {}
@@ -350,7 +350,7 @@ def main():
         variants["fp32_same_workload"] = {
             "value": N * K / (r32["ms"] * 1e-3), "ms_per_step": r32["ms"] / K, "dtype": "f32",
             "roofline": roofline_for(spec, "curved", D.FP32, r32),
-            "schedule": {"x": r32["sched"][0], "y": r32["sched"][1], "write_through": r32["write_through"]}}
+            "schedule": {"x": r32["sched"][0], "y": r32["sched"][1], "write_through_mask": r32["write_through"]}}
         big = W.flat_small(n=4096, steps=200)
         progress("variant: flat 4096x4096 FP32")
         rb = time_solve(D, big, D.FP32, 200, 10, 100)
@@ -358,7 +358,7 @@ def main():
             "value": big.n1 * big.n2 * 200 / (rb["ms"] * 1e-3), "ms_per_step": rb["ms"] / 200, "dtype": "f32",
             "note": "flat 4096x4096 packet solve, 256 MiB state (beyond the Infinity Cache)",
             "roofline": roofline_for(big, "flat", D.FP32, rb),
-            "schedule": {"x": rb["sched"][0], "y": rb["sched"][1], "write_through": rb["write_through"]}}
+            "schedule": {"x": rb["sched"][0], "y": rb["sched"][1], "write_through_mask": rb["write_through"]}}
         progress("variant: second-order directional step FP64")
         rc = time_solve(D, spec, D.FP64, 500, args.warmup, 100, scheme=D.SCHEME_EXP_SPLIT_2BIS)
         variants["step2bis_corrected_fp64"] = {

@@ -259,14 +259,15 @@ dirac_status dirac_schedule_get(int32_t n, int32_t precision, int32_t direction,
 dirac_status dirac_get_schedule(const dirac_solver* s, int32_t direction, dirac_schedule* out);
 dirac_status dirac_set_schedule(dirac_solver* s, int32_t direction, const dirac_schedule* sch);
 
-/* State stores of the direction kernels: 0 = ordinary stores (the default),
- * 1 = device-scope write-through stores, which send each line to memory at
- * once instead of leaving it dirty in the XCD's L2 until the kernel ends.
- * Write-through pays on small grids whose kernels are latency-bound and loses
- * on large streaming ones; dirac_autotune measures both and keeps the faster.
- * Results are bitwise the same either way.  Scheme II's plain and printed
- * directional steps without potentials only, and write-through for n1, n2 <=
- * 1024 only (else DIRAC_E_ARG). */
+/* State stores of the direction kernels, a bit mask: bit 0 for the x kernel,
+ * bit 1 for the y kernel; a set bit selects device-scope write-through stores,
+ * which send each line to memory at once instead of leaving it dirty in the
+ * XCD's L2 until the kernel ends (0 = ordinary stores, the default).
+ * Write-through pays on some small grids whose kernels are latency-bound and
+ * loses on large streaming ones; dirac_autotune measures both per direction
+ * and keeps the faster.  Results are bitwise the same either way.  Scheme II's
+ * plain and printed directional steps without potentials only, and
+ * write-through for n1, n2 <= 1024 only (else DIRAC_E_ARG). */
 dirac_status dirac_set_store_mode(dirac_solver* s, int32_t write_through);
 dirac_status dirac_get_store_mode(const dirac_solver* s, int32_t* write_through);
 
@@ -292,10 +293,11 @@ dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
  * potentials (DIRAC_E_ARG). */
 dirac_status dirac_time_directions(dirac_solver* s, int32_t reps, double* us_out);
 
-/* Autotuner: time every compiled schedule of both directions on this solver's
- * own buffers (the state is saved and restored, so the solve is unchanged),
- * then both store modes with the chosen schedules; keep the fastest per (n,
- * precision, direction, grid shape) in a process-wide cache and apply it.
+/* Autotuner: time every compiled schedule and store mode of each direction on
+ * this solver's own buffers (the state is saved and restored, so the solve is
+ * unchanged), x then y, twice over so each direction is tuned with the other's
+ * choice in place; keep the fastest per (n, precision, direction, grid shape)
+ * in a process-wide cache and apply it.
  * reps = timed steps per candidate, in [1, 4096]; candidates run as in
  * dirac_step_n's graph mode. */
 dirac_status dirac_autotune(dirac_solver* s, int32_t reps);

@@ -246,11 +246,11 @@ int solver_mode(const dirac_solver* s) { return (s->curved ? 2 : 0) + (s->pml ? 
 constexpr int kStoreWtMaxN = 1024;
 bool store_wt_compiled(const dirac_solver* s) { return s->g.n1 <= kStoreWtMaxN && s->g.n2 <= kStoreWtMaxN; }
 
-// Store mode the autotuner measured fastest for this shape (kept with the
-// direction-x entry), else ordinary stores.
-bool pick_store_mode(int prec, int n1, int n2, int mode) {
+// Store mode the autotuner measured fastest for this direction and shape, else
+// ordinary stores.
+bool pick_store_mode(int prec, int n, int dir, int other, int mode) {
     std::lock_guard<std::mutex> lk(tune_mutex());
-    auto it = tune_cache().find(TuneKey{prec, n1, 0, n2, mode});
+    auto it = tune_cache().find(TuneKey{prec, n, dir, other, mode});
     return it != tune_cache().end() && it->second.wt != 0;
 }
 
@@ -283,7 +283,7 @@ StageParams<T> stage_params(const dirac_solver* s, int dir, int e_pre, int e_pos
     p.e_pre = e_pre;
     p.e_post = e_post;
     p.e0u = cpx<T>{(T)s->e0u_re, (T)s->e0u_im};
-    p.wt = s->store_wt ? 1 : 0;
+    p.wt = s->store_wt[dir] ? 1 : 0;
     return p;
 }
 
@@ -631,7 +631,8 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
     const int mode = solver_mode(s);
     s->sched[0] = pick_entry(prec, g->n1, 0, g->n2, mode);
     s->sched[1] = pick_entry(prec, g->n2, 1, g->n1, mode);
-    s->store_wt = store_wt_compiled(s) && pick_store_mode(prec, g->n1, g->n2, mode);
+    s->store_wt[0] = store_wt_compiled(s) && pick_store_mode(prec, g->n1, 0, g->n2, mode);
+    s->store_wt[1] = store_wt_compiled(s) && pick_store_mode(prec, g->n2, 1, g->n1, mode);
     *out = s;
     return DIRAC_OK;
 }
@@ -801,20 +802,21 @@ dirac_status dirac_set_schedule(dirac_solver* s, int32_t dir, const dirac_schedu
 }
 
 dirac_status dirac_set_store_mode(dirac_solver* s, int32_t write_through) {
-    if (!s || (write_through != 0 && write_through != 1)) return fail(DIRAC_E_ARG, "bad arguments");
+    if (!s || write_through < 0 || write_through > 3) return fail(DIRAC_E_ARG, "bad arguments");
     if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || s->has_em)
         return fail(DIRAC_E_ARG, "the store mode applies to Scheme II's plain and printed directional steps "
                                  "without potentials only");
     if (write_through && !store_wt_compiled(s))
         return fail(DIRAC_E_ARG, "write-through stores are compiled for n1, n2 <= %d only", kStoreWtMaxN);
-    s->store_wt = write_through != 0;
+    s->store_wt[0] = (write_through & 1) != 0;
+    s->store_wt[1] = (write_through & 2) != 0;
     drop_graph(s);
     return DIRAC_OK;
 }
 
 dirac_status dirac_get_store_mode(const dirac_solver* s, int32_t* write_through) {
     if (!s || !write_through) return fail(DIRAC_E_ARG, "bad arguments");
-    *write_through = s->store_wt ? 1 : 0;
+    *write_through = (s->store_wt[0] ? 1 : 0) | (s->store_wt[1] ? 2 : 0);
     return DIRAC_OK;
 }
 
@@ -957,31 +959,36 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
         hipEventElapsedTime(&ms, e0, e1);
         return DIRAC_OK;
     };
-    s->store_wt = false;
+    // Coordinate search over (schedule, store mode) per direction, two sweeps
+    // x, y, x, y: the choices interact (the y kernel reads what the x kernel
+    // wrote, and how it was written), so each direction is re-tuned once with
+    // the other's choice in place.
+    const bool wt_ok = store_wt_compiled(s);
+    s->store_wt[0] = s->store_wt[1] = false;
     double dir_ms[2] = {0, 0};
-    for (int dir = 0; dir < 2 && result == DIRAC_OK; ++dir) {
-        const int n = dir == 0 ? s->g.n1 : s->g.n2;
-        const KernelEntry* best = s->sched[dir];
-        double best_ms = 1e300;
-        for (const auto& e : kernel_registry()) {
-            if (e.prec != s->prec || e.n != n || e.dir != dir) continue;
-            s->sched[dir] = &e;
-            float ms = 0;
-            if ((result = time_steps(ms)) != DIRAC_OK) break;
-            if (ms < best_ms) { best_ms = ms; best = &e; }
+    for (int sweep = 0; sweep < 2 && result == DIRAC_OK; ++sweep) {
+        for (int dir = 0; dir < 2 && result == DIRAC_OK; ++dir) {
+            const int n = dir == 0 ? s->g.n1 : s->g.n2;
+            const KernelEntry* best = s->sched[dir];
+            bool best_wt = s->store_wt[dir];
+            double best_ms = 1e300;
+            for (const auto& e : kernel_registry()) {
+                if (e.prec != s->prec || e.n != n || e.dir != dir) continue;
+                for (int wt = 0; wt <= (wt_ok ? 1 : 0) && result == DIRAC_OK; ++wt) {
+                    s->sched[dir] = &e;
+                    s->store_wt[dir] = wt != 0;
+                    float ms = 0;
+                    if ((result = time_steps(ms)) != DIRAC_OK) break;
+                    if (ms < best_ms) { best_ms = ms; best = &e; best_wt = wt != 0; }
+                }
+                if (result != DIRAC_OK) break;
+            }
+            s->sched[dir] = best;
+            s->store_wt[dir] = best_wt;
+            dir_ms[dir] = best_ms;
         }
-        s->sched[dir] = best;
-        dir_ms[dir] = best_ms;
     }
-    // then the store mode with the chosen schedules
-    if (result == DIRAC_OK && store_wt_compiled(s)) {
-        float ms_wb = 0, ms_wt = 0;
-        if ((result = time_steps(ms_wb)) == DIRAC_OK) {
-            s->store_wt = true;
-            if ((result = time_steps(ms_wt)) == DIRAC_OK) s->store_wt = ms_wt < ms_wb;
-        }
-        if (result != DIRAC_OK) s->store_wt = false;
-    }
+    if (result != DIRAC_OK) s->store_wt[0] = s->store_wt[1] = false;
     if (result == DIRAC_OK) {
         std::lock_guard<std::mutex> lk(tune_mutex());
         for (int dir = 0; dir < 2; ++dir) {
@@ -989,7 +996,7 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
             const int other = dir == 0 ? s->g.n2 : s->g.n1;
             const KernelEntry* best = s->sched[dir];
             tune_cache()[TuneKey{s->prec, n, dir, other, mode}] =
-                TuneVal{best->radix, best->lines, best->cpt, dir_ms[dir] / reps, s->store_wt ? 1 : 0};
+                TuneVal{best->radix, best->lines, best->cpt, dir_ms[dir] / reps, s->store_wt[dir] ? 1 : 0};
         }
     }
     (void)hipEventDestroy(e0);

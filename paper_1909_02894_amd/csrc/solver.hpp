@@ -61,7 +61,7 @@ struct dirac_solver {
     int64_t step = 0;
     bool has_state = false;
     const dirac::KernelEntry* sched[2] = {nullptr, nullptr};
-    bool store_wt = false;     // write-through state stores in the direction kernels
+    bool store_wt[2] = {false, false};   // write-through state stores, x / y direction kernels
     bool use_graph = true;
     int graph_chunk = 32;
     hipGraph_t graph = nullptr;

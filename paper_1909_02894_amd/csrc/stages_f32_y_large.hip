@@ -9,6 +9,7 @@
 #define DIRAC_DIR 1
 REGO(512, 8, 4, 2)
 REG(512, 8, 4, 1)
+REG(512, 8, 2, 1)
 REG(512, 8, 8, 2)
 REG(512, 16, 8, 2)
 REGO(1024, 8, 4, 1)

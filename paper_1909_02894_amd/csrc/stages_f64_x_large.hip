@@ -11,6 +11,7 @@ REGO(512, 4, 1, 2)
 REG(512, 8, 2, 1)
 REG(512, 4, 1, 1)
 REG(512, 8, 1, 2)
+REG(512, 8, 1, 1)
 REGO(1024, 8, 1, 1)
 REG(1024, 8, 1, 2)
 REG(1024, 4, 1, 1)

@@ -12,6 +12,7 @@ REG(512, 4, 2, 2)
 REG(512, 8, 2, 2)
 REG(512, 8, 4, 2)
 REG(512, 8, 4, 1)
+REG(512, 8, 1, 1)
 REGO(1024, 8, 4, 2)
 REG(1024, 8, 4, 1)
 REG(1024, 8, 2, 2)

@@ -376,13 +376,13 @@ class Solver:
         _check(lib.dirac_set_launch_mode(self.h, int(use_graph), chunk))
 
     def store_mode(self) -> int:
-        """1 if the direction kernels store the state write-through, else 0."""
+        """Write-through mask of the direction kernels' state stores: bit 0 x, bit 1 y."""
         v = C.c_int32()
         _check(lib.dirac_get_store_mode(self.h, C.byref(v)))
         return v.value
 
-    def set_store_mode(self, write_through: bool):
-        _check(lib.dirac_set_store_mode(self.h, int(bool(write_through))))
+    def set_store_mode(self, mask: int):
+        _check(lib.dirac_set_store_mode(self.h, int(mask)))
 
     def step_n_timed(self, n):
         ms = (C.c_double * 2)()
