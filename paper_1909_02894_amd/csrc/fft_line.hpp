@@ -80,18 +80,23 @@ template <typename T>
 __device__ __forceinline__ T gld(const T* p) { return *(const __attribute__((address_space(1))) T*)p; }
 template <typename T>
 __device__ __forceinline__ void gst(T* p, T v) { *(__attribute__((address_space(1))) T*)p = v; }
-// Device-scope write-through store (global_store ... sc1, in 8-byte pieces): the
-// line goes to memory at once instead of sitting dirty in this XCD's L2 until
-// the end-of-dispatch writeback.
-template <typename T>
-__device__ __forceinline__ void gst_wt(T* p, T v) {
-    static_assert(sizeof(T) % 8 == 0, "8-byte pieces");
-    typedef __attribute__((address_space(1))) unsigned long long g64;
-    g64* q = (g64*)p;
-    unsigned long long w[sizeof(T) / 8];
-    __builtin_memcpy(w, &v, sizeof(T));
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) __hip_atomic_store(q + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Device-scope write-through stores (buffer_store ... sc1) of 16 or 8 bytes at
+// byte offset `off` from the wave-uniform `base`: the line goes to memory at
+// once instead of sitting dirty in this XCD's L2 until the end-of-dispatch
+// write-back.  Full-width stores, so a wave's contiguous stores still combine
+// into whole lines.  The resource's third dword is the gfx9 raw-buffer format;
+// the range (2 GiB) covers every supported state.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wt_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, 0x00020000);
+}
+constexpr int kCacheSc1 = 16;      // cache-policy bit sc1 of the buffer intrinsics
+__device__ __forceinline__ void gst_wt16(const void* base, uint32_t off, u32x4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, wt_rsrc(base), (int)off, 0, kCacheSc1);
+}
+__device__ __forceinline__ void gst_wt8(const void* base, uint32_t off, u32x2 v) {
+    __builtin_amdgcn_raw_buffer_store_b64(v, wt_rsrc(base), (int)off, 0, kCacheSc1);
 }
 __device__ __forceinline__ cpx<float> gld(const cpx<float>* p) {
     const f2v v = gld(reinterpret_cast<const f2v*>(p));

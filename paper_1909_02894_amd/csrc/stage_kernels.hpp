@@ -86,24 +86,40 @@ __device__ __forceinline__ void load_point(const T* p, uint32_t idx, cpx<T>& u, 
         v = {(T)A.z, (T)A.w};
     }
 }
-// WT: device-scope write-through stores (gst_wt) instead of ordinary ones.
+// WT: device-scope write-through stores (gst_wt16 / gst_wt8) instead of
+// ordinary ones; p must be wave-uniform then (the kernel's state pointer).
 template <typename T, bool WT = false>
 __device__ __forceinline__ void store_point(T* p, uint32_t idx, cpx<T> u, cpx<T> v) {
-    char* b = reinterpret_cast<char*>(p) + idx * (uint32_t)(4 * sizeof(T));
-    auto st = [](auto* q, auto x) { if constexpr (WT) gst_wt(q, x); else gst(q, x); };
+    const uint32_t off = idx * (uint32_t)(4 * sizeof(T));
+    char* b = reinterpret_cast<char*>(p) + off;
     if constexpr (sizeof(T) == 8) {
-        st(reinterpret_cast<d2v*>(b), d2v{u.re, u.im});
-        st(reinterpret_cast<d2v*>(b) + 1, d2v{v.re, v.im});
+        const d2v a{u.re, u.im}, c{v.re, v.im};
+        if constexpr (WT) {
+            gst_wt16(p, off, __builtin_bit_cast(u32x4, a));
+            gst_wt16(p, off + 16, __builtin_bit_cast(u32x4, c));
+        } else {
+            gst(reinterpret_cast<d2v*>(b), a);
+            gst(reinterpret_cast<d2v*>(b) + 1, c);
+        }
     } else {
-        st(reinterpret_cast<f4v*>(b), f4v{u.re, u.im, v.re, v.im});
+        const f4v a{u.re, u.im, v.re, v.im};
+        if constexpr (WT) gst_wt16(p, off, __builtin_bit_cast(u32x4, a));
+        else gst(reinterpret_cast<f4v*>(b), a);
     }
 }
 template <typename T, bool WT = false>
 __device__ __forceinline__ void store_comp(T* p, uint32_t idx, int c, cpx<T> v) {
-    char* b = reinterpret_cast<char*>(p) + idx * (uint32_t)(4 * sizeof(T)) + c * (uint32_t)(2 * sizeof(T));
-    auto st = [](auto* q, auto x) { if constexpr (WT) gst_wt(q, x); else gst(q, x); };
-    if constexpr (sizeof(T) == 8) st(reinterpret_cast<d2v*>(b), d2v{v.re, v.im});
-    else st(reinterpret_cast<f2v*>(b), f2v{v.re, v.im});
+    const uint32_t off = idx * (uint32_t)(4 * sizeof(T)) + c * (uint32_t)(2 * sizeof(T));
+    char* b = reinterpret_cast<char*>(p) + off;
+    if constexpr (sizeof(T) == 8) {
+        const d2v a{v.re, v.im};
+        if constexpr (WT) gst_wt16(p, off, __builtin_bit_cast(u32x4, a));
+        else gst(reinterpret_cast<d2v*>(b), a);
+    } else {
+        const f2v a{v.re, v.im};
+        if constexpr (WT) gst_wt8(p, off, __builtin_bit_cast(u32x2, a));
+        else gst(reinterpret_cast<f2v*>(b), a);
+    }
 }
 
 // Workgroup -> tile map that keeps neighbouring tiles on one XCD.  Workgroups
