@@ -266,8 +266,8 @@ dirac_status dirac_set_schedule(dirac_solver* s, int32_t direction, const dirac_
  * Write-through pays on some small grids whose kernels are latency-bound and
  * loses on large streaming ones; dirac_autotune measures both per direction
  * and keeps the faster.  Results are bitwise the same either way.  Scheme II's
- * plain and printed directional steps without potentials only, and
- * write-through for n1, n2 <= 1024 only (else DIRAC_E_ARG). */
+ * plain and printed directional steps without potentials only; write-through
+ * for the y kernel only with n2 <= 1024 (else DIRAC_E_ARG). */
 dirac_status dirac_set_store_mode(dirac_solver* s, int32_t write_through);
 dirac_status dirac_get_store_mode(const dirac_solver* s, int32_t* write_through);
 

@@ -241,10 +241,9 @@ static std::mutex& tune_mutex() { static std::mutex m; return m; }
 
 int solver_mode(const dirac_solver* s) { return (s->curved ? 2 : 0) + (s->pml ? 1 : 0); }
 
-// The direction kernels carry the write-through store path for lines of at
-// most this many points (stage_tile).
-constexpr int kStoreWtMaxN = 1024;
-bool store_wt_compiled(const dirac_solver* s) { return s->g.n1 <= kStoreWtMaxN && s->g.n2 <= kStoreWtMaxN; }
+// Whether the direction kernel carries the write-through store path (every
+// row kernel; column kernels up to kStoreWtMaxColN points, stage_tile).
+bool store_wt_compiled(const dirac_solver* s, int dir) { return dir == 0 || s->g.n2 <= kStoreWtMaxColN; }
 
 // Store mode the autotuner measured fastest for this direction and shape, else
 // ordinary stores.
@@ -631,8 +630,8 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
     const int mode = solver_mode(s);
     s->sched[0] = pick_entry(prec, g->n1, 0, g->n2, mode);
     s->sched[1] = pick_entry(prec, g->n2, 1, g->n1, mode);
-    s->store_wt[0] = store_wt_compiled(s) && pick_store_mode(prec, g->n1, 0, g->n2, mode);
-    s->store_wt[1] = store_wt_compiled(s) && pick_store_mode(prec, g->n2, 1, g->n1, mode);
+    s->store_wt[0] = store_wt_compiled(s, 0) && pick_store_mode(prec, g->n1, 0, g->n2, mode);
+    s->store_wt[1] = store_wt_compiled(s, 1) && pick_store_mode(prec, g->n2, 1, g->n1, mode);
     *out = s;
     return DIRAC_OK;
 }
@@ -806,8 +805,9 @@ dirac_status dirac_set_store_mode(dirac_solver* s, int32_t write_through) {
     if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || s->has_em)
         return fail(DIRAC_E_ARG, "the store mode applies to Scheme II's plain and printed directional steps "
                                  "without potentials only");
-    if (write_through && !store_wt_compiled(s))
-        return fail(DIRAC_E_ARG, "write-through stores are compiled for n1, n2 <= %d only", kStoreWtMaxN);
+    if ((write_through & 2) && !store_wt_compiled(s, 1))
+        return fail(DIRAC_E_ARG, "write-through stores of the y kernel are compiled for n2 <= %d only",
+                    kStoreWtMaxColN);
     s->store_wt[0] = (write_through & 1) != 0;
     s->store_wt[1] = (write_through & 2) != 0;
     drop_graph(s);
@@ -963,7 +963,6 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
     // x, y, x, y: the choices interact (the y kernel reads what the x kernel
     // wrote, and how it was written), so each direction is re-tuned once with
     // the other's choice in place.
-    const bool wt_ok = store_wt_compiled(s);
     s->store_wt[0] = s->store_wt[1] = false;
     double dir_ms[2] = {0, 0};
     for (int sweep = 0; sweep < 2 && result == DIRAC_OK; ++sweep) {
@@ -974,7 +973,7 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
             double best_ms = 1e300;
             for (const auto& e : kernel_registry()) {
                 if (e.prec != s->prec || e.n != n || e.dir != dir) continue;
-                for (int wt = 0; wt <= (wt_ok ? 1 : 0) && result == DIRAC_OK; ++wt) {
+                for (int wt = 0; wt <= (store_wt_compiled(s, dir) ? 1 : 0) && result == DIRAC_OK; ++wt) {
                     s->sched[dir] = &e;
                     s->store_wt[dir] = wt != 0;
                     float ms = 0;

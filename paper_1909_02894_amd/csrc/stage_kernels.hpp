@@ -33,7 +33,7 @@ struct StageParams {
                                  // direction-x launches (which load E up front), 0 in direction y
     int e_post;                  // Step-5 exponential applied after the blend (0, 1)
     cpx<T> e0u;                  // uniform e0 when E is null (flat: e^{-i dt m c^2 / 2})
-    int wt;                      // 1: write-through state stores (lines of n <= 1024)
+    int wt;                      // 1: write-through state stores (rows; columns of n <= 1024)
 };
 
 struct ObsParams {
@@ -86,6 +86,9 @@ __device__ __forceinline__ void load_point(const T* p, uint32_t idx, cpx<T>& u, 
         v = {(T)A.z, (T)A.w};
     }
 }
+// Longest column line whose kernel carries the write-through store path.
+constexpr int kStoreWtMaxColN = 1024;
+
 // WT: device-scope write-through stores (gst_wt16 / gst_wt8) instead of
 // ordinary ones; p must be wave-uniform then (the kernel's state pointer).
 template <typename T, bool WT = false>
@@ -287,10 +290,10 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
         applyE(1);
     }
     if (!valid) return;
-    // write-through stores exist for the shorter lines only: they pay on
-    // small latency-bound grids, and the extra store path perturbs the code
-    // of the long-line kernels (measured 18% slower at n = 4096 unexecuted)
-    if (N <= 1024 && p.wt) {
+    // write-through stores exist in every row kernel and in the column kernels
+    // of n <= 1024: the extra store path perturbs the long column kernels
+    // (the 4096-point one ran 16% slower with it, executed or not)
+    if ((!COLS || N <= kStoreWtMaxColN) && p.wt) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint32_t q = gidx(line, c.j + r * P);

@@ -243,8 +243,18 @@ def test_write_through_stores_are_bitwise(D, prec):
                 s.close()
     big = D.Solver.from_spec(W.flat_small(n=2048, steps=1), precision=prec)
     with pytest.raises(D.DiracError):
-        big.set_store_mode(1)                  # compiled for n <= 1024 only
+        big.set_store_mode(2)                  # y kernels: compiled for n <= 1024 only
     assert big.store_mode() == 0
+    big.set_store_mode(1)                      # row kernels of any length
+    assert big.store_mode() == 1
+    big_spec = W.flat_small(n=2048, steps=2)
+    outs = []
+    for mask in (0, 1):
+        big.set_store_mode(mask)
+        big.set_initial_spinor(W.initial_spinor(big_spec))
+        big.step_n(2)
+        outs.append(big.get_spinor())
+    assert np.array_equal(outs[0], outs[1])
     big.close()
     s = D.Solver.from_spec(spec, precision=prec)
     s.set_initial_spinor(psi0)
