@@ -81,8 +81,7 @@ def time_solve(D, spec, precision, steps, warmup, timed_steps, scheme=0):
     psi0 = torch.from_numpy(W.initial_spinor(spec).view(np.float64).copy()).cuda()
     s.set_initial_spinor_device(psi0)
     torch.cuda.synchronize()
-    if scheme != D.SCHEME_EXP_SPLIT_2BIS:
-        s.autotune(200)              # warm-up part 1: pick the fastest compiled schedules and store mode
+    s.autotune(200)                  # warm-up part 1: pick the fastest schedules and store modes
     s.step_n(warmup)
     torch.cuda.synchronize()
     st = s.stream
@@ -236,6 +235,7 @@ def bench_em(D, W, spec, steps=500):
     pot["Ax"][:] = 1.0
     s = D.Solver.from_spec(spec, precision=D.FP64, potentials=pot)
     s.set_initial_spinor(W.initial_spinor(spec))
+    s.autotune(50)                   # store modes (the state and step counter are restored)
     s.step_n(10)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)

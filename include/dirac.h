@@ -265,9 +265,9 @@ dirac_status dirac_set_schedule(dirac_solver* s, int32_t direction, const dirac_
  * XCD's L2 until the kernel ends (0 = ordinary stores, the default).
  * Write-through pays on some small grids whose kernels are latency-bound and
  * loses on large streaming ones; dirac_autotune measures both per direction
- * and keeps the faster.  Results are bitwise the same either way.  Scheme II's
- * plain and printed directional steps without potentials only; write-through
- * for the y kernel only with n2 <= 1024 (else DIRAC_E_ARG). */
+ * and keeps the faster.  Results are bitwise the same either way.  Every form
+ * of Scheme II's directional step (not Scheme I); write-through for the y
+ * kernel only with n2 <= 1024 (else DIRAC_E_ARG). */
 dirac_status dirac_set_store_mode(dirac_solver* s, int32_t write_through);
 dirac_status dirac_get_store_mode(const dirac_solver* s, int32_t* write_through);
 
@@ -297,7 +297,9 @@ dirac_status dirac_time_directions(dirac_solver* s, int32_t reps, double* us_out
  * this solver's own buffers (the state is saved and restored, so the solve is
  * unchanged), x then y, twice over so each direction is tuned with the other's
  * choice in place; keep the fastest per (n, precision, direction, grid shape)
- * in a process-wide cache and apply it.
+ * in a process-wide cache and apply it.  The corrected second-order step and
+ * solves with potentials have one schedule per size: only their store modes
+ * are searched.  Not for Scheme I (DIRAC_E_ARG).
  * reps = timed steps per candidate, in [1, 4096]; candidates run as in
  * dirac_step_n's graph mode. */
 dirac_status dirac_autotune(dirac_solver* s, int32_t reps);

@@ -185,8 +185,13 @@ __global__ void __launch_bounds__(bis_threads(N)) bis_stage_kernel(BisParams<T> 
         applyE(1);
     }
     if (!valid) return;
+    if ((!COLS || N <= kStoreWtMaxColN) && p.wt) {     // write-through (as in stage_tile)
 #pragma unroll
-    for (int r = 0; r < R; ++r) store_point(p.psi, gidx(line, c.j + r * P), v[0][r], v[1][r]);
+        for (int r = 0; r < R; ++r) store_point<T, true>(p.psi, gidx(line, c.j + r * P), v[0][r], v[1][r]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) store_point(p.psi, gidx(line, c.j + r * P), v[0][r], v[1][r]);
+    }
 }
 
 }  // namespace dirac

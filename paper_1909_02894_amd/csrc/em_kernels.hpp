@@ -199,7 +199,8 @@ __global__ void __launch_bounds__(em_threads(N)) em_stage_kernel(EmParams<T> ep)
             load_record(ep.rec, g, qe, ae);
             apply_mat(em_exponential(qe, ep.fA[2], ep.fV[2]), u, w);
         }
-        store_point(p.psi, g, u, w);
+        if ((!COLS || N <= kStoreWtMaxColN) && p.wt) store_point<T, true>(p.psi, g, u, w);   // as in stage_tile
+        else store_point(p.psi, g, u, w);
     }
 }
 

@@ -240,6 +240,11 @@ static std::map<TuneKey, TuneVal>& tune_cache() { static std::map<TuneKey, TuneV
 static std::mutex& tune_mutex() { static std::mutex m; return m; }
 
 int solver_mode(const dirac_solver* s) { return (s->curved ? 2 : 0) + (s->pml ? 1 : 0); }
+// Tuning-cache mode: the kernel mode plus the kernel family (the corrected
+// second-order step and the potential kernels are tuned apart).
+int tune_mode(const dirac_solver* s) {
+    return solver_mode(s) + (s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS ? 4 : 0) + (s->has_em ? 8 : 0);
+}
 
 // Whether the direction kernel carries the write-through store path (every
 // row kernel; column kernels up to kStoreWtMaxColN points, stage_tile).
@@ -627,7 +632,7 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
                          "stable only for b in [0, 1]", host_fold[0], host_fold[1]));
     s->b_min = host_fold[0];
     s->b_max = host_fold[1];
-    const int mode = solver_mode(s);
+    const int mode = tune_mode(s);
     s->sched[0] = pick_entry(prec, g->n1, 0, g->n2, mode);
     s->sched[1] = pick_entry(prec, g->n2, 1, g->n1, mode);
     s->store_wt[0] = store_wt_compiled(s, 0) && pick_store_mode(prec, g->n1, 0, g->n2, mode);
@@ -802,9 +807,8 @@ dirac_status dirac_set_schedule(dirac_solver* s, int32_t dir, const dirac_schedu
 
 dirac_status dirac_set_store_mode(dirac_solver* s, int32_t write_through) {
     if (!s || write_through < 0 || write_through > 3) return fail(DIRAC_E_ARG, "bad arguments");
-    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || s->has_em)
-        return fail(DIRAC_E_ARG, "the store mode applies to Scheme II's plain and printed directional steps "
-                                 "without potentials only");
+    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES)
+        return fail(DIRAC_E_ARG, "the store mode applies to Scheme II's directional steps");
     if ((write_through & 2) && !store_wt_compiled(s, 1))
         return fail(DIRAC_E_ARG, "write-through stores of the y kernel are compiled for n2 <= %d only",
                     kStoreWtMaxColN);
@@ -925,9 +929,11 @@ dirac_status dirac_time_directions(dirac_solver* s, int32_t reps, double* us_out
 
 dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
     if (!s || reps < 1 || reps > 4096) return fail(DIRAC_E_ARG, "bad arguments");
-    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES || s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || s->has_em)
-        return fail(DIRAC_E_ARG, "schedules apply to Scheme II's plain and printed directional steps without "
-                                 "potentials only");
+    if (s->scheme.scheme == DIRAC_SCHEME_CN_GMRES)
+        return fail(DIRAC_E_ARG, "the autotuner applies to Scheme II's directional steps");
+    // the corrected second-order step and the potential kernels have one
+    // schedule each: only their store modes are searched
+    const bool one_schedule = s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || s->has_em;
     if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
     const size_t N = (size_t)s->g.n1 * s->g.n2;
     const size_t bytes = N * 4 * (s->prec == DIRAC_FP32 ? 4 : 8);
@@ -937,7 +943,7 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
-    const int mode = solver_mode(s);
+    const int mode = tune_mode(s);
     dirac_status result = DIRAC_OK;
     // Candidates are timed as they run: reps + 1 steps whose middle reps - 1
     // (y, x) pairs replay one HIP graph (direct launches of small grids would
@@ -973,6 +979,7 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
             double best_ms = 1e300;
             for (const auto& e : kernel_registry()) {
                 if (e.prec != s->prec || e.n != n || e.dir != dir) continue;
+                if (one_schedule && &e != best) continue;
                 for (int wt = 0; wt <= (store_wt_compiled(s, dir) ? 1 : 0) && result == DIRAC_OK; ++wt) {
                     s->sched[dir] = &e;
                     s->store_wt[dir] = wt != 0;

@@ -98,11 +98,32 @@ def test_em_limits(D):
     spec = W.curved_bump(n=64, steps=1)
     s = D.Solver.from_spec(spec, potentials=potentials(spec))
     s.set_initial_spinor(W.initial_spinor(spec))
-    with pytest.raises(D.DiracError):
-        s.autotune(2)
+    s.autotune(2)                                    # store modes only
     b = D.Batch(precision=D.FP64, capacity=2)
     with pytest.raises(D.DiracError):
         b.add(s)
     b.close()
     us = s.time_directions(5)
     assert all(u > 0 for u in us)
+
+
+def test_em_store_modes_are_bitwise_and_tuned(D):
+    # write-through stores change no bit; the tuner restores the state and the
+    # step counter (the potentials' time depends on it)
+    spec = W.curved_bump(n=64, steps=7, m=0.5)
+    pot = potentials(spec)
+    outs = []
+    for mask in (0, 3):
+        s = D.Solver.from_spec(spec, potentials=pot)
+        s.set_store_mode(mask)
+        s.set_initial_spinor(W.initial_spinor(spec))
+        s.step_n(7)
+        outs.append(s.get_spinor())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+    s = D.Solver.from_spec(spec, potentials=pot)
+    s.set_initial_spinor(W.initial_spinor(spec))
+    s.autotune(3)
+    assert s.observables()["step"] == 0
+    s.step_n(7)
+    assert np.array_equal(s.get_spinor(), outs[0])

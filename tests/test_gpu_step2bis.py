@@ -114,8 +114,7 @@ def test_step2bis_limits(D):
     spec = W.curved_bump(n=64, steps=1)
     s = D.Solver.from_spec(spec, scheme=D.SCHEME_EXP_SPLIT_2BIS)
     s.set_initial_spinor(W.initial_spinor(spec))
-    with pytest.raises(D.DiracError):
-        s.autotune(2)
+    s.autotune(2)                                    # store modes only
     b = D.Batch(precision=D.FP64, capacity=2)
     with pytest.raises(D.DiracError):
         b.add(s)
@@ -124,3 +123,30 @@ def test_step2bis_limits(D):
     with pytest.raises(D.DiracError) as ei:
         D.Solver.from_spec(spec, scheme=D.SCHEME_EXP_SPLIT_2BIS)
     assert "2048" in str(ei.value)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_corrected_store_modes_are_bitwise_and_tuned(D, prec):
+    # write-through stores change no bit; the tuner searches them (and restores
+    # the state and step counter); a 2048-point column kernel carries none
+    spec = W.curved_bump(n=128, steps=6, m=0.5)
+    outs = []
+    for mask in (0, 1, 2, 3):
+        s = D.Solver.from_spec(spec, precision=prec, scheme=D.SCHEME_EXP_SPLIT_2BIS)
+        s.set_store_mode(mask)
+        s.set_initial_spinor(W.initial_spinor(spec))
+        s.step_n(6)
+        outs.append(s.get_spinor())
+        s.close()
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+    s = D.Solver.from_spec(spec, precision=prec, scheme=D.SCHEME_EXP_SPLIT_2BIS)
+    s.set_initial_spinor(W.initial_spinor(spec))
+    s.autotune(3)
+    assert s.store_mode() in (0, 1, 2, 3) and s.observables()["step"] == 0
+    s.step_n(6)
+    assert np.array_equal(s.get_spinor(), outs[0])
+    tall = W.flat_small(n=16, steps=1)
+    tall.n2, tall.pml_width = 2048, 2
+    t = D.Solver.from_spec(tall, precision=prec, scheme=D.SCHEME_EXP_SPLIT_2BIS)
+    with pytest.raises(D.DiracError):
+        t.set_store_mode(2)
