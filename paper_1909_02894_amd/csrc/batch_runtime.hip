@@ -291,8 +291,8 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
 
     const int64_t qmax = steps[act[0]];
     // the launches of phase (step k, direction d): one per size group with
-    // work, or -- when some group is too small to fill the GPU alone -- one
-    // launch of the multi-group kernel over all of them
+    // work, except that the groups too small to fill the GPU alone share one
+    // launch of the multi-group kernel (at most 8 sizes: n = 16 .. 2048)
     struct GroupLaunch {
         const void* fn;
         size_t smem;

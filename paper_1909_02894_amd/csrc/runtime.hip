@@ -945,10 +945,11 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
     const int mode = tune_mode(s);
     dirac_status result = DIRAC_OK;
-    // Candidates are timed as they run: reps + 1 steps whose middle reps - 1
-    // (y, x) pairs replay one HIP graph (direct launches of small grids would
-    // time the host's launch rate, not the kernels).  The first pass builds the
-    // graph and warms up; the second is timed.
+    // Candidates are timed as they run: reps + 1 steps whose middle reps (y, x)
+    // pairs replay one HIP graph (direct launches of small grids would time
+    // the host's launch rate, not the kernels; solves with potentials launch
+    // directly anyway).  The first pass builds the graph and warms up; the
+    // second is timed.
     const bool use_graph0 = s->use_graph;
     const int chunk0 = s->graph_chunk;
     s->use_graph = true;
