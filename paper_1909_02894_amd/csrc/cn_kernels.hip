@@ -181,6 +181,13 @@ __global__ void cn_scale_kernel(const double* x, double* y, size_t n, double alp
         y[i] = alpha * x[i];
 }
 
+// y <- x / sqrt(norm2[0]): normalisation by a norm the device computed
+__global__ void cn_scale_by_norm_kernel(const double* x, double* y, size_t n, const double* norm2) {
+    const double alpha = 1.0 / sqrt(norm2[0]);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = alpha * x[i];
+}
+
 // y <- x - y  (residual r = b - A x0 with y = A x0)
 __global__ void cn_sub_kernel(const double* x, double* y, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -235,6 +242,11 @@ hipError_t launch_cn_axpy(const double* V, size_t vstride, int nk, const double*
 
 hipError_t launch_cn_scale(const double* x, double* y, size_t n, double alpha, hipStream_t s) {
     hipLaunchKernelGGL(cn_scale_kernel, dim3(1024), dim3(256), 0, s, x, y, n, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_cn_scale_by_norm(const double* x, double* y, size_t n, const double* norm2, hipStream_t s) {
+    hipLaunchKernelGGL(cn_scale_by_norm_kernel, dim3(1024), dim3(256), 0, s, x, y, n, norm2);
     return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ hipError_t launch_cn_dots(const double* V, size_t vstride, int nk, const double*
 hipError_t launch_cn_axpy(const double* V, size_t vstride, int nk, const double* coef, double* w, size_t ncplx,
                           double sign, hipStream_t s);
 hipError_t launch_cn_scale(const double* x, double* y, size_t n, double alpha, hipStream_t s);
+hipError_t launch_cn_scale_by_norm(const double* x, double* y, size_t n, const double* norm2, hipStream_t s);
 hipError_t launch_cn_sub(const double* x, double* y, size_t n, hipStream_t s);
 
 }  // namespace dirac

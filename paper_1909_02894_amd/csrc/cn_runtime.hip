@@ -5,7 +5,7 @@
 // with G = I + (dt/2) alpha.T and G~ = I - (dt/2) alpha.T.  Every vector operation
 // runs on the device; the host holds only the small Hessenberg least-squares
 // problem of each GMRES cycle (Givens rotations, back substitution), and reads
-// one column of it per Arnoldi iteration.
+// its columns in batches (gmres below).
 //
 // GMRES(m): Arnoldi with classical Gram-Schmidt applied twice (CGS2), started
 // from x0 = psi^{n+1/2}; a cycle ends when the rotated residual estimate falls
@@ -38,11 +38,13 @@ struct CnCtx {
     double* work;
     double* V;                        // Krylov basis, m + 1 vectors
     double* part;
-    double* coef;                     // [4][64] complex: h pass 1, h pass 2, norm, update
+    double* coef;                     // [5][64] complex: (unused), (unused), norm, update, rhs norm;
+                                      // then per Arnoldi iteration j: [3][64] h pass 1, h pass 2, norm
     double h;                         // (dt / 2) c
 
     double* vec(int k) const { return V + (size_t)k * vstride; }
     double* coef_row(int r) const { return coef + (size_t)r * 128; }
+    double* rec_row(int j, int r) const { return coef + (size_t)(5 + 3 * j + r) * 128; }
 };
 
 #define CN_TRY(expr, what)                                                                              \
@@ -77,30 +79,46 @@ hipError_t norm2_dev(const CnCtx& c, const double* v, int row) {
     return launch_cn_dots(v, 0, 1, v, c.ncplx, c.part, kCnDotBlocks, 64, c.coef_row(row), c.st);
 }
 
-dirac_status read_coef(const CnCtx& c, double* host, size_t doubles) {
-    CN_TRY(hipMemcpyAsync(host, c.coef, doubles * sizeof(double), hipMemcpyDeviceToHost, c.st), "read GMRES coefficients");
+dirac_status read_coef(const CnCtx& c, const double* src, double* host, size_t doubles) {
+    CN_TRY(hipMemcpyAsync(host, src, doubles * sizeof(double), hipMemcpyDeviceToHost, c.st), "read GMRES coefficients");
     CN_TRY(hipStreamSynchronize(c.st), "synchronise GMRES");
     return DIRAC_OK;
 }
 
-// Solve G x = rhs in place (x = psi on entry is the initial guess).
-dirac_status gmres(CnCtx& c, double bnorm, int64_t& iters, double& rel_res) {
+// Solve G x = rhs in place (x = psi on entry is the initial guess).  The norm
+// of rhs is on the device (coef row 4) and read with the first residual.
+//
+// Arnoldi iterations are queued in batches without a host round trip: each
+// iteration's Hessenberg column and norm go to their own coefficient rows and
+// the next basis vector is normalised on the device by that norm; the host
+// then reads the batch's columns at once and applies the rotations column by
+// column.  A cycle that converges inside a batch uses only its first columns
+// (the later ones were computed and are dropped), so the iterate is the one
+// the column-by-column form gives.  The first batch of a cycle is one short of
+// the previous cycle's length; later batches are single iterations.
+dirac_status gmres(CnCtx& c, int64_t& iters, double& rel_res) {
     dirac_solver* s = c.s;
     const int m = s->scheme.gmres_restart;
-    const double tol = s->scheme.gmres_rtol * bnorm;
     std::vector<zd> H((size_t)(m + 1) * m), g(m + 1), sn(m), y(m);
-    std::vector<double> cs(m), host(3 * 128);
+    std::vector<double> cs(m), host(5 * 128), cols((size_t)3 * 128 * m);
     std::vector<double>& upload = s->cn_host;            // outlives the async upload
     upload.assign(128, 0.0);
     auto Hat = [&](int i, int j) -> zd& { return H[(size_t)i * m + j]; };
     int64_t used = 0;
+    double tol = 0.0, bnorm = 0.0;
+    bool first = true;
     for (;;) {
         // explicit residual r = rhs - G x
         CN_TRY(apply_G(c, c.psi, c.work, +1.0), "apply G");
         CN_TRY(launch_cn_sub(c.rhs, c.work, 4 * c.npts, c.st), "residual");
         CN_TRY(norm2_dev(c, c.work, 2), "residual norm");
-        dirac_status r = read_coef(c, host.data(), 3 * 128);
+        dirac_status r = read_coef(c, c.coef, host.data(), 5 * 128);
         if (r != DIRAC_OK) return r;
+        if (first) {
+            bnorm = std::sqrt(host[512]);
+            tol = s->scheme.gmres_rtol * bnorm;
+            first = false;
+        }
         const double beta = std::sqrt(host[256]);
         if (!std::isfinite(beta)) return fail(DIRAC_E_NONFINITE, "GMRES residual is not finite");
         rel_res = bnorm > 0 ? beta / bnorm : 0.0;
@@ -111,47 +129,64 @@ dirac_status gmres(CnCtx& c, double bnorm, int64_t& iters, double& rel_res) {
         CN_TRY(launch_cn_scale(c.work, c.vec(0), 4 * c.npts, 1.0 / beta, c.st), "normalise");
         std::fill(g.begin(), g.end(), zd(0));
         g[0] = beta;
-        int k = 0;
-        for (int j = 0; j < m; ++j) {
-            CN_TRY(apply_G(c, c.vec(j), c.work, +1.0), "apply G");
-            for (int pass = 0; pass < 2; ++pass) {        // CGS2
-                CN_TRY(launch_cn_dots(c.V, c.vstride, j + 1, c.work, c.ncplx, c.part, kCnDotBlocks, 64,
-                                      c.coef_row(pass), c.st), "Gram-Schmidt dots");
-                CN_TRY(launch_cn_axpy(c.V, c.vstride, j + 1, c.coef_row(pass), c.work, c.ncplx, 1.0, c.st),
-                       "Gram-Schmidt update");
+        int k = 0, j = 0;
+        bool done = false;
+        int batch = std::max(1, s->cn_cycle_len - 1);
+        while (!done && j < m) {
+            const int nb = (int)std::min<int64_t>({(int64_t)batch, (int64_t)(m - j),
+                                                   std::max<int64_t>(1, s->scheme.gmres_max_iter - used)});
+            batch = 1;
+            for (int q = 0; q < nb; ++q) {
+                const int jj = j + q;
+                CN_TRY(apply_G(c, c.vec(jj), c.work, +1.0), "apply G");
+                for (int pass = 0; pass < 2; ++pass) {    // CGS2
+                    CN_TRY(launch_cn_dots(c.V, c.vstride, jj + 1, c.work, c.ncplx, c.part, kCnDotBlocks, 64,
+                                          c.rec_row(jj, pass), c.st), "Gram-Schmidt dots");
+                    CN_TRY(launch_cn_axpy(c.V, c.vstride, jj + 1, c.rec_row(jj, pass), c.work, c.ncplx, 1.0, c.st),
+                           "Gram-Schmidt update");
+                }
+                CN_TRY(launch_cn_dots(c.work, 0, 1, c.work, c.ncplx, c.part, kCnDotBlocks, 64, c.rec_row(jj, 2), c.st),
+                       "Arnoldi norm");
+                if (jj + 1 < m)
+                    CN_TRY(launch_cn_scale_by_norm(c.work, c.vec(jj + 1), 4 * c.npts, c.rec_row(jj, 2), c.st),
+                           "normalise");
             }
-            CN_TRY(norm2_dev(c, c.work, 2), "Arnoldi norm");
-            r = read_coef(c, host.data(), 3 * 128);
+            r = read_coef(c, c.rec_row(j, 0), cols.data(), (size_t)3 * 128 * nb);
             if (r != DIRAC_OK) return r;
-            ++used;
-            for (int i = 0; i <= j; ++i)
-                Hat(i, j) = zd(host[2 * i] + host[128 + 2 * i], host[2 * i + 1] + host[128 + 2 * i + 1]);
-            const double hn = std::sqrt(host[256]);
-            if (!std::isfinite(hn)) return fail(DIRAC_E_NONFINITE, "Arnoldi vector is not finite");
-            // previous rotations on the new column
-            for (int i = 0; i < j; ++i) {
-                const zd a = Hat(i, j), b2 = Hat(i + 1, j);
-                Hat(i, j) = cs[i] * a + sn[i] * b2;
-                Hat(i + 1, j) = -std::conj(sn[i]) * a + cs[i] * b2;
+            for (int q = 0; q < nb && !done; ++q) {
+                const int jc = j + q;
+                const double* col = cols.data() + (size_t)3 * 128 * q;
+                ++used;
+                for (int i = 0; i <= jc; ++i)
+                    Hat(i, jc) = zd(col[2 * i] + col[128 + 2 * i], col[2 * i + 1] + col[128 + 2 * i + 1]);
+                const double hn = std::sqrt(col[256]);
+                if (!std::isfinite(hn)) return fail(DIRAC_E_NONFINITE, "Arnoldi vector is not finite");
+                // previous rotations on the new column
+                for (int i = 0; i < jc; ++i) {
+                    const zd a = Hat(i, jc), b2 = Hat(i + 1, jc);
+                    Hat(i, jc) = cs[i] * a + sn[i] * b2;
+                    Hat(i + 1, jc) = -std::conj(sn[i]) * a + cs[i] * b2;
+                }
+                // new rotation zeroing the subdiagonal hn (real, >= 0)
+                const zd a = Hat(jc, jc);
+                const double aa = std::abs(a), rr = std::hypot(aa, hn);
+                if (aa == 0.0) {
+                    cs[jc] = 0.0;
+                    sn[jc] = 1.0;
+                } else {
+                    cs[jc] = aa / rr;
+                    sn[jc] = (a / aa) * hn / rr;
+                }
+                Hat(jc, jc) = cs[jc] * a + sn[jc] * hn;
+                g[jc + 1] = -std::conj(sn[jc]) * g[jc];
+                g[jc] = cs[jc] * g[jc];
+                k = jc + 1;
+                const double est = std::abs(g[jc + 1]);
+                if (hn == 0.0 || est <= tol || used >= s->scheme.gmres_max_iter) done = true;
             }
-            // new rotation zeroing the subdiagonal hn (real, >= 0)
-            const zd a = Hat(j, j);
-            const double aa = std::abs(a), rr = std::hypot(aa, hn);
-            if (aa == 0.0) {
-                cs[j] = 0.0;
-                sn[j] = 1.0;
-            } else {
-                cs[j] = aa / rr;
-                sn[j] = (a / aa) * hn / rr;
-            }
-            Hat(j, j) = cs[j] * a + sn[j] * hn;
-            g[j + 1] = -std::conj(sn[j]) * g[j];
-            g[j] = cs[j] * g[j];
-            k = j + 1;
-            const double est = std::abs(g[j + 1]);
-            if (hn == 0.0 || est <= tol || used >= s->scheme.gmres_max_iter) break;
-            if (j + 1 < m) CN_TRY(launch_cn_scale(c.work, c.vec(j + 1), 4 * c.npts, 1.0 / hn, c.st), "normalise");
+            j += nb;
         }
+        s->cn_cycle_len = k;
         // back substitution H y = g and x += V y
         for (int i = k - 1; i >= 0; --i) {
             zd acc = g[i];
@@ -190,7 +225,6 @@ dirac_status cn_step_n(dirac_solver* s, int64_t nsteps) {
     c.coef = reinterpret_cast<double*>(b + s->lay.cn_coef);
     c.h = 0.5 * s->g.dt * s->g.c;
     const double* E = s->curved ? reinterpret_cast<const double*>(b + s->lay.E) : nullptr;
-    std::vector<double> host(3 * 128);
     // Step 3 of the previous step, then Step 1 of this one (one application when
     // the step opens the call, or Step 3 alone after the last step); with
     // time-dependent potentials the two use t_{n-1/2} and t_{n+1/2}
@@ -211,11 +245,8 @@ dirac_status cn_step_n(dirac_solver* s, int64_t nsteps) {
     for (int64_t n = 0; n < nsteps; ++n) {
         CN_TRY(exp_steps(s->step, n == 0 ? 1 : 2, false), "Step 1");
         CN_TRY(apply_G(c, c.psi, c.rhs, -1.0), "apply G~");
-        CN_TRY(norm2_dev(c, c.rhs, 2), "right-hand side norm");
-        dirac_status r = read_coef(c, host.data(), 3 * 128);
-        if (r != DIRAC_OK) return r;
-        const double bnorm = std::sqrt(host[256]);
-        r = gmres(c, bnorm, s->cn_iters, s->cn_last_res);
+        CN_TRY(norm2_dev(c, c.rhs, 4), "right-hand side norm");
+        dirac_status r = gmres(c, s->cn_iters, s->cn_last_res);
         if (r != DIRAC_OK) return r;
         s->step += 1;
     }

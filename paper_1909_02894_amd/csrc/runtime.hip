@@ -197,7 +197,7 @@ Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* 
         L.cn_vecbytes = align256(N * 32);
         L.cn_vec = take(L.cn_vecbytes * (size_t)(sc.gmres_restart + 3));
         L.cn_part = take((size_t)kCnDotBlocks * 64 * 2 * 8);
-        L.cn_coef = take(4 * 64 * 2 * 8);
+        L.cn_coef = take((size_t)(5 + 3 * sc.gmres_restart) * 64 * 2 * 8);   // shared rows + one record per iteration
     } else {
         L.cn_vec = L.cn_part = L.cn_coef = SIZE_MAX;
         L.cn_vecbytes = 0;

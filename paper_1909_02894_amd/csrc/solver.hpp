@@ -70,6 +70,7 @@ struct dirac_solver {
     dirac_scheme scheme{};
     int64_t cn_iters = 0;
     double cn_last_res = 0;
+    int cn_cycle_len = 0;             // Arnoldi columns of the last GMRES cycle (batch size hint)
     std::vector<double> cn_host;     // host source of the last GMRES update upload
     bool has_em = false;             // time-dependent potentials
     double em_charge = 0;
