@@ -29,38 +29,54 @@ __global__ void __launch_bounds__((N / cn_radix(N)) * cn_lines(N)) cn_apply_kern
     const typename F::Coord c = F::coord(threadIdx.x);
     const int line = xcd_tile(blockIdx.x, gridDim.x) * L + c.l;
     const bool valid = line < p.nlines;
+    const int lline = valid ? line : p.nlines - 1;     // loads: clamped, branch-free
     const uint32_t n1 = (uint32_t)p.n1;
-    auto gidx = [&](int pos) -> uint32_t { return COLS ? (uint32_t)pos * n1 + line : (uint32_t)line * n1 + pos; };
+    auto gidx = [&](int ln, int pos) -> uint32_t {
+        return COLS ? (uint32_t)pos * n1 + ln : (uint32_t)ln * n1 + pos;
+    };
+    // every global load goes out before the first wait: the vector, twiddles,
+    // derivative symbol, blend factors and (y pass) the x pass's output
+    cpx<T> v[2][R], in[2][R], o[2][R];
+    T d[R], bf[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) load_point(p.in, gidx(lline, c.j + r * P), v[0][r], v[1][r]);
     const cpx<T>* tw = p.tw;
+    cpx<T> twv[TS::ON ? F::TW_ITER : 1];
+    if constexpr (TS::ON) F::tw_load(twv, p.tw, threadIdx.x);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        d[r] = gld(p.D + c.j + r * P);
+        bf[r] = gld(p.inv_s + c.j + r * P);              // ones without a layer
+    }
+    if (p.a) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) bf[r] = ld_at(p.a, gidx(lline, c.j + r * P)) * bf[r];
+    }
+    if constexpr (COLS) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) load_point(p.out, gidx(lline, c.j + r * P), o[0][r], o[1][r]);
+    }
     if constexpr (TS::ON) {
-        cpx<double> twv[F::TW_ITER];
-        F::tw_load(twv, p.tw, threadIdx.x);
         F::tw_store(twv, twl, threadIdx.x);
         tw = twl;
     }
-    cpx<T> v[2][R], in[2][R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        v[0][r] = v[1][r] = cpx<T>{0, 0};
-        if (valid) load_point(p.in, gidx(c.j + r * P), v[0][r], v[1][r]);
         in[0][r] = v[0][r];
         in[1][r] = v[1][r];
     }
     F::template fft<false, TS::ON>(v, lds, c, tw);
 #pragma unroll
     for (int s = 0; s < R; ++s) {
-        const T d = p.D[c.j + s * P];
-        v[0][s] = mul_i(scal(d, v[0][s]));
-        v[1][s] = mul_i(scal(d, v[1][s]));
+        v[0][s] = mul_i(scal(d[s], v[0][s]));
+        v[1][s] = mul_i(scal(d[s], v[1][s]));
     }
     F::template fft<true, TS::ON>(v, lds, c, tw);
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const uint32_t q = gidx(c.j + r * P);
-        T b = p.a ? *at(p.a, q) : T(1);
-        if (p.inv_s) b *= p.inv_s[c.j + r * P];
-        const T f = p.scale * b;                   // s (dt/2) c b
+        const uint32_t q = gidx(line, c.j + r * P);
+        const T f = p.scale * bf[r];               // s (dt/2) c b
         cpx<T> t0, t1;                             // sigma_i [[d_i]] psi
         if constexpr (!COLS) {
             t0 = v[1][r];
@@ -74,7 +90,8 @@ __global__ void __launch_bounds__((N / cn_radix(N)) * cn_lines(N)) cn_apply_kern
             o0 = in[0][r];
             o1 = in[1][r];
         } else {
-            load_point(p.out, q, o0, o1);
+            o0 = o[0][r];
+            o1 = o[1][r];
         }
         store_point(p.out, q, o0 + scal(f, t0), o1 + scal(f, t1));
     }

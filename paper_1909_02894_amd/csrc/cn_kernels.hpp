@@ -12,7 +12,7 @@ struct CnApplyParams {
     const double* in;        // vector the transport operator acts on
     double* out;             // x pass: out = in + term; y pass: out += term
     const double* a;         // a(x) per point, or null (a = 1)
-    const double* inv_s;     // 1/S along the line direction, or null
+    const double* inv_s;     // 1/S along the line direction (ones without a layer)
     const double* D;         // xi / n along the line direction
     const cpx<double>* tw;   // twiddles
     int n1;                  // points per row

@@ -62,7 +62,7 @@ hipError_t apply_G(const CnCtx& c, const double* in, double* out, double sign) {
         p.in = in;
         p.out = out;
         p.a = s->curved ? reinterpret_cast<const double*>(b + s->lay.a) : nullptr;
-        p.inv_s = s->pml ? reinterpret_cast<const double*>(b + s->lay.inv_s[dir]) : nullptr;
+        p.inv_s = reinterpret_cast<const double*>(b + s->lay.inv_s[dir]);   // ones without a layer
         p.D = reinterpret_cast<const double*>(b + s->lay.D[dir]);
         p.tw = reinterpret_cast<const cpx<double>*>(b + s->lay.tw[dir]);
         p.n1 = s->g.n1;
