@@ -114,45 +114,146 @@ __global__ void cn_exp_kernel(double* psi, const double* E, double2 e0u, size_t 
     store_point(psi, (uint32_t)i, u, v);
 }
 
-// Partial sums of sum_i conj(V_k[i]) w[i] for k in [k0, k0 + 8) over a grid-stride
-// range of complex elements; partials[block][k] (complex), fixed order.
-__global__ void __launch_bounds__(256) cn_multidot_kernel(const double* V, size_t vstride, int k0, int nk,
-                                                          const double* w, size_t ncplx, double* partials, int ldp) {
-    double ar[8] = {0, 0, 0, 0, 0, 0, 0, 0}, ai[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
-        const double2 x = reinterpret_cast<const double2*>(w)[i];
+// Fixed-order workgroup sum of NS complex values per thread (a 64-lane butterfly,
+// then the four waves in order); slot k of the result goes to out[2k], out[2k+1].
+template <int NS>
+__device__ __forceinline__ void block_sum_store(double (&ar)[NS], double (&ai)[NS], double* out) {
+    static_assert(NS >= 1 && NS <= 9, "slots per launch");
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (k < nk) {
-                const double2 y = reinterpret_cast<const double2*>(V + (size_t)(k0 + k) * vstride)[i];
-                ar[k] += y.x * x.x + y.y * x.y;
-                ai[k] += y.x * x.y - y.y * x.x;
-            }
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            ar[k] += __shfl_xor(ar[k], off);
+            ai[k] += __shfl_xor(ai[k], off);
         }
     }
-    __shared__ double sr[256][8], si[256][8];
+    __shared__ double sr[NS][4], si[NS][4];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) { sr[threadIdx.x][k] = ar[k]; si[threadIdx.x][k] = ai[k]; }
+        for (int k = 0; k < NS; ++k) {
+            sr[k][wave] = ar[k];
+            si[k][wave] = ai[k];
+        }
+    }
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                sr[threadIdx.x][k] += sr[threadIdx.x + off][k];
-                si[threadIdx.x][k] += si[threadIdx.x + off][k];
-            }
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < (unsigned)nk) {
-        partials[2 * ((size_t)blockIdx.x * ldp + k0 + threadIdx.x)] = sr[0][threadIdx.x];
-        partials[2 * ((size_t)blockIdx.x * ldp + k0 + threadIdx.x) + 1] = si[0][threadIdx.x];
+    if ((int)threadIdx.x < NS) {
+        const int k = threadIdx.x;
+        out[2 * k] = ((sr[k][0] + sr[k][1]) + sr[k][2]) + sr[k][3];
+        out[2 * k + 1] = ((si[k][0] + si[k][1]) + si[k][2]) + si[k][3];
     }
 }
 
-// out[k] = sum over blocks of partials[block][k], k < nk: one workgroup per k,
-// a fixed per-thread order over the blocks and a fixed tree, so the result does
-// not depend on timing.
+// Partial sums of <V_k, w> = sum_i conj(V_k[i]) w[i] for the NK vectors k0 .. k0+NK-1
+// and, with SELF, of ||w||^2 (slot k0+NK, real) over a grid-stride range of complex
+// elements: partials[block][slot] (complex), fixed order.  All loads of an element
+// are issued together.
+template <int NK, bool SELF>
+__global__ void __launch_bounds__(256) cn_dots_kernel(const double* V, size_t vstride, int k0, const double* w,
+                                                      size_t ncplx, double* partials, int ldp) {
+    constexpr int NS = NK + (SELF ? 1 : 0);
+    double ar[NS], ai[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) ar[k] = ai[k] = 0.0;
+    const double2* W = reinterpret_cast<const double2*>(w);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
+        const double2 x = W[i];
+        double2 y[NK > 0 ? NK : 1];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) y[k] = reinterpret_cast<const double2*>(V + (size_t)(k0 + k) * vstride)[i];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            ar[k] += y[k].x * x.x + y[k].y * x.y;
+            ai[k] += y[k].x * x.y - y[k].y * x.x;
+        }
+        if constexpr (SELF) ar[NK] += x.x * x.x + x.y * x.y;
+    }
+    block_sum_store<NS>(ar, ai, partials + 2 * ((size_t)blockIdx.x * ldp + k0));
+}
+
+// The first Gram-Schmidt update fused with the second pass's dots:
+// w <- w - sum_{k<NK} coef_k V_k in place, and partial sums of <V_k, w> (slots 0..NK-1)
+// and ||w||^2 (slot NK) of the updated w, as cn_dots_kernel writes them.
+template <int NK>
+__global__ void __launch_bounds__(256) cn_axpy_dots_kernel(const double* V, size_t vstride, const double* coef,
+                                                           double* w, size_t ncplx, double* partials, int ldp) {
+    constexpr int NS = NK + 1;
+    double ar[NS], ai[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) ar[k] = ai[k] = 0.0;
+    double2* W = reinterpret_cast<double2*>(w);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
+        double2 x = W[i];
+        double2 y[NK];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) y[k] = reinterpret_cast<const double2*>(V + (size_t)k * vstride)[i];
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            const double cr = coef[2 * k], ci = coef[2 * k + 1];
+            x.x -= cr * y[k].x - ci * y[k].y;
+            x.y -= cr * y[k].y + ci * y[k].x;
+        }
+        W[i] = x;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            ar[k] += y[k].x * x.x + y[k].y * x.y;
+            ai[k] += y[k].x * x.y - y[k].y * x.x;
+        }
+        ar[NK] += x.x * x.x + x.y * x.y;
+    }
+    block_sum_store<NS>(ar, ai, partials + 2 * (size_t)blockIdx.x * ldp);
+}
+
+// out <- alpha (w - sign sum_{k<nk} coef_k V_k), nk = 8 nfull + NKR, coef complex on the
+// device (out may be w).  alpha = 1, or with NORM the reciprocal norm of the result:
+// coef[nk] holds ||w||^2 and the V_k are orthonormal, so the result's squared norm is
+// ||w||^2 - sum |coef_k|^2 (clamped at 0; alpha = 0 then); block 0 stores it to norm_out.
+template <int NKR, bool NORM>
+__global__ void __launch_bounds__(256) cn_axpy_kernel(const double* V, size_t vstride, int nfull, const double* coef,
+                                                      const double* w, double* out, size_t ncplx, double sign,
+                                                      double* norm_out) {
+    double alpha = 1.0;
+    if constexpr (NORM) {
+        const int nk = 8 * nfull + NKR;
+        double n2 = coef[2 * nk];
+        for (int k = 0; k < nk; ++k) n2 -= coef[2 * k] * coef[2 * k] + coef[2 * k + 1] * coef[2 * k + 1];
+        n2 = n2 > 0.0 ? n2 : 0.0;
+        alpha = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) norm_out[0] = n2;
+    }
+    const double2* Wi = reinterpret_cast<const double2*>(w);
+    double2* O = reinterpret_cast<double2*>(out);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
+        double2 x = Wi[i];
+        for (int c8 = 0; c8 < nfull; ++c8) {
+            double2 y[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) y[k] = reinterpret_cast<const double2*>(V + (size_t)(8 * c8 + k) * vstride)[i];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const double cr = coef[2 * (8 * c8 + k)], ci = coef[2 * (8 * c8 + k) + 1];
+                x.x -= sign * (cr * y[k].x - ci * y[k].y);
+                x.y -= sign * (cr * y[k].y + ci * y[k].x);
+            }
+        }
+        double2 y[NKR > 0 ? NKR : 1];
+#pragma unroll
+        for (int k = 0; k < NKR; ++k) y[k] = reinterpret_cast<const double2*>(V + (size_t)(8 * nfull + k) * vstride)[i];
+#pragma unroll
+        for (int k = 0; k < NKR; ++k) {
+            const double cr = coef[2 * (8 * nfull + k)], ci = coef[2 * (8 * nfull + k) + 1];
+            x.x -= sign * (cr * y[k].x - ci * y[k].y);
+            x.y -= sign * (cr * y[k].y + ci * y[k].x);
+        }
+        if constexpr (NORM) {
+            x.x *= alpha;
+            x.y *= alpha;
+        }
+        O[i] = x;
+    }
+}
+
+// out[k] = sum over blocks of partials[block][k] (complex), one workgroup per slot, fixed order.
 __global__ void __launch_bounds__(256) cn_reduce_kernel(const double* partials, int nblocks, int ldp, double* out) {
     const int k = blockIdx.x;
     double r = 0, i = 0;
@@ -177,30 +278,8 @@ __global__ void __launch_bounds__(256) cn_reduce_kernel(const double* partials, 
     }
 }
 
-// w <- w - sign sum_k coef[k] V_k (coef complex, read from device memory), k < nk.
-__global__ void __launch_bounds__(256) cn_multiaxpy_kernel(const double* V, size_t vstride, int nk,
-                                                           const double* coef, double* w, size_t ncplx, double sign) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
-        double2 x = reinterpret_cast<double2*>(w)[i];
-        for (int k = 0; k < nk; ++k) {
-            const double2 y = reinterpret_cast<const double2*>(V + (size_t)k * vstride)[i];
-            const double cr = coef[2 * k], ci = coef[2 * k + 1];
-            x.x -= sign * (cr * y.x - ci * y.y);
-            x.y -= sign * (cr * y.y + ci * y.x);
-        }
-        reinterpret_cast<double2*>(w)[i] = x;
-    }
-}
-
 // y <- alpha x (alpha real), or y <- x when alpha == 1.
 __global__ void cn_scale_kernel(const double* x, double* y, size_t n, double alpha) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        y[i] = alpha * x[i];
-}
-
-// y <- x / sqrt(norm2[0]): normalisation by a norm the device computed
-__global__ void cn_scale_by_norm_kernel(const double* x, double* y, size_t n, const double* norm2) {
-    const double alpha = 1.0 / sqrt(norm2[0]);
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         y[i] = alpha * x[i];
 }
@@ -241,29 +320,92 @@ hipError_t launch_cn_exp(double* psi, const double* E, double e0r, double e0i, s
     return hipGetLastError();
 }
 
-hipError_t launch_cn_dots(const double* V, size_t vstride, int nk, const double* w, size_t ncplx, double* partials,
-                          int nblocks, int ldp, double* out, hipStream_t s) {
-    for (int k0 = 0; k0 < nk; k0 += 8) {
-        hipLaunchKernelGGL(cn_multidot_kernel, dim3(nblocks), dim3(256), 0, s, V, vstride, k0,
-                           nk - k0 < 8 ? nk - k0 : 8, w, ncplx, partials, ldp);
+template <bool SELF>
+static void launch_dots_chunk(int nk, const double* V, size_t vstride, int k0, const double* w, size_t ncplx,
+                              double* partials, int nblocks, int ldp, hipStream_t s) {
+#define DIRAC_CN_DOTS(NK)                                                                                    \
+    case NK:                                                                                                 \
+        hipLaunchKernelGGL((cn_dots_kernel<NK, SELF>), dim3(nblocks), dim3(256), 0, s, V, vstride, k0, w,   \
+                           ncplx, partials, ldp);                                                           \
+        break;
+    if constexpr (SELF) {
+        if (nk == 0) {
+            hipLaunchKernelGGL((cn_dots_kernel<0, true>), dim3(nblocks), dim3(256), 0, s, V, vstride, k0, w, ncplx,
+                               partials, ldp);
+            return;
+        }
     }
-    hipLaunchKernelGGL(cn_reduce_kernel, dim3(nk), dim3(256), 0, s, (const double*)partials, nblocks, ldp, out);
+    switch (nk) {
+        DIRAC_CN_DOTS(1) DIRAC_CN_DOTS(2) DIRAC_CN_DOTS(3) DIRAC_CN_DOTS(4)
+        DIRAC_CN_DOTS(5) DIRAC_CN_DOTS(6) DIRAC_CN_DOTS(7) DIRAC_CN_DOTS(8)
+        default: break;
+    }
+#undef DIRAC_CN_DOTS
+}
+
+hipError_t launch_cn_dots(const double* V, size_t vstride, int nk, bool self, const double* w, size_t ncplx,
+                          double* partials, int nblocks, int ldp, double* out, hipStream_t s) {
+    const int slots = nk + (self ? 1 : 0);
+    if (slots < 1 || slots > ldp || nblocks < 1) return hipErrorInvalidValue;
+    int k0 = 0;
+    for (; nk - k0 > 8; k0 += 8) launch_dots_chunk<false>(8, V, vstride, k0, w, ncplx, partials, nblocks, ldp, s);
+    if (self)
+        launch_dots_chunk<true>(nk - k0, V, vstride, k0, w, ncplx, partials, nblocks, ldp, s);
+    else
+        launch_dots_chunk<false>(nk - k0, V, vstride, k0, w, ncplx, partials, nblocks, ldp, s);
+    hipLaunchKernelGGL(cn_reduce_kernel, dim3(slots), dim3(256), 0, s, (const double*)partials, nblocks, ldp, out);
     return hipGetLastError();
 }
 
-hipError_t launch_cn_axpy(const double* V, size_t vstride, int nk, const double* coef, double* w, size_t ncplx,
-                          double sign, hipStream_t s) {
-    hipLaunchKernelGGL(cn_multiaxpy_kernel, dim3(1024), dim3(256), 0, s, V, vstride, nk, coef, w, ncplx, sign);
+hipError_t launch_cn_axpy_dots(const double* V, size_t vstride, int nk, const double* coef, double* w, size_t ncplx,
+                               double* partials, int nblocks, int ldp, double* out, hipStream_t s) {
+    if (nk < 1 || nk > kCnFusedMax || nk + 1 > ldp || nblocks < 1) return hipErrorInvalidValue;
+#define DIRAC_CN_AXD(NK)                                                                                     \
+    case NK:                                                                                                 \
+        hipLaunchKernelGGL((cn_axpy_dots_kernel<NK>), dim3(nblocks), dim3(256), 0, s, V, vstride, coef, w,  \
+                           ncplx, partials, ldp);                                                           \
+        break;
+    switch (nk) {
+        DIRAC_CN_AXD(1) DIRAC_CN_AXD(2) DIRAC_CN_AXD(3) DIRAC_CN_AXD(4)
+        DIRAC_CN_AXD(5) DIRAC_CN_AXD(6) DIRAC_CN_AXD(7) DIRAC_CN_AXD(8)
+        default: break;
+    }
+#undef DIRAC_CN_AXD
+    hipLaunchKernelGGL(cn_reduce_kernel, dim3(nk + 1), dim3(256), 0, s, (const double*)partials, nblocks, ldp, out);
     return hipGetLastError();
+}
+
+template <bool NORM>
+static hipError_t launch_axpy_t(const double* V, size_t vstride, int nk, const double* coef, const double* w,
+                                double* out, size_t ncplx, double sign, double* norm_out, hipStream_t s) {
+    if (nk < 0 || (NORM && !norm_out)) return hipErrorInvalidValue;
+    const int nfull = nk / 8;
+#define DIRAC_CN_AXPY(R)                                                                                     \
+    case R:                                                                                                  \
+        hipLaunchKernelGGL((cn_axpy_kernel<R, NORM>), dim3(1024), dim3(256), 0, s, V, vstride, nfull, coef,  \
+                           w, out, ncplx, sign, norm_out);                                                  \
+        break;
+    switch (nk % 8) {
+        DIRAC_CN_AXPY(0) DIRAC_CN_AXPY(1) DIRAC_CN_AXPY(2) DIRAC_CN_AXPY(3)
+        DIRAC_CN_AXPY(4) DIRAC_CN_AXPY(5) DIRAC_CN_AXPY(6) DIRAC_CN_AXPY(7)
+        default: break;
+    }
+#undef DIRAC_CN_AXPY
+    return hipGetLastError();
+}
+
+hipError_t launch_cn_axpy(const double* V, size_t vstride, int nk, const double* coef, const double* w, double* out,
+                          size_t ncplx, double sign, hipStream_t s) {
+    return launch_axpy_t<false>(V, vstride, nk, coef, w, out, ncplx, sign, nullptr, s);
+}
+
+hipError_t launch_cn_axpy_normalise(const double* V, size_t vstride, int nk, const double* coef, const double* w,
+                                    double* out, size_t ncplx, double* norm2_out, hipStream_t s) {
+    return launch_axpy_t<true>(V, vstride, nk, coef, w, out, ncplx, 1.0, norm2_out, s);
 }
 
 hipError_t launch_cn_scale(const double* x, double* y, size_t n, double alpha, hipStream_t s) {
     hipLaunchKernelGGL(cn_scale_kernel, dim3(1024), dim3(256), 0, s, x, y, n, alpha);
-    return hipGetLastError();
-}
-
-hipError_t launch_cn_scale_by_norm(const double* x, double* y, size_t n, const double* norm2, hipStream_t s) {
-    hipLaunchKernelGGL(cn_scale_by_norm_kernel, dim3(1024), dim3(256), 0, s, x, y, n, norm2);
     return hipGetLastError();
 }
 

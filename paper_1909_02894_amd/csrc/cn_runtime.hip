@@ -76,7 +76,7 @@ hipError_t apply_G(const CnCtx& c, const double* in, double* out, double sign) {
 
 // ||v||^2 into coef row `row`, slot 0 (device), fixed-order reduction.
 hipError_t norm2_dev(const CnCtx& c, const double* v, int row) {
-    return launch_cn_dots(v, 0, 1, v, c.ncplx, c.part, kCnDotBlocks, 64, c.coef_row(row), c.st);
+    return launch_cn_dots(nullptr, 0, 0, true, v, c.ncplx, c.part, kCnDotBlocks, 64, c.coef_row(row), c.st);
 }
 
 dirac_status read_coef(const CnCtx& c, const double* src, double* host, size_t doubles) {
@@ -139,17 +139,23 @@ dirac_status gmres(CnCtx& c, int64_t& iters, double& rel_res) {
             for (int q = 0; q < nb; ++q) {
                 const int jj = j + q;
                 CN_TRY(apply_G(c, c.vec(jj), c.work, +1.0), "apply G");
-                for (int pass = 0; pass < 2; ++pass) {    // CGS2
-                    CN_TRY(launch_cn_dots(c.V, c.vstride, jj + 1, c.work, c.ncplx, c.part, kCnDotBlocks, 64,
-                                          c.rec_row(jj, pass), c.st), "Gram-Schmidt dots");
-                    CN_TRY(launch_cn_axpy(c.V, c.vstride, jj + 1, c.rec_row(jj, pass), c.work, c.ncplx, 1.0, c.st),
+                // classical Gram-Schmidt applied twice; the second pass's dots ride on the
+                // first update, and the second update writes the next basis vector, normalised
+                // by ||w1||^2 - ||h2||^2 (w1 after the first pass, V orthonormal)
+                const int nk = jj + 1;
+                CN_TRY(launch_cn_dots(c.V, c.vstride, nk, false, c.work, c.ncplx, c.part, kCnDotBlocks, 64,
+                                      c.rec_row(jj, 0), c.st), "Gram-Schmidt dots");
+                if (nk <= kCnFusedMax) {
+                    CN_TRY(launch_cn_axpy_dots(c.V, c.vstride, nk, c.rec_row(jj, 0), c.work, c.ncplx, c.part,
+                                               kCnDotBlocks, 64, c.rec_row(jj, 1), c.st), "Gram-Schmidt update");
+                } else {
+                    CN_TRY(launch_cn_axpy(c.V, c.vstride, nk, c.rec_row(jj, 0), c.work, c.work, c.ncplx, 1.0, c.st),
                            "Gram-Schmidt update");
+                    CN_TRY(launch_cn_dots(c.V, c.vstride, nk, true, c.work, c.ncplx, c.part, kCnDotBlocks, 64,
+                                          c.rec_row(jj, 1), c.st), "Gram-Schmidt dots");
                 }
-                CN_TRY(launch_cn_dots(c.work, 0, 1, c.work, c.ncplx, c.part, kCnDotBlocks, 64, c.rec_row(jj, 2), c.st),
-                       "Arnoldi norm");
-                if (jj + 1 < m)
-                    CN_TRY(launch_cn_scale_by_norm(c.work, c.vec(jj + 1), 4 * c.npts, c.rec_row(jj, 2), c.st),
-                           "normalise");
+                CN_TRY(launch_cn_axpy_normalise(c.V, c.vstride, nk, c.rec_row(jj, 1), c.work, c.vec(jj + 1),
+                                                c.ncplx, c.rec_row(jj, 2), c.st), "normalise");
             }
             r = read_coef(c, c.rec_row(j, 0), cols.data(), (size_t)3 * 128 * nb);
             if (r != DIRAC_OK) return r;
@@ -199,7 +205,8 @@ dirac_status gmres(CnCtx& c, int64_t& iters, double& rel_res) {
         }
         CN_TRY(hipMemcpyAsync(c.coef_row(3), upload.data(), 2 * k * sizeof(double), hipMemcpyHostToDevice, c.st),
                "upload update");
-        CN_TRY(launch_cn_axpy(c.V, c.vstride, k, c.coef_row(3), c.psi, c.ncplx, -1.0, c.st), "solution update");
+        CN_TRY(launch_cn_axpy(c.V, c.vstride, k, c.coef_row(3), c.psi, c.psi, c.ncplx, -1.0, c.st),
+               "solution update");
     }
     iters += used;
     return DIRAC_OK;

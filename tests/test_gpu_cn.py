@@ -114,6 +114,22 @@ def test_cn_restarted_gmres_large_step(D):
     assert O.rel_l2(s.get_spinor(), O.cn_run(psi0, T, 4)) < 1e-10
 
 
+def test_cn_long_cycles_past_the_fused_kernels(D):
+    # cycles of up to 40 Arnoldi vectors (about 90 iterations per step): past eight
+    # basis vectors the first update and the second pass's dots run as separate
+    # kernels, the dots in chunks of eight, the updates over full chunks of eight
+    spec = W.curved_bump(n=64, steps=3, m=1.0)
+    spec.dt = 1.2
+    psi0 = W.initial_spinor(spec)
+    s = cn_solver(D, spec, rtol=1e-13, restart=40)
+    s.set_initial_spinor(psi0)
+    s.step_n(3)
+    iters, res = s.cn_stats()
+    assert iters >= 3 * 12 and res <= 1e-13
+    T = O.build_tables(oracle_problem(spec))
+    assert O.rel_l2(s.get_spinor(), O.cn_run(psi0, T, 3)) < 1e-10
+
+
 def test_cn_reports_no_convergence(D):
     spec = W.curved_bump(n=32, steps=1, m=1.0)
     spec.dt = 0.4
