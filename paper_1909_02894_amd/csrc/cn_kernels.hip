@@ -12,15 +12,21 @@
 
 namespace dirac {
 
-__host__ __device__ constexpr int cn_radix(int n) { return n <= 64 ? 4 : 8; }
-__host__ __device__ constexpr int cn_lines(int n) { return (n / cn_radix(n)) >= 256 ? 1 : 256 / (n / cn_radix(n)); }
+// Row passes: radix 4 up to 512 points (more threads per line); column passes: radix 8
+// and at least two lines per workgroup (32-byte row segments of the FP64 state).
+// At least 64 threads per workgroup, and as many workgroups as lines allow.
+__host__ __device__ constexpr int cn_radix(int n, bool cols) { return n <= 64 ? 4 : (cols || n > 512 ? 8 : 4); }
+__host__ __device__ constexpr int cn_lines(int n, bool cols) {
+    return (n / cn_radix(n, cols)) >= 64 ? (cols ? 2 : 1)
+                                         : (cols && 64 / (n / cn_radix(n, cols)) < 2 ? 2 : 64 / (n / cn_radix(n, cols)));
+}
 
 // out = in + s h c b_x sigma_x [[d_x]] in          (x pass, rows)
 // out = out + s h c b_y sigma_y [[d_y]] in         (y pass, columns)
 template <int N, bool COLS>
-__global__ void __launch_bounds__((N / cn_radix(N)) * cn_lines(N)) cn_apply_kernel(CnApplyParams p) {
+__global__ void __launch_bounds__((N / cn_radix(N, COLS)) * cn_lines(N, COLS)) cn_apply_kernel(CnApplyParams p) {
     using T = double;
-    constexpr int R = cn_radix(N), L = cn_lines(N);
+    constexpr int R = cn_radix(N, COLS), L = cn_lines(N, COLS);
     using F = LineFFT<T, N, R, L, COLS, 2>;
     using TS = TwStage<T, N>;
     constexpr int P = F::P;
@@ -294,8 +300,8 @@ __global__ void cn_sub_kernel(const double* x, double* y, size_t n) {
 
 template <bool COLS>
 static hipError_t launch_apply_dir(int n, int nlines, const CnApplyParams& p, hipStream_t s) {
-    const int L = cn_lines(n);
-    const dim3 grid((nlines + L - 1) / L), block((n / cn_radix(n)) * L);
+    const int L = cn_lines(n, COLS);
+    const dim3 grid((nlines + L - 1) / L), block((n / cn_radix(n, COLS)) * L);
     switch (n) {
         case 16: hipLaunchKernelGGL((cn_apply_kernel<16, COLS>), grid, block, 0, s, p); break;
         case 32: hipLaunchKernelGGL((cn_apply_kernel<32, COLS>), grid, block, 0, s, p); break;
