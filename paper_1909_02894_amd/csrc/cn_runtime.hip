@@ -94,8 +94,9 @@ dirac_status read_coef(const CnCtx& c, const double* src, double* host, size_t d
 // then reads the batch's columns at once and applies the rotations column by
 // column.  A cycle that converges inside a batch uses only its first columns
 // (the later ones were computed and are dropped), so the iterate is the one
-// the column-by-column form gives.  The first batch of a cycle is one short of
-// the previous cycle's length; later batches are single iterations.
+// the column-by-column form gives.  The first batch of a cycle is the previous
+// cycle's length (steady solves converge at the same count); later batches are
+// single iterations.
 dirac_status gmres(CnCtx& c, int64_t& iters, double& rel_res) {
     dirac_solver* s = c.s;
     const int m = s->scheme.gmres_restart;
@@ -131,7 +132,7 @@ dirac_status gmres(CnCtx& c, int64_t& iters, double& rel_res) {
         g[0] = beta;
         int k = 0, j = 0;
         bool done = false;
-        int batch = std::max(1, s->cn_cycle_len - 1);
+        int batch = std::max(1, s->cn_cycle_len);
         while (!done && j < m) {
             const int nb = (int)std::min<int64_t>({(int64_t)batch, (int64_t)(m - j),
                                                    std::max<int64_t>(1, s->scheme.gmres_max_iter - used)});
