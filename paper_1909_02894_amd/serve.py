@@ -1,7 +1,7 @@
 """Continuous-batching request loop over the batch engine.
 
-Solve requests (grid, metric, layer, initial packet, step count) arrive over
-time.  The loop keeps one device arena (a torch uint8 tensor of `budget_bytes`)
+Solve requests (grid, metric, layer, step count, and the initial spinor as
+their payload) arrive over time.  The loop keeps one device arena (a torch uint8 tensor of `budget_bytes`)
 and sub-allocates each admitted solve's buffer from it by its footprint
 (``dirac_footprint_bytes``); a request is admitted as soon as it has arrived,
 a batch slot is free and the arena has room, in arrival order.  Admitted solves
@@ -77,6 +77,7 @@ class Request:
     arrival: float
     spec: W.SolveSpec
     steps: int
+    psi0: np.ndarray | None = None       # initial spinor payload; built from the spec at admission if None
     admitted: float = -1.0
     finished: float = -1.0
     result: np.ndarray | None = None
@@ -167,21 +168,24 @@ class Server:
         max_running = 0
         quanta = 0
         qi = 0
-        while qi < len(pending) or running:
+        def admit():
             # admit everything that has arrived and fits (arrival order, no overtaking)
+            nonlocal qi
             while qi < len(pending) and pending[qi].arrival * time_scale <= now() and len(running) < self.capacity:
                 r = pending[qi]
-                fp = self._footprint(r.spec)
-                got = self.arena.alloc(fp)
+                got = self.arena.alloc(self._footprint(r.spec))
                 if got is None:
                     break
                 off, size = got
                 s = _ArenaSolver(r.spec, self.precision, self._ptr(off), size, self.setup_stream)
-                s.set_initial_spinor(W.initial_spinor(r.spec))
+                s.set_initial_spinor(r.psi0 if r.psi0 is not None else W.initial_spinor(r.spec))
                 slot = self.batch.add(s)
                 r.admitted = now()
                 running[slot] = _Running(r, s, slot, off, size, r.steps)
                 qi += 1
+
+        while qi < len(pending) or running:
+            admit()
             peak = max(peak, self.arena.used)
             max_running = max(max_running, len(running))
             if not running:
@@ -196,19 +200,7 @@ class Server:
             quanta += 1
             # while the quantum runs, admit newly arrived requests (their setup runs on
             # the setup stream and overlaps the batch stream)
-            while qi < len(pending) and pending[qi].arrival * time_scale <= now() and \
-                    len(running) < self.capacity:
-                r = pending[qi]
-                got = self.arena.alloc(self._footprint(r.spec))
-                if got is None:
-                    break
-                off, size = got
-                s = _ArenaSolver(r.spec, self.precision, self._ptr(off), size, self.setup_stream)
-                s.set_initial_spinor(W.initial_spinor(r.spec))
-                slot = self.batch.add(s)
-                r.admitted = now()
-                running[slot] = _Running(r, s, slot, off, size, r.steps)
-                qi += 1
+            admit()
             self.batch.sync()
             t_done = now()
             for sl, st in steps.items():
@@ -238,8 +230,10 @@ class Server:
 
 
 def make_requests(count: int, rate_per_s: float, seed: int = 5000, sizes=(64, 128, 256, 512, 1024),
-                  steps_range=(200, 5000)) -> list[Request]:
+                  steps_range=(200, 5000), payload: bool = True) -> list[Request]:
+    """Poisson arrivals of packet solves.  payload: each request carries its initial
+    spinor, as a client would send it (else the server builds it at admission)."""
     out = []
     for i, (t, spec) in enumerate(W.serving_arrivals(count, rate_per_s, seed, sizes, steps_range)):
-        out.append(Request(i, t, spec, spec.steps))
+        out.append(Request(i, t, spec, spec.steps, W.initial_spinor(spec) if payload else None))
     return out
