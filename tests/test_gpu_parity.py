@@ -295,6 +295,21 @@ def test_config2_full_size_short_and_long(D):
     assert ob["norm_l2"] < ob0["norm_l2"] * 1.05
 
 
+def test_config2_in_the_tuned_launch_configuration(D):
+    # the configuration the benchmark times: schedules and store modes chosen by
+    # the tuner, graph replay; element-wise parity for 20 steps, split 7 + 13
+    spec = W.curved_bump(n=512, steps=20)
+    s = D.Solver.from_spec(spec)
+    s.set_initial_spinor(W.initial_spinor(spec))
+    s.autotune(30)
+    assert s.observables()["step"] == 0
+    assert s.store_mode() in (0, 1, 2, 3)
+    s.step_n(7)
+    s.step_n(13)
+    _, o = oracle_run(spec, 20)
+    assert O.rel_l2(s.get_spinor(), o[20]) < TOL64
+
+
 def test_precision_report_flat_2048(D, capsys):
     # 2048^2 flat packet solve for 5000 steps in FP32 and FP64 against the exact
     # discrete propagator U(xi)^n of the scheme (computed in FP64 without a time loop).
