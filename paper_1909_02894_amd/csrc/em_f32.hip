@@ -7,7 +7,7 @@
 namespace dirac {
 
 #define EMK(N, DIR) \
-    EmEntry{1, N, DIR, em_lines(N), em_threads(N), reinterpret_cast<const void*>(&em_stage_kernel<float, N, DIR == 1>)}
+    EmEntry{1, N, DIR, em_lines(N, DIR == 1), em_threads(N, DIR == 1), reinterpret_cast<const void*>(&em_stage_kernel<float, N, DIR == 1>)}
 
 const EmEntry* em_entries_f32(int* count) {
     static const EmEntry e[] = {EMK(16, 0),  EMK(32, 0),  EMK(64, 0),  EMK(128, 0), EMK(256, 0),  EMK(512, 0),

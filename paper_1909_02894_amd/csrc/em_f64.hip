@@ -7,7 +7,7 @@
 namespace dirac {
 
 #define EMK(N, DIR) \
-    EmEntry{0, N, DIR, em_lines(N), em_threads(N), reinterpret_cast<const void*>(&em_stage_kernel<double, N, DIR == 1>)}
+    EmEntry{0, N, DIR, em_lines(N, DIR == 1), em_threads(N, DIR == 1), reinterpret_cast<const void*>(&em_stage_kernel<double, N, DIR == 1>)}
 
 const EmEntry* em_entries_f64(int* count) {
     static const EmEntry e[] = {EMK(16, 0),  EMK(32, 0),  EMK(64, 0),  EMK(128, 0), EMK(256, 0),  EMK(512, 0),

@@ -16,7 +16,7 @@ namespace dirac {
 
 template <typename T>
 struct EmParams {
-    StageParams<T> s;            // psi, inv_s, K, tw, n1, nlines, e_pre, e_post (a, E, e0u unused)
+    StageParams<T> s;            // psi, inv_s, K, tw, n1, nlines, e_pre (x only), e_post (a, E, e0u unused)
     const T* rec;                // 8 T per point
     double fA[3], fV[3];         // envelope values: Step-1 applications in order, then Step 5
 };
@@ -26,9 +26,18 @@ struct EmEntry {
     const void* fn;
 };
 
-__host__ __device__ constexpr int em_radix(int n) { return n <= 64 ? 4 : 8; }
-__host__ __device__ constexpr int em_lines(int n) { return (n / em_radix(n)) >= 256 ? 1 : 256 / (n / em_radix(n)); }
-__host__ __device__ constexpr int em_threads(int n) { return (n / em_radix(n)) * em_lines(n); }
+// Radix 4 in both directions (more threads per line: the row kernels are
+// ALU-bound on the per-point exponentials, and radix 8 with both components per
+// thread would hold the column kernels to one wave per SIMD); one row or two
+// columns per workgroup (row segments of two points) up to 256-thread lines, so
+// that a 512-point grid gives every SIMD a wave.  At least 64 threads per workgroup.
+__host__ __device__ constexpr int em_radix(int) { return 4; }
+__host__ __device__ constexpr int em_lines(int n, bool cols) {
+    return (n / em_radix(n)) >= 256 ? 1
+           : (n / em_radix(n)) >= 64 ? (cols ? 2 : 1)
+           : (cols && 64 / (n / em_radix(n)) < 2 ? 2 : 64 / (n / em_radix(n)));
+}
+__host__ __device__ constexpr int em_threads(int n, bool cols) { return (n / em_radix(n)) * em_lines(n, cols); }
 
 const EmEntry* em_entry(int prec, int n, int dir);
 hipError_t launch_em_exp(double* psi, const double* rec, size_t npts, int times, const double* fA, const double* fV,
@@ -118,6 +127,13 @@ __device__ __forceinline__ void load_record(const T* rec, uint32_t idx, double (
     }
 }
 
+// The record's a alone (the column kernels, which apply no exponential before
+// their transform).
+template <typename T>
+__device__ __forceinline__ double load_record_a(const T* rec, uint32_t idx) {
+    return (double)gld(rec + (size_t)idx * 8 + 6);
+}
+
 template <typename T>
 __device__ __forceinline__ void apply_mat(const Mat2& m, cpx<T>& u, cpx<T>& v) {
     const cpx<T> m00{(T)m.m00.re, (T)m.m00.im}, m01{(T)m.m01.re, (T)m.m01.im};
@@ -129,8 +145,8 @@ __device__ __forceinline__ void apply_mat(const Mat2& m, cpx<T>& u, cpx<T>& v) {
 }
 
 template <typename T, int N, bool COLS>
-__global__ void __launch_bounds__(em_threads(N)) em_stage_kernel(EmParams<T> ep) {
-    constexpr int R = em_radix(N), L = em_lines(N);
+__global__ void __launch_bounds__(em_threads(N, COLS)) em_stage_kernel(EmParams<T> ep) {
+    constexpr int R = em_radix(N), L = em_lines(N, COLS);
     using F = LineFFT<T, N, R, L, COLS, 2>;
     using TS = TwStage<T, N>;
     constexpr int P = F::P;
@@ -146,15 +162,17 @@ __global__ void __launch_bounds__(em_threads(N)) em_stage_kernel(EmParams<T> ep)
         return COLS ? (uint32_t)pos * n1 + ln : (uint32_t)ln * n1 + pos;
     };
 
-    // every global load of the tile goes out before the first wait
+    // every global load of the tile goes out before the first wait; the column
+    // kernels (e_pre = 0) read only a from the record
     cpx<T> v[2][R], old[2][R], ksym[R];
-    double q[R][6], a[R];
+    double q[COLS ? 1 : R][6], a[R];
     T b[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t g = gidx(lline, c.j + r * P);
         load_point(p.psi, g, v[0][r], v[1][r]);
-        load_record(ep.rec, g, q[r], a[r]);
+        if constexpr (COLS) a[r] = load_record_a(ep.rec, g);
+        else load_record(ep.rec, g, q[r], a[r]);
     }
     const cpx<T>* tw = p.tw;
     cpx<T> twv[TS::ON ? F::TW_ITER : 1];
@@ -170,7 +188,8 @@ __global__ void __launch_bounds__(em_threads(N)) em_stage_kernel(EmParams<T> ep)
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        for (int k = 0; k < p.e_pre; ++k) apply_mat(em_exponential(q[r], ep.fA[k], ep.fV[k]), v[0][r], v[1][r]);
+        if constexpr (!COLS)
+            for (int k = 0; k < p.e_pre; ++k) apply_mat(em_exponential(q[r], ep.fA[k], ep.fV[k]), v[0][r], v[1][r]);
         old[0][r] = v[0][r];
         old[1][r] = v[1][r];
     }
