@@ -6,7 +6,7 @@
 namespace dirac {
 
 #define BIS(N, DIR)                                                                                    \
-    BisEntry{1, N, DIR, bis_lines(N), bis_threads(N),                                                \
+    BisEntry{1, N, DIR, bis_lines(N, DIR == 1), bis_threads(N, DIR == 1),                              \
              {reinterpret_cast<const void*>(&bis_stage_kernel<float, N, DIR == 1, 1>),                   \
               reinterpret_cast<const void*>(&bis_stage_kernel<float, N, DIR == 1, 2>)}}
 

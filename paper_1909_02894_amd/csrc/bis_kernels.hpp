@@ -29,16 +29,23 @@ struct BisEntry {
     const void* fn[2];     // [0] flat with layer, [1] curved
 };
 
+// Radix 4; one row or two columns per workgroup (row segments of two points)
+// from 64-thread lines, so that a 512-point grid gives every SIMD a wave; at
+// least 64 threads per workgroup.
 constexpr int kBisRadix = 4;
-__host__ __device__ constexpr int bis_lines(int n) { return (n / kBisRadix) >= 256 ? 1 : 256 / (n / kBisRadix); }
-__host__ __device__ constexpr int bis_threads(int n) { return (n / kBisRadix) * bis_lines(n); }
+__host__ __device__ constexpr int bis_lines(int n, bool cols) {
+    return (n / kBisRadix) >= 256 ? 1
+           : (n / kBisRadix) >= 64 ? (cols ? 2 : 1)
+           : (cols && 64 / (n / kBisRadix) < 2 ? 2 : 64 / (n / kBisRadix));
+}
+__host__ __device__ constexpr int bis_threads(int n, bool cols) { return (n / kBisRadix) * bis_lines(n, cols); }
 
 const BisEntry* bis_entry(int prec, int n, int dir);
 
 // MODE 1: flat with layer (b = 1/S, b' = 0, uniform diagonal E); MODE 2: curved.
 template <typename T, int N, bool COLS, int MODE>
-__global__ void __launch_bounds__(bis_threads(N)) bis_stage_kernel(BisParams<T> bp) {
-    constexpr int R = kBisRadix, L = bis_lines(N);
+__global__ void __launch_bounds__(bis_threads(N, COLS)) bis_stage_kernel(BisParams<T> bp) {
+    constexpr int R = kBisRadix, L = bis_lines(N, COLS);
     using F = LineFFT<T, N, R, L, COLS, 2>;
     using TS = TwStage<T, N>;
     constexpr int P = F::P;
