@@ -79,6 +79,17 @@ def test_cn_curved_bump_with_layer(D, m):
     assert O.rel_l2(s.get_spinor(), O.cn_run(psi0, T, 8)) < TOL
 
 
+def test_cn_full_size_grid(D):
+    # the benchmark's 512^2 grid (operator workgroups of one row or two columns)
+    spec = W.curved_bump(n=512, seed=1909, steps=2, m=1.0)
+    psi0 = W.initial_spinor(spec)
+    s = cn_solver(D, spec)
+    s.set_initial_spinor(psi0)
+    s.step_n(2)
+    T = O.build_tables(oracle_problem(spec))
+    assert O.rel_l2(s.get_spinor(), O.cn_run(psi0, T, 2)) < TOL
+
+
 def test_cn_accepts_a_above_one_that_scheme_two_rejects(D):
     n1, n2, a = 64, 16, 8.0
     f = x_only_fields(n1, n2, a)

@@ -63,6 +63,16 @@ def test_em_curved_bump_with_layer_fp64(D, m):
     assert abs(ob["energy_im"] - ro.energy_im) <= 1e-10 * max(1.0, abs(ro.energy_re))
 
 
+@pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL32)])
+def test_em_full_size_grid(D, precision, tol):
+    # the benchmark's 512^2 grid: one row or two columns per workgroup
+    spec = W.curved_bump(n=512, seed=1909, steps=3, m=1.0)
+    pot = potentials(spec, seed=11)
+    _, g = gpu(D, spec, 3, pot, precision=precision, split=(1,))
+    ref = O.run(W.initial_spinor(spec), O.build_tables(oracle_problem(spec, potentials=pot)), 3)
+    assert O.rel_l2(g, ref) < tol
+
+
 def test_em_rectangular_exp3_fp32_and_printed(D):
     spec = W.paper_exp3(n=128, steps=16)
     spec.n2, spec.dt = 32, 2e-3

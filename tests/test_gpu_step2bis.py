@@ -53,6 +53,13 @@ def test_corrected_curved_bump_fp32(D):
     assert O.rel_l2(g, ref) < TOL32
 
 
+def test_corrected_full_size_grid(D):
+    # the benchmark's 512^2 grid (one row or two columns per workgroup)
+    spec = W.curved_bump(n=512, seed=1909, steps=3, m=1.0)
+    _, g, ref = run_pair(D, spec, 3, D.SCHEME_EXP_SPLIT_2BIS, O.STEP2BIS_CORRECTED, split=(1,))
+    assert O.rel_l2(g, ref) < TOL64
+
+
 def test_corrected_exp3_rectangular_and_flat_layer(D):
     spec = W.paper_exp3(n=64, steps=8)
     spec.n2 = 32
