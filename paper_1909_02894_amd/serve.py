@@ -131,7 +131,7 @@ class ServeStats:
 
 class Server:
     def __init__(self, precision=D.FP32, budget_bytes=288 << 30, capacity=512, quantum=64, keep_results=False,
-                 device=None):
+                 device=None, policy="share", fill_points=1 << 22):
         import torch
         self.precision = precision
         self.device = device or torch.device("cuda", torch.cuda.current_device())
@@ -145,6 +145,27 @@ class Server:
         self.capacity = capacity
         self.quantum = quantum
         self.keep_results = keep_results
+        if policy not in ("share", "srpt"):
+            raise ValueError("policy must be 'share' or 'srpt'")
+        self.policy = policy
+        self.fill_points = fill_points
+
+    def _plan(self, running):
+        """Steps per running solve for the next quantum.  share: every solve advances.
+        srpt: solves in order of least remaining work (grid points x steps left) until
+        their grid points reach fill_points (enough to keep the device busy); the
+        others wait for a later quantum."""
+        if self.policy == "share":
+            return {sl: min(self.quantum, ru.remaining) for sl, ru in running.items()}
+        order = sorted(running.items(),
+                       key=lambda kv: (kv[1].remaining * kv[1].req.spec.n1 * kv[1].req.spec.n2, kv[1].req.rid))
+        steps, points = {}, 0
+        for sl, ru in order:
+            if steps and points >= self.fill_points:
+                break
+            steps[sl] = min(self.quantum, ru.remaining)
+            points += ru.req.spec.n1 * ru.req.spec.n2
+        return steps
 
     def _ptr(self, off):
         return None if self.arena.base is None else self.arena.base + off
@@ -195,7 +216,7 @@ class Server:
                     if wait > 0:
                         time.sleep(min(wait, 0.01))
                 continue
-            steps = {sl: min(self.quantum, ru.remaining) for sl, ru in running.items()}
+            steps = self._plan(running)
             self.batch.run(steps)
             quanta += 1
             # while the quantum runs, admit newly arrived requests (their setup runs on

@@ -23,9 +23,12 @@ def small_requests(S, count, rate, seed=5000):
     return S.make_requests(count, rate, seed=seed, sizes=(64, 128, 256), steps_range=(20, 90))
 
 
-def test_served_equals_alone_and_oracle(S):
+@pytest.mark.parametrize("policy", ["share", "srpt"])
+def test_served_equals_alone_and_oracle(S, policy):
+    # srpt with a fill target of one 128^2 grid: most quanta leave solves waiting
     reqs = small_requests(S, 14, 400.0)
-    srv = S.Server(precision=1, budget_bytes=1 << 30, capacity=8, quantum=16, keep_results=True)
+    srv = S.Server(precision=1, budget_bytes=1 << 30, capacity=8, quantum=16, keep_results=True, policy=policy,
+                   fill_points=128 * 128)
     st = srv.run(reqs)
     srv.close()
     assert st.requests == len(reqs) and st.max_running > 1
