@@ -295,6 +295,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--skip-variants", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--variants", default=None,
+                    help="comma-separated variant names to run (default: all; serve_poisson needs batch_256_mixed)")
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (counter calibration)")
@@ -344,13 +346,17 @@ def main():
         "roofline": roofline_for(spec, "curved", D.FP64, r64),
     }
     variants = {}
-    if not args.skip_variants:
+    # --variants a,b: only those (e.g. for counter passes); the serving runs need the batch's rate
+    chosen = None if args.variants is None else set(args.variants.split(","))
+    want = lambda k: not args.skip_variants and (chosen is None or k in chosen)
+    if want("fp32_same_workload"):
         progress("variant: same workload FP32")
         r32 = time_solve(D, spec, D.FP32, K, args.warmup, timed)
         variants["fp32_same_workload"] = {
             "value": N * K / (r32["ms"] * 1e-3), "ms_per_step": r32["ms"] / K, "dtype": "f32",
             "roofline": roofline_for(spec, "curved", D.FP32, r32),
             "schedule": {"x": r32["sched"][0], "y": r32["sched"][1], "write_through_mask": r32["write_through"]}}
+    if want("fp32_flat_4096"):
         big = W.flat_small(n=4096, steps=200)
         progress("variant: flat 4096x4096 FP32")
         rb = time_solve(D, big, D.FP32, 200, 10, 100)
@@ -359,6 +365,7 @@ def main():
             "note": "flat 4096x4096 packet solve, 256 MiB state (beyond the Infinity Cache)",
             "roofline": roofline_for(big, "flat", D.FP32, rb),
             "schedule": {"x": rb["sched"][0], "y": rb["sched"][1], "write_through_mask": rb["write_through"]}}
+    if want("step2bis_corrected_fp64"):
         progress("variant: second-order directional step FP64")
         rc = time_solve(D, spec, D.FP64, 500, args.warmup, 100, scheme=D.SCHEME_EXP_SPLIT_2BIS)
         variants["step2bis_corrected_fp64"] = {
@@ -367,26 +374,32 @@ def main():
             "x_avg_us": round(rc["kernel_us"][0], 3), "y_avg_us": round(rc["kernel_us"][1], 3),
             "roofline": variant_roofline(N, (120, 88), rc["kernel_us"],
                                          "x: state r/w 64 + E 32 + a 8 + gradient pair 16 B/pt; y: 64 + 8 + 16")}
+    if want("scheme1_cn_gmres"):
         progress("variant: Scheme I")
         variants["scheme1_cn_gmres"] = bench_cn(D, spec)
+    if want("em_potentials_fp64"):
         progress("variant: potentials")
         variants["em_potentials_fp64"] = bench_em(D, W, spec)
+    if want("fp32_3d_flat_256"):
         progress("variant: 3-D 256^3 FP32")
         variants["fp32_3d_flat_256"] = bench_3d(D, W, 256, D.FP32, False)
+    if want("fp64_3d_curved_128"):
         progress("variant: 3-D 128^3 FP64")
         variants["fp64_3d_curved_128"] = bench_3d(D, W, 128, D.FP64, True)
+    if want("batch_256_mixed"):
         progress("variant: batch of 256 solves")
         bt = bench_batch(D, W)
         variants["batch_256_mixed"] = bt
-        # serving at ~0.7x the measured batch capacity
-        mean_work = np.mean([n * n for n in (64, 128, 256, 512, 1024)]) * (200 + 5000) / 2.0
-        rate = 0.7 * bt["value"] / mean_work
-        progress("variant: serving, 288 GB budget")
-        variants["serve_poisson"] = bench_serve(100, rate, 288 << 30)
-        progress("variant: serving, 2 GB budget")
-        variants["serve_poisson_2GB"] = bench_serve(40, rate, 2 << 30, seed=5001)
-        out["latency"] = {"p50_s": variants["serve_poisson"]["p50_s"], "p99_s": variants["serve_poisson"]["p99_s"],
-                          "source": "serve_poisson"}
+        if want("serve_poisson"):
+            # serving at ~0.7x the measured batch capacity
+            mean_work = np.mean([n * n for n in (64, 128, 256, 512, 1024)]) * (200 + 5000) / 2.0
+            rate = 0.7 * bt["value"] / mean_work
+            progress("variant: serving, 288 GB budget")
+            variants["serve_poisson"] = bench_serve(100, rate, 288 << 30)
+            progress("variant: serving, 2 GB budget")
+            variants["serve_poisson_2GB"] = bench_serve(40, rate, 2 << 30, seed=5001)
+            out["latency"] = {"p50_s": variants["serve_poisson"]["p50_s"],
+                              "p99_s": variants["serve_poisson"]["p99_s"], "source": "serve_poisson"}
     out["variants"] = variants
     if not args.skip_cpu:
         progress("oracle on the host")

@@ -2,7 +2,7 @@
 
     python -m paper_1909_02894_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
     python -m paper_1909_02894_amd.profiling traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
-        <copy_write.csv> <grid> <out.json> "<command>"
+        <copy_write.csv> <grid | square> <out.json> "<command>"
     python -m paper_1909_02894_amd.profiling trace <kernel_trace.csv> <out.md> "<command>" [filter]
 
 `stats` turns a ``--kernel-trace --stats`` kernel table into a short markdown
@@ -55,6 +55,8 @@ def bench_name(kernel: str, grid: str):
     if not m:
         return None
     t, n, r, lines, cols, mode, cpt = m.groups()
+    if grid == "square":                  # every solve in the run is n x n
+        grid = f"{n}x{n}"
     return f"{'y' if cols == 'true' else 'x'}_stage_{'f64' if t == 'double' else 'f32'}_{grid}_{MODE_NAMES[int(mode)]}"
 
 
