@@ -251,8 +251,8 @@ def bench_em(D, W, spec, steps=500):
             "ms_per_step": ms / steps, "note": "Gaussian scalar potential and a uniform laser-like vector "
             "potential pulse; exponential rebuilt per point and step", "x_avg_us": round(1e3 * kms[0] / cnt[0], 3),
             "y_avg_us": round(1e3 * kms[1] / cnt[1], 3),
-            "roofline": variant_roofline(spec.n1 * spec.n2, (128, 128), [1e3 * kms[d] / cnt[d] for d in (0, 1)],
-                                         "state r/w 64 + the 64-byte point record in both directions; the x "
+            "roofline": variant_roofline(spec.n1 * spec.n2, (128, 72), [1e3 * kms[d] / cnt[d] for d in (0, 1)],
+                                         "x: state r/w 64 + the 64-byte point record, y: 64 + a 8 B/pt; the x "
                                          "kernel is ALU-bound (FP64 exponential per point, twice)")}
 
 
