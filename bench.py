@@ -283,6 +283,10 @@ def cpu_baseline(spec, steps):
             "seconds": round(dt, 2)}
 
 
+VARIANTS = {"fp32_same_workload", "fp32_flat_4096", "step2bis_corrected_fp64", "scheme1_cn_gmres",
+            "em_potentials_fp64", "fp32_3d_flat_256", "fp64_3d_curved_128", "batch_256_mixed", "serve_poisson"}
+
+
 def progress(msg: str):
     """One line on stderr before each GPU stage, so a failing run names its stage."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -301,6 +305,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (counter calibration)")
     args = ap.parse_args()
+    if args.variants is not None and not set(args.variants.split(",")) <= VARIANTS:
+        print(f"unknown variants: {sorted(set(args.variants.split(',')) - VARIANTS)}; known: {sorted(VARIANTS)}",
+              file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); a multi-GPU form of this solver is "
               "not built", file=sys.stderr)
