@@ -510,6 +510,138 @@ def test_cn_curved_step_matches_dense_solve():
     assert O.rel_l2(O.cn_step(psi, T), ref) < 1e-12
 
 
+def _appendix_b_matrix(n, a):
+    """Differentiation matrix of Appendix B in closed form (the extra factor i of
+    the printed formula removed, literal Nyquist mode), written out entry by entry."""
+    D = np.empty((n, n), complex)
+    for k in range(n):
+        for kp in range(n):
+            D[k, kp] = (-1j * math.pi / (2 * a) if k == kp else
+                        math.pi / (2 * a) * (-1) ** (k - kp) * (1 / math.tan(math.pi * (k - kp) / n) - 1j))
+    return D
+
+
+def _type1_inverse_stretch(n, a, w, s0):
+    """1/S of a type-I layer of w points next to the periodic seam (R4), from the
+    definition Sigma(s) = s0 (s + d)^2, d = w h, |x_k| - L = -min(k, n - k) h."""
+    h = 2 * a / n
+    out = np.ones(n)
+    for k in range(n):
+        dk = min(k, n - k)
+        if dk <= w:
+            out[k] = 1.0 / (1.0 + s0 * ((w - dk) * h) ** 2)
+    return out
+
+
+def _exp3_a(X, Y):
+    """a = e^{Phi - Psi} of Numerical Experiment 3 in closed form."""
+    r2 = X * X + Y * Y
+    return np.exp(np.exp(-0.01 * r2) - np.exp(-0.005 * r2))
+
+
+def _exp3_E(x, y, c, m, dt):
+    """Step-1 factor exp(-i dt/2 [e^Phi m c^2 sigma_z + F]), F = -i c a (chi_x sigma_x +
+    chi_y sigma_y) / 2 with chi = Phi (the printed 2-D equation), by scipy expm per
+    point; the gradient of Phi by central differences of its closed form."""
+    E = np.empty((y.size, x.size, 2, 2), complex)
+    phi = lambda u, v: math.exp(-0.01 * (u * u + v * v))
+    dl = 1e-6
+    for j, yv in enumerate(y):
+        for i, xv in enumerate(x):
+            px = (phi(xv + dl, yv) - phi(xv - dl, yv)) / (2 * dl)
+            py = (phi(xv, yv + dl) - phi(xv, yv - dl)) / (2 * dl)
+            av = math.exp(phi(xv, yv) - math.exp(-0.005 * (xv * xv + yv * yv)))
+            Fm = -0.5j * c * av * (px * O.SIGMA_X + py * O.SIGMA_Y)
+            E[j, i] = scipy.linalg.expm(-0.5j * dt * (math.exp(phi(xv, yv)) * m * c * c * O.SIGMA_Z + Fm))
+    return E
+
+
+def test_cn_curved_layer_operator_matches_appendix_b_construction():
+    # Scheme I with a layer and a metric that varies along both axes, on a
+    # rectangular grid whose layers differ per axis (h1 != h2).  G = I + (dt/2)
+    # c (b_x sigma_x D_x + b_y sigma_y D_y) (eq. (cn), Appendix A: a/S_x on the x
+    # derivative, a/S_y on the y derivative) is assembled densely here from the
+    # Appendix-B matrices, with a, 1/S and E computed here; a swap of b_x and b_y,
+    # or a dropped 1/S, changes the result.
+    n1, n2, a1, a2, c, m, dt, w, s0 = 16, 8, 3.0, 2.0, 1.1, 0.8, 0.15, 3, 2.0
+    p = O.Problem(n1=n1, n2=n2, a1=a1, a2=a2, dt=dt, c=c, m=m, metric=O.METRIC_PAPER_EXP3,
+                  spin=O.SPIN_PAPER, pml_width=w, pml_sigma0=s0)
+    T = O.build_tables(p)
+    x, y = -a1 + (2 * a1 / n1) * np.arange(n1), -a2 + (2 * a2 / n2) * np.arange(n2)
+    X, Y = np.meshgrid(x, y)
+    av = _exp3_a(X, Y)
+    bx = av * _type1_inverse_stretch(n1, a1, w, s0)[None, :]
+    by = av * _type1_inverse_stretch(n2, a2, w, s0)[:, None]
+    assert np.max(np.abs(bx - by)) > 0.1                 # the two axes really differ
+    Dx, Dy = _appendix_b_matrix(n1, a1), _appendix_b_matrix(n2, a2)
+    sx, sy = O.SIGMA_X, O.SIGMA_Y
+    nn = n2 * n1 * 2
+    A = np.zeros((nn, nn), complex)                       # alpha(x) . T as a dense matrix
+    idx = lambda j, i, s: (j * n1 + i) * 2 + s
+    for j in range(n2):
+        for i in range(n1):
+            for s in range(2):
+                for t in range(2):
+                    for k in range(n1):
+                        A[idx(j, i, s), idx(j, k, t)] += c * bx[j, i] * sx[s, t] * Dx[i, k]
+                    for k in range(n2):
+                        A[idx(j, i, s), idx(k, i, t)] += c * by[j, i] * sy[s, t] * Dy[j, k]
+    G = np.eye(nn) + 0.5 * dt * A
+    Gt = np.eye(nn) - 0.5 * dt * A
+    E = _exp3_E(x, y, c, m, dt)
+    rng = np.random.default_rng(29)
+    psi = rng.standard_normal((n2, n1, 2)) + 1j * rng.standard_normal((n2, n1, 2))
+    half = np.einsum("jiab,jib->jia", E, psi)
+    star = np.linalg.solve(G, Gt @ half.ravel()).reshape(psi.shape)
+    ref = np.einsum("jiab,jib->jia", E, star)
+    assert O.rel_l2(O.cn_step(psi, T), ref) < 1e-11
+
+
+def test_step2bis_corrected_full_step_with_a_two_axis_metric():
+    # One corrected second-order step (R15) on the Experiment-3 metric, which
+    # varies along both axes, with layers that differ per axis: b' along y is
+    # (d_y a) / S^2, here from central differences of the closed-form a, so using
+    # the x-gradient (or the x layer) for it changes the result.
+    n1, n2, a1, a2, c, m, dt, w, s0 = 16, 8, 6.0, 4.0, 1.0, 0.6, 0.12, 3, 1.5
+    p = O.Problem(n1=n1, n2=n2, a1=a1, a2=a2, dt=dt, c=c, m=m, metric=O.METRIC_PAPER_EXP3,
+                  spin=O.SPIN_PAPER, pml_width=w, pml_sigma0=s0, step2=O.STEP2BIS_CORRECTED)
+    T = O.build_tables(p)
+    x, y = -a1 + (2 * a1 / n1) * np.arange(n1), -a2 + (2 * a2 / n2) * np.arange(n2)
+    X, Y = np.meshgrid(x, y)
+    av = _exp3_a(X, Y)
+    dl = 1e-6
+    dax = (_exp3_a(X + dl, Y) - _exp3_a(X - dl, Y)) / (2 * dl)
+    day = (_exp3_a(X, Y + dl) - _exp3_a(X, Y - dl)) / (2 * dl)
+    is1, is2 = _type1_inverse_stretch(n1, a1, w, s0), _type1_inverse_stretch(n2, a2, w, s0)
+    bx, by = av * is1[None, :], av * is2[:, None]
+    dbx, dby = dax * is1[None, :], day * is2[:, None]
+    assert np.max(np.abs(dbx - dby)) > 0.02
+    E = _exp3_E(x, y, c, m, dt)
+
+    def stage(v, n, a, sig, b, db):
+        # rows of v are lines along the direction; explicit DFT sums and Appendix-B matrices
+        D1 = _appendix_b_matrix(n, a)
+        D2 = D1 @ D1
+        xi = np.array([(q if q < n // 2 else q - n) * math.pi / a for q in range(n)])
+        F = np.exp(-2j * math.pi * np.outer(np.arange(n), np.arange(n)) / n)
+        K = np.array([math.cos(c * dt * z) * O.ID2 - 1j * math.sin(c * dt * z) * sig for z in xi])
+        out = np.empty_like(v)
+        for j in range(v.shape[0]):
+            Xi = np.conj(F) @ np.einsum("qab,qb->qa", K, F @ v[j]) / n
+            out[j] = (b[j][:, None] * Xi + (1 - b[j][:, None]) * v[j]
+                      + 0.5 * (c * dt) ** 2 * (-(b[j] * (1 - b[j]))[:, None] * (D2 @ v[j])
+                                               + (b[j] * db[j])[:, None] * (D1 @ v[j])))
+        return out
+
+    rng = np.random.default_rng(31)
+    psi = rng.standard_normal((n2, n1, 2)) + 1j * rng.standard_normal((n2, n1, 2))
+    v = np.einsum("jiab,jib->jia", E, psi)
+    v = stage(v, n1, a1, O.SIGMA_X, bx, dbx)
+    v = stage(v.transpose(1, 0, 2), n2, a2, O.SIGMA_Y, by.T, dby.T).transpose(1, 0, 2)
+    ref = np.einsum("jiab,jib->jia", E, v)
+    assert O.rel_l2(O.step(psi, T), ref) < 1e-10
+
+
 def test_cn_is_second_order_for_x_only_data_and_unconditionally_stable():
     # data constant in y: no splitting error between directions; CN transport is
     # second order; with a > 1 (outside Scheme II's stability range) the plain norm
