@@ -208,26 +208,48 @@ dirac_status dirac_create_solver(const dirac_grid* grid, const dirac_metric* met
  * residual reached by the last solve. */
 dirac_status dirac_cn_stats(const dirac_solver* s, int64_t* iterations, double* last_rel_residual);
 
-/* Upload the initial spinor (host [n2][n1][2] complex128, not normalised) and
- * reset the step counter and time to 0.  Synchronises the stream. */
+/* Scheme I stopping rule of the solves that follow (Sec. 5.1: the linear system
+ * of eq. (cn) is solved iteratively): at most max_iter >= 1 GMRES iterations per
+ * step, stop at ||G x - b|| <= rtol ||b|| (rtol > 0).  A step that fails
+ * (DIRAC_E_NOCONV, DIRAC_E_NONFINITE) leaves the state and step counter of the
+ * whole dirac_step_n call as they were, so the call can be retried after
+ * loosening the limits.  DIRAC_E_ARG for other schemes. */
+dirac_status dirac_cn_set_limits(dirac_solver* s, int32_t max_iter, double rtol);
+
+/* Upload the initial spinor psi^0 sampled at the grid points x_i = -a1 + i h1,
+ * y_j = -a2 + j h2 of Sec. 5 (the collocation points of the partial DFTs
+ * F_1, F_2 defined there): host [n2][n1][2] complex128, taken as given (not
+ * normalised).  Resets the step counter and time to 0.  Synchronises the
+ * stream.  DIRAC_E_NONFINITE if any value is not finite (nothing uploaded). */
 dirac_status dirac_set_initial_spinor(dirac_solver* s, const double* psi_host);
 
 /* Same from device memory: psi_dev holds [n2][n1][2] complex128 on the
- * solver's device.  Asynchronous on the solver's stream. */
+ * solver's device (caller-owned, read before the next call on the stream
+ * completes).  Asynchronous on the solver's stream; values are not checked. */
 dirac_status dirac_set_initial_spinor_device(dirac_solver* s, const void* psi_dev);
 
-/* Advance nsteps >= 0 time steps (Step 1, x, y, Step 5 each), asynchronously
- * on the solver's stream.  Between consecutive steps Step 5 and the next Step 1
- * are applied back to back in registers (E then E), which is the same
- * arithmetic as the unfused order. */
+/* Advance nsteps >= 0 time steps of the scheme chosen at creation.  Scheme II:
+ * the Strang-split step of eq. (poly_mod) -- Step 1 (eq. (step1)), the x and y
+ * directional steps of eq. (second_scheme) with the layer's a/S^i, Step 5
+ * (eq. (step3)) -- asynchronously on the solver's stream.  Between consecutive
+ * steps Step 5 and the next Step 1 are applied back to back in registers (E then
+ * E), which is the same arithmetic as the unfused order.  Scheme I (eq. (cn)):
+ * synchronous (the host drives the GMRES cycles); if a solve fails
+ * (DIRAC_E_NOCONV, DIRAC_E_NONFINITE) the state and step counter are put back
+ * to those at entry.  DIRAC_E_STATE before an initial spinor. */
 dirac_status dirac_step_n(dirac_solver* s, int64_t nsteps);
 
-/* Compute the observables of the current state (two spectral-derivative
- * passes with fused FP64 partial sums, then one fixed-order FP64 reduction;
- * bitwise reproducible).  Synchronises the stream. */
+/* Compute the observables of the current state into *out (caller-owned):
+ * the discrete L2 norm of eq. (l2gamma) (dA sum over the grid), its weighted
+ * form, and the energy with the spectral derivative of eq. (trick) (fields of
+ * dirac_obs above).  Two derivative passes with fused FP64 partial sums, then
+ * one fixed-order FP64 reduction: bitwise reproducible.  Synchronises the
+ * stream.  DIRAC_E_STATE before an initial spinor. */
 dirac_status dirac_observables(dirac_solver* s, dirac_obs* out);
 
-/* Copy the state to host memory as complex128 [n2][n1][2].  Synchronises. */
+/* Copy the state psi^n at the grid points of Sec. 5 to host memory
+ * (caller-owned, 4 n1 n2 doubles) as complex128 [n2][n1][2] (FP32 states are
+ * widened exactly).  Synchronises. */
 dirac_status dirac_get_spinor(dirac_solver* s, double* psi_host_out);
 
 /* Release the handle (host memory only; the caller's device buffer is untouched). */

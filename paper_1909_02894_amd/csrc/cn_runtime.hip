@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <string>
 #include <vector>
 
 #include "../../include/dirac.h"
@@ -250,16 +251,39 @@ dirac_status cn_step_n(dirac_solver* s, int64_t nsteps) {
         }
         return launch_em_exp(c.psi, reinterpret_cast<const double*>(b + s->lay.em), c.npts, times, fA, fV, c.st);
     };
-    for (int64_t n = 0; n < nsteps; ++n) {
-        CN_TRY(exp_steps(s->step, n == 0 ? 1 : 2, false), "Step 1");
-        CN_TRY(apply_G(c, c.psi, c.rhs, -1.0), "apply G~");
-        CN_TRY(norm2_dev(c, c.rhs, 4), "right-hand side norm");
-        dirac_status r = gmres(c, s->cn_iters, s->cn_last_res);
-        if (r != DIRAC_OK) return r;
-        s->step += 1;
+    // A failed call leaves the solver as it was: the state at entry is kept in
+    // the staging area (N x 32 bytes, Scheme I is FP64) and put back, with the
+    // step counter, if any step fails (its Step 1 and the closing Step 3 of the
+    // earlier steps of this call would otherwise be half applied).
+    const size_t state_bytes = c.npts * 32;
+    char* saved = b + s->lay.scratch;
+    CN_TRY(hipMemcpyAsync(saved, c.psi, state_bytes, hipMemcpyDeviceToDevice, c.st), "save state");
+    const int64_t step0 = s->step;
+    auto steps = [&]() -> dirac_status {
+        for (int64_t n = 0; n < nsteps; ++n) {
+            CN_TRY(exp_steps(s->step, n == 0 ? 1 : 2, false), "Step 1");
+            CN_TRY(apply_G(c, c.psi, c.rhs, -1.0), "apply G~");
+            CN_TRY(norm2_dev(c, c.rhs, 4), "right-hand side norm");
+            dirac_status r = gmres(c, s->cn_iters, s->cn_last_res);
+            if (r != DIRAC_OK) return r;
+            s->step += 1;
+        }
+        CN_TRY(exp_steps(s->step - 1, 1, true), "Step 3");
+        CN_TRY(hipStreamSynchronize(c.st), "synchronise");
+        return DIRAC_OK;
+    };
+    const dirac_status r = steps();
+    if (r != DIRAC_OK) {
+        const std::string msg = dirac_last_error();
+        s->step = step0;
+        s->cn_cycle_len = 0;
+        const hipError_t e1 = hipMemcpyAsync(c.psi, saved, state_bytes, hipMemcpyDeviceToDevice, c.st);
+        const hipError_t e2 = hipStreamSynchronize(c.st);
+        if (e1 != hipSuccess || e2 != hipSuccess)
+            return fail(r, "%s (restoring the state also failed: %s)", msg.c_str(),
+                        hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        return fail(r, "%s", msg.c_str());
     }
-    CN_TRY(exp_steps(s->step - 1, 1, true), "Step 3");
-    CN_TRY(hipStreamSynchronize(c.st), "synchronise");
     return DIRAC_OK;
 }
 

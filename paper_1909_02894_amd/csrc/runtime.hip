@@ -510,6 +510,16 @@ dirac_status dirac_cn_stats(const dirac_solver* s, int64_t* iterations, double* 
     return DIRAC_OK;
 }
 
+dirac_status dirac_cn_set_limits(dirac_solver* s, int32_t max_iter, double rtol) {
+    if (!s) return fail(DIRAC_E_ARG, "null solver");
+    if (s->scheme.scheme != DIRAC_SCHEME_CN_GMRES) return fail(DIRAC_E_ARG, "not a Scheme I solver");
+    if (max_iter < 1) return fail(DIRAC_E_ARG, "max_iter must be >= 1");
+    if (!(rtol > 0) || !std::isfinite(rtol)) return fail(DIRAC_E_ARG, "rtol must be finite and > 0");
+    s->scheme.gmres_max_iter = max_iter;
+    s->scheme.gmres_rtol = rtol;
+    return DIRAC_OK;
+}
+
 dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, const dirac_pml* pml,
                                  int32_t prec, const dirac_scheme* scp, const dirac_em* em, void* device_buffer,
                                  size_t bytes, void* hip_stream, dirac_solver** out) {

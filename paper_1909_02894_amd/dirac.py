@@ -112,6 +112,7 @@ SIGNATURES = {
     "dirac_create_solver": (C.c_int32, [C.POINTER(Grid), C.POINTER(Metric), C.POINTER(Pml), C.c_int32,
                                         C.POINTER(Scheme), C.POINTER(Em), _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     "dirac_cn_stats": (C.c_int32, [_vp, C.POINTER(C.c_int64), _dp]),
+    "dirac_cn_set_limits": (C.c_int32, [_vp, C.c_int32, C.c_double]),
     "dirac_set_initial_spinor": (C.c_int32, [_vp, _dp]),
     "dirac_set_initial_spinor_device": (C.c_int32, [_vp, _vp]),
     "dirac_step_n": (C.c_int32, [_vp, C.c_int64]),
@@ -265,6 +266,10 @@ def cn_stats(h):
     return int(it.value), float(res.value)
 
 
+def cn_set_limits(h, max_iter: int, rtol: float):
+    _check(lib.dirac_cn_set_limits(h, int(max_iter), float(rtol)))
+
+
 def set_initial_spinor(h, psi: np.ndarray):
     psi = np.ascontiguousarray(psi, dtype=np.complex128)
     _check(lib.dirac_set_initial_spinor(h, psi.view(np.float64).ctypes.data_as(_dp)))
@@ -398,6 +403,9 @@ class Solver:
         us = (C.c_double * 2)()
         _check(lib.dirac_time_directions(self.h, reps, us))
         return [us[0], us[1]]
+
+    def cn_set_limits(self, max_iter: int, rtol: float):
+        cn_set_limits(self.h, max_iter, rtol)
 
     def cn_stats(self):
         """(total GMRES iterations, last relative residual) of a Scheme I solver."""

@@ -145,9 +145,20 @@ def test_cn_reports_no_convergence(D):
     spec = W.curved_bump(n=32, steps=1, m=1.0)
     spec.dt = 0.4
     s = cn_solver(D, spec, rtol=1e-15, restart=2, max_iter=2)
-    s.set_initial_spinor(W.initial_spinor(spec))
+    psi0 = W.initial_spinor(spec)
+    s.set_initial_spinor(psi0)
     with pytest.raises(D.DiracError) as ei:
-        s.step_n(1)
+        s.step_n(3)
     assert ei.value.status == -8
+    # the failed call left the solver as it was: state bitwise, step counter 0
+    assert np.array_equal(s.get_spinor(), psi0)
+    assert s.observables()["step"] == 0
+    # a retry with a workable stopping rule gives the oracle's three steps
+    s.cn_set_limits(400, 1e-14)
+    s.step_n(3)
+    T = O.build_tables(oracle_problem(spec))
+    assert O.rel_l2(s.get_spinor(), O.cn_run(psi0, T, 3)) < TOL
+    with pytest.raises(D.DiracError):
+        s.cn_set_limits(0, 1e-14)
     with pytest.raises(D.DiracError):
         s.autotune(2)
