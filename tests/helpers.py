@@ -18,3 +18,33 @@ def oracle_problem(s, fields=None, step2=0, potentials=None) -> "O.Problem":
                      spin=s.spin, bump_A=s.bump_A, bump_s=s.bump_s, fields=fields,
                      pml_width=s.pml_width, pml_type=s.pml_type, pml_sigma0=s.pml_sigma0,
                      pml_theta=s.pml_theta, step2=step2, em=em)
+
+
+def oracle_checkpoints(spec, checkpoints, psi0=None):
+    """The oracle's states of a workload spec at the given step counts (one pass)."""
+    from paper_1909_02894_amd import workloads as W
+    T = O.build_tables(oracle_problem(spec))
+    psi = W.initial_spinor(spec) if psi0 is None else psi0
+    out, done = {}, 0
+    for c in sorted(set(checkpoints)):
+        psi = O.run(psi, T, c - done)
+        done = c
+        out[c] = psi
+    return out
+
+
+def oracle_final_many(specs_steps, workers=6):
+    """oracle_checkpoints(spec, [steps])[steps] for each (spec, steps), computed in
+    separate processes (spawned: they import NumPy and the oracle only)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=max(1, min(workers, len(specs_steps))),
+                             mp_context=mp.get_context("spawn")) as ex:
+        futs = [ex.submit(oracle_checkpoints, sp, [st]) for sp, st in specs_steps]
+        return [f.result()[st] for f, (_, st) in zip(futs, specs_steps)]
+
+
+def max_rel(a, ref):
+    """max_k |a_k - ref_k| / max_k |ref_k|."""
+    import numpy as np
+    return float(np.abs(a - ref).max() / np.abs(ref).max())
