@@ -2,14 +2,22 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-variants] [--skip-cpu]
 
-Workload (the curved-graphene-shaped solve): 512 x 512 periodic grid on
-[-20,20)^2, static sheet over a Gaussian bump h = A exp(-r^2/s^2) with A, s
-drawn from seed 1909, absorbing layer of 32 points per side (type I, sigma0 = 1,
-theta = 0), massless, c = 1, dt = 0.01, Gaussian packet of width 2 at a seeded
-momentum; the state starts resident in HBM.  One "step" = Step 1 + x + y +
-Step 5 of the scheme over the whole grid.  The headline value is the FP64 path
-(complex128 state); the FP32 path (FP64-generated tables, FP64 reductions) and
-a large flat FP32 solve beyond the 256 MB Infinity Cache are reported beside it.
+Headline workload (the largest single-GPU configuration): 256 independent
+curved-graphene-shaped solves advanced together by the batch engine, FP32
+(tables generated in FP64 and rounded once, FP64 reductions).  Solve i draws
+its grid size n uniformly from {128, 256, 512} (n x n points on [-20,20)^2,
+absorbing layer of n/16 points per side, type I, sigma0 = 1, theta = 0), its
+bump h = A exp(-r^2/s^2) (A in [0.5, 2], s in [2, 6]) and its packet momentum
+from seed 4000 + i; massless, c = 1, dt = 0.01.  ~460 MiB of state, beyond the
+256 MB Infinity Cache; inputs resident in HBM when the timed region starts.
+One "step" = one time step (Step 1 + x + y + Step 5) of every solve; the K
+timed steps are one replay of the run's HIP graph.  Kernel durations for the
+roofline come from a second pass with per-launch HIP events.
+
+Variants beside it: the same batch in FP64, the curved 512^2 solve (FP64 and
+FP32), the flat 2048^2 precision workload (FP32 and FP64, 5000 steps), flat and
+curved single solves beyond the Infinity Cache, the second-order step, Scheme I,
+potentials, 3-D, and Poisson serving (p50/p99 latency).
 
 Prints ONE JSON line.
 """
@@ -74,7 +82,7 @@ def load_traffic(name: str, instantiation: str | None = None):
     return dict(rec, instantiation=instantiation)
 
 
-def time_solve(D, spec, precision, steps, warmup, timed_steps, scheme=0):
+def time_solve(D, spec, precision, steps, warmup, timed_steps, scheme=0, keep_state=False):
     import torch
     s = D.Solver.from_spec(spec, precision=precision, scheme=scheme)
     from paper_1909_02894_amd import workloads as W
@@ -96,6 +104,7 @@ def time_solve(D, spec, precision, steps, warmup, timed_steps, scheme=0):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     obs = s.observables()
+    state = s.get_spinor() if keep_state else None
     # per-launch durations in the real x, y order: every launch carries its own
     # start/stop events on the solver's stream (kernel execution time)
     kms, cnt = s.step_n_timed(timed_steps)
@@ -105,7 +114,8 @@ def time_solve(D, spec, precision, steps, warmup, timed_steps, scheme=0):
     sched = (s.schedule(0), s.schedule(1))
     wt = s.store_mode()
     s.close()
-    return dict(ms=ms, wall=wall, obs=obs, kernel_us=kus, isolated_us=iso, sched=sched, write_through=wt)
+    return dict(ms=ms, wall=wall, obs=obs, kernel_us=kus, isolated_us=iso, sched=sched, write_through=wt,
+                state=state)
 
 
 def roofline_for(spec, kind, precision, r):
@@ -120,7 +130,11 @@ def roofline_for(spec, kind, precision, r):
     inst = (f"stage_kernel<{'double' if precision == 0 else 'float'}, {spec.n1 if dom == 0 else spec.n2}, {rr}, "
             f"{ll}, {'true' if dom == 1 else 'false'}, {mode}, {cc}>")
     tr = load_traffic(name, inst)
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+    sz = 8 if precision == 0 else 4
+    working = N * (8 * sz if kind != "curved" else 13 * sz)       # state + per-point tables
+    bound = "hbm" if working > INFINITY_CACHE_BYTES else "cache-resident"
+    return {"bound": bound, "working_set_bytes": working, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
             "kernel": name, "avg_launch_us": round(avg[dom] * 1e3, 3),
             "algorithmic_bytes_per_launch": byt,
@@ -129,41 +143,108 @@ def roofline_for(spec, kind, precision, r):
             "isolated_us": [round(u, 3) for u in r["isolated_us"]]}
 
 
-def bench_batch(D, W, count=256, steps=1000):
-    """Many independent curved solves of mixed size advanced by the batch engine:
-    one graph launch for the whole run (timed on its second, graph-reusing run)."""
+BATCH_SIZES = (128, 256, 512)
+INFINITY_CACHE_BYTES = 256 << 20
+
+
+def batch_kernel_name(precision: int, d: int, n, sched: int | None) -> str:
+    t = "double" if precision == 0 else "float"
+    if n == "multi":
+        return f"batch_multi_kernel<{t}, {'true' if d else 'false'}>"
+    return f"batch_group_kernel<{t}, {'true' if d else 'false'}, {n}, {sched}>"
+
+
+def batch_schedule_index(radix: int, cpt: int, n: int) -> int:
+    """The batch kernel's schedule template argument for (radix, components):
+    schedules 0/1 use the default radix (4 for n <= 64, else 8), 2/3 the other;
+    odd schedules carry one component per thread."""
+    default = 4 if n <= 64 else 8
+    return (0 if radix == default else 2) + (1 if cpt == 1 else 0)
+
+
+def bench_batch(D, W, precision, steps, warmup, timed_steps, count=256):
+    """The batch workload: autotuned schedules, `warmup` untimed steps, the
+    graph of the K-step run recorded and instantiated untimed, then the timed
+    replay (HIP events on the batch stream).  A second pass of `timed_steps`
+    steps launches every phase kernel with its own start/stop events for the
+    per-kernel durations."""
     import torch
-    specs = W.batch_mix(count, 4000, (128, 256, 512), steps)
-    b = D.Batch(precision=D.FP32, capacity=count)
+    specs = W.batch_mix(count, 4000, BATCH_SIZES, steps)
+    b = D.Batch(precision=precision, capacity=count)
     solvers = []
     for sp in specs:
-        s = D.Solver.from_spec(sp, precision=D.FP32, stream=b.stream)
+        s = D.Solver.from_spec(sp, precision=precision, stream=b.stream)
         s.set_initial_spinor(W.initial_spinor(sp))
         b.add(s)
         solvers.append(s)
     b.autotune(5)                   # schedule per (direction, n), states restored
-    sched = {str(n): [b.schedule(n, 0), b.schedule(n, 1)] for n in (128, 256, 512)}
-    b.run([steps] * count)          # builds and replays the graph
+    sched = {n: [b.schedule(n, 0), b.schedule(n, 1)] for n in BATCH_SIZES}
+    if warmup > 0:
+        b.run([warmup] * count)
+    b.prepare([steps] * count)      # record + instantiate the K-step graph (untimed)
     b.sync()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(b.stream)
-    b.run([steps] * count)          # the same run: graph reused
+    b.run([steps] * count)          # graph replay
     e1.record(b.stream)
     b.sync()
     ms = e0.elapsed_time(e1)
-    pts = sum(sp.n1 * sp.n2 for sp in specs)
-    fin = all(s.observables()["finite"] for s in solvers[:8])
-    algo = 88.0 * pts * steps
-    hist = {n: sum(1 for sp in specs if sp.n1 == n) for n in (128, 256, 512)}
+    cls = b.run_timed([timed_steps] * count)
+    fin = all(s.observables()["finite"] for s in solvers[::16])
     b.close()
-    return {"value": pts * steps / (ms * 1e-3), "unit": "grid-point*steps/s", "dtype": "f32",
-            "solves": count, "steps": steps, "grid_sizes": hist, "ms": ms, "finite": fin, "schedules": sched,
-            "step_roofline": {"bound": "hbm", "achieved": round(algo / (ms * 1e-3) / 1e9, 1),
-                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                              "bytes_per_point_step": 88,
-                              "state_bytes": pts * 16}}
+    pts = sum(sp.n1 * sp.n2 for sp in specs)
+    sz = 8 if precision == 0 else 4
+    step_bytes = 22 * sz * pts                         # x 13 sz + y 9 sz per point (curved)
+    classes = {}
+    for (d, n), (kms, cnt, byt) in cls.items():
+        avg_us = 1e3 * kms / cnt
+        bpl = byt / cnt
+        sc = None if n == "multi" else batch_schedule_index(sched[n][d][0], sched[n][d][2], n)
+        classes[f"{'xy'[d]}_{n}"] = {
+            "kernel": batch_kernel_name(precision, d, n, sc), "launches": cnt, "avg_launch_us": round(avg_us, 2),
+            "algorithmic_bytes_per_launch": round(bpl), "achieved_GBs": round(bpl / (avg_us * 1e-6) / 1e9, 1),
+            "frac": round(bpl / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4), "total_ms": round(kms, 3)}
+    dom = max(classes, key=lambda k: classes[k]["total_ms"])
+    dc = classes[dom]
+    phase = {}
+    for d in "xy":
+        ks = [c for k, c in classes.items() if k.startswith(d)]
+        tb = sum(c["algorithmic_bytes_per_launch"] * c["launches"] for c in ks)
+        tt = sum(c["total_ms"] for c in ks) * 1e-3
+        phase[d] = round(tb / tt / 1e9 / HBM_PEAK_GBS, 4)
+    tr = load_batch_traffic(dc["kernel"])
+    roof = {"bound": "hbm", "achieved": dc["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": dc["frac"], "traffic": tr, "kernel": dc["kernel"], "avg_launch_us": dc["avg_launch_us"],
+            "algorithmic_bytes_per_launch": dc["algorithmic_bytes_per_launch"],
+            "bytes_per_point": {"x": 13 * sz, "y": 9 * sz},
+            "timing": f"{timed_steps} steps of direct launches, each with its own hipExtLaunchKernel start/stop "
+                      "events on the batch stream (x and y phases in the order of a real run)",
+            "kernels": classes, "phase_frac": phase,
+            "step_frac": round(step_bytes * steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "step_timing": f"one HIP graph replay of {steps} steps (the timed region)"}
+    hist = {str(n): sum(1 for sp in specs if sp.n1 == n) for n in BATCH_SIZES}
+    return {"value": pts * steps / (ms * 1e-3), "ms": ms, "ms_per_step": ms / steps, "dtype": "f64" if sz == 8 else "f32",
+            "solves": count, "points": pts, "state_bytes": pts * 4 * sz, "grid_sizes": hist, "finite": fin,
+            "schedules": {str(n): v for n, v in sched.items()}, "roofline": roof}
+
+
+def load_batch_traffic(kernel: str):
+    """HBM bytes per launch of a batch phase kernel from rocprofv3 FETCH_SIZE /
+    WRITE_SIZE (profiles/traffic.json, key batch_kernels), or None when absent or
+    taken on other kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    from paper_1909_02894_amd.profiling import kernel_sources_digest
+    if d.get("kernel_sources") != kernel_sources_digest():
+        return None
+    rec = d.get("batch_kernels", {}).get(kernel)
+    return None if rec is None else dict(rec, instantiation=kernel)
 
 
 def bench_cn(D, spec, steps=40):
@@ -268,23 +349,9 @@ def bench_serve(count, rate, budget, quantum=64, seed=5000):
             "max_running": st.max_running, "quanta": st.quanta, "peak_arena_bytes": st.peak_arena_bytes}
 
 
-def cpu_baseline(spec, steps):
-    from oracle import dirac_oracle as O
-    from paper_1909_02894_amd import workloads as W
-    from tests.helpers import oracle_problem
-    T = O.build_tables(oracle_problem(spec))
-    psi = W.initial_spinor(spec)
-    t0 = time.perf_counter()
-    O.run(psi, T, steps)
-    dt = time.perf_counter() - t0
-    return {"value": spec.n1 * spec.n2 * steps / dt, "unit": "grid-point*steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of the same {spec.n1}x{spec.n2} curved solve (NumPy complex128, "
-                      f"single-threaded pocketfft); host has {os.cpu_count()} logical CPUs",
-            "seconds": round(dt, 2)}
-
-
-VARIANTS = {"fp32_same_workload", "fp32_flat_4096", "step2bis_corrected_fp64", "scheme1_cn_gmres",
-            "em_potentials_fp64", "fp32_3d_flat_256", "fp64_3d_curved_128", "batch_256_mixed", "serve_poisson"}
+VARIANTS = {"batch_256_fp64", "curved_512_fp64", "curved_512_fp32", "flat_2048_precision", "flat_4096_fp32",
+            "flat_4096_fp64", "curved_2048_fp64", "curved_4096_fp32", "step2bis_corrected_fp64", "scheme1_cn_gmres",
+            "em_potentials_fp64", "fp32_3d_flat_256", "fp64_3d_curved_128", "serve_poisson"}
 
 
 def progress(msg: str):
@@ -292,16 +359,48 @@ def progress(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def single_variant(D, spec, kind, precision, steps, warmup, timed, note, keep_state=False):
+    r = time_solve(D, spec, precision, steps, warmup, timed, keep_state=keep_state)
+    out = {"value": spec.n1 * spec.n2 * steps / (r["ms"] * 1e-3), "unit": "grid-point*steps/s",
+           "ms_per_step": r["ms"] / steps, "steps": steps, "dtype": "f64" if precision == 0 else "f32",
+           "grid": [spec.n1, spec.n2], "note": note, "roofline": roofline_for(spec, kind, precision, r),
+           "schedule": {"x": r["sched"][0], "y": r["sched"][1], "write_through_mask": r["write_through"]},
+           "launch_mode": "HIP graph replay of 32-step chunks (value); direct launches with per-launch events "
+                          "(kernel durations)"}
+    return out, r.get("state")
+
+
+def cpu_baseline_batch(W, steps):
+    """The oracle on a bounded sample of the batch workload: the first solve of
+    each grid size, `steps` steps each, single-threaded."""
+    from oracle import dirac_oracle as O
+    from tests.helpers import oracle_problem
+    specs = W.batch_mix(256, 4000, BATCH_SIZES, steps)
+    sample = [next(sp for sp in specs if sp.n1 == n) for n in BATCH_SIZES]
+    work, secs = 0, 0.0
+    for sp in sample:
+        T = O.build_tables(oracle_problem(sp))
+        psi = W.initial_spinor(sp)
+        t0 = time.perf_counter()
+        O.run(psi, T, steps)
+        secs += time.perf_counter() - t0
+        work += sp.n1 * sp.n2 * steps
+    return {"value": work / secs, "unit": "grid-point*steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} steps of one solve of each size ({', '.join(f'{sp.n1}x{sp.n1} seed {sp.seed}' for sp in sample)}) "
+                      f"of the 256-solve batch (NumPy complex128, single-threaded pocketfft); the host has "
+                      f"{os.cpu_count()} logical CPUs", "seconds": round(secs, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--skip-variants", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--variants", default=None,
-                    help="comma-separated variant names to run (default: all; serve_poisson needs batch_256_mixed)")
-    ap.add_argument("--cpu-steps", type=int, default=300)
+                    help="comma-separated variant names to run (default: all)")
+    ap.add_argument("--cpu-steps", type=int, default=250)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (counter calibration)")
     args = ap.parse_args()
@@ -327,91 +426,124 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_each_way": 1 << 30, "copies": 3}), flush=True)
         return
-    spec = W.curved_bump(n=512, seed=1909, steps=args.steps)
     K = args.steps
-    timed = min(K, 500)
-    progress(f"headline: curved 512x512 FP64, {K} steps")
-    r64 = time_solve(D, spec, D.FP64, K, args.warmup, timed)
-    N = spec.n1 * spec.n2
-    value = N * K / (r64["ms"] * 1e-3)
+    timed = max(1, min(K, 50))
+    progress(f"headline: batch of 256 curved solves, FP32, {K} steps")
+    hb = bench_batch(D, W, D.FP32, K, args.warmup, timed)
     out = {
         "metric": "grid-point*steps/s on 1 MI355X (FP32 vs FP64), % HBM peak; p50/p99 latency",
-        "value": value,
+        "value": hb["value"],
         "unit": "grid-point*steps/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": r64["ms"] / K,
+        "ms_per_step": hb["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "curved bump 512x512, seed 1909, 32-point type-I layer, m=0, dt=0.01, FP64",
-                   "grid": [spec.n1, spec.n2], "bump_A": round(spec.bump_A, 6), "bump_s": round(spec.bump_s, 6),
-                   "k0": [round(k, 6) for k in spec.k0],
-                   "schedule": {"x": r64["sched"][0], "y": r64["sched"][1], "write_through_mask": r64["write_through"]}},
-        "roofline": roofline_for(spec, "curved", D.FP64, r64),
+        "config": {"workload": "batch of 256 independent curved-bump solves (seeds 4000+i, n uniform over "
+                               "{128,256,512}, n x n on [-20,20)^2, n/16-point type-I layer, m=0, dt=0.01), FP32, "
+                               "one HIP graph per run",
+                   "solves": hb["solves"], "grid_sizes": hb["grid_sizes"], "points": hb["points"],
+                   "state_bytes": hb["state_bytes"], "schedules": hb["schedules"]},
+        "roofline": hb["roofline"],
     }
     variants = {}
-    # --variants a,b: only those (e.g. for counter passes); the serving runs need the batch's rate
     chosen = None if args.variants is None else set(args.variants.split(","))
     want = lambda k: not args.skip_variants and (chosen is None or k in chosen)
-    if want("fp32_same_workload"):
-        progress("variant: same workload FP32")
-        r32 = time_solve(D, spec, D.FP32, K, args.warmup, timed)
-        variants["fp32_same_workload"] = {
-            "value": N * K / (r32["ms"] * 1e-3), "ms_per_step": r32["ms"] / K, "dtype": "f32",
-            "roofline": roofline_for(spec, "curved", D.FP32, r32),
-            "schedule": {"x": r32["sched"][0], "y": r32["sched"][1], "write_through_mask": r32["write_through"]}}
-    if want("fp32_flat_4096"):
+    if want("batch_256_fp64"):
+        progress("variant: the same batch in FP64")
+        h64 = bench_batch(D, W, D.FP64, K, args.warmup, timed)
+        variants["batch_256_fp64"] = {k: h64[k] for k in ("value", "ms_per_step", "dtype", "state_bytes", "schedules",
+                                                           "finite", "roofline")}
+        variants["batch_256_fp64"]["fp32_speedup"] = round(hb["value"] / h64["value"], 3)
+    spec512 = W.curved_bump(n=512, seed=1909, steps=2000)
+    if want("curved_512_fp64"):
+        progress("variant: curved 512x512 FP64, 2000 steps")
+        variants["curved_512_fp64"], _ = single_variant(
+            D, spec512, "curved", D.FP64, 2000, args.warmup, 500,
+            "curved bump 512x512, seed 1909, 32-point type-I layer, m=0, dt=0.01 (~20 MB working set)")
+    if want("curved_512_fp32"):
+        progress("variant: curved 512x512 FP32, 2000 steps")
+        variants["curved_512_fp32"], _ = single_variant(
+            D, spec512, "curved", D.FP32, 2000, args.warmup, 500, "the same solve in FP32")
+    if want("flat_2048_precision"):
+        flat = W.flat_small(n=2048, steps=5000)
+        progress("variant: flat 2048x2048 FP32, 5000 steps")
+        v32, s32 = single_variant(D, flat, "flat", D.FP32, 5000, 0, 100,
+                                  "flat 2048x2048 packet solve, 5000 steps (precision workload)", keep_state=True)
+        progress("variant: flat 2048x2048 FP64, 5000 steps")
+        v64, s64 = single_variant(D, flat, "flat", D.FP64, 5000, 0, 100, "the same solve in FP64", keep_state=True)
+        diff = float(np.linalg.norm((s32 - s64).ravel()) / np.linalg.norm(s64.ravel()))
+        mx = float(np.abs(s32 - s64).max() / np.abs(s64).max())
+        del s32, s64
+        variants["flat_2048_fp32"] = v32
+        variants["flat_2048_fp64"] = v64
+        variants["flat_2048_precision"] = {
+            "fp32_speedup": round(v32["value"] / v64["value"], 3),
+            "fp32_vs_fp64_gpu_rel_l2_at_5000": diff, "fp32_vs_fp64_gpu_maxabs_over_max_at_5000": mx,
+            "note": "both GPU paths after the same 5000 steps; against the exact discrete propagator the tests "
+                    "bound FP32 by 1e-3 and FP64 by 1e-10 at step 5000, below the scheme's own time error (~1e-3)"}
+    if want("flat_4096_fp32"):
         big = W.flat_small(n=4096, steps=200)
         progress("variant: flat 4096x4096 FP32")
-        rb = time_solve(D, big, D.FP32, 200, 10, 100)
-        variants["fp32_flat_4096"] = {
-            "value": big.n1 * big.n2 * 200 / (rb["ms"] * 1e-3), "ms_per_step": rb["ms"] / 200, "dtype": "f32",
-            "note": "flat 4096x4096 packet solve, 256 MiB state (beyond the Infinity Cache)",
-            "roofline": roofline_for(big, "flat", D.FP32, rb),
-            "schedule": {"x": rb["sched"][0], "y": rb["sched"][1], "write_through_mask": rb["write_through"]}}
+        variants["flat_4096_fp32"], _ = single_variant(D, big, "flat", D.FP32, 200, 10, 100,
+                                                       "flat 4096x4096 packet solve, 256 MiB state")
+    if want("flat_4096_fp64"):
+        big = W.flat_small(n=4096, steps=100)
+        progress("variant: flat 4096x4096 FP64")
+        variants["flat_4096_fp64"], _ = single_variant(D, big, "flat", D.FP64, 100, 10, 50,
+                                                       "flat 4096x4096 packet solve, 512 MiB state")
+    if want("curved_2048_fp64"):
+        cb = W.curved_bump(n=2048, seed=1909, steps=200)
+        progress("variant: curved 2048x2048 FP64")
+        variants["curved_2048_fp64"], _ = single_variant(
+            D, cb, "curved", D.FP64, 200, 10, 100, "curved bump 2048x2048 with a 128-point layer: 128 MiB state "
+            "+ 160 MiB of per-point tables")
+    if want("curved_4096_fp32"):
+        cb = W.curved_bump(n=4096, seed=1909, steps=100)
+        progress("variant: curved 4096x4096 FP32")
+        variants["curved_4096_fp32"], _ = single_variant(
+            D, cb, "curved", D.FP32, 100, 10, 50, "curved bump 4096x4096 with a 256-point layer: 256 MiB state "
+            "+ 320 MiB of per-point tables")
     if want("step2bis_corrected_fp64"):
         progress("variant: second-order directional step FP64")
-        rc = time_solve(D, spec, D.FP64, 500, args.warmup, 100, scheme=D.SCHEME_EXP_SPLIT_2BIS)
+        N = spec512.n1 * spec512.n2
+        rc = time_solve(D, spec512, D.FP64, 500, args.warmup, 100, scheme=D.SCHEME_EXP_SPLIT_2BIS)
         variants["step2bis_corrected_fp64"] = {
             "value": N * 500 / (rc["ms"] * 1e-3), "ms_per_step": rc["ms"] / 500, "dtype": "f64",
-            "note": "second-order directional step (three inverse transforms per direction), same workload",
+            "note": "second-order directional step (three inverse transforms per direction), curved 512x512",
             "x_avg_us": round(rc["kernel_us"][0], 3), "y_avg_us": round(rc["kernel_us"][1], 3),
             "roofline": variant_roofline(N, (120, 88), rc["kernel_us"],
                                          "x: state r/w 64 + E 32 + a 8 + gradient pair 16 B/pt; y: 64 + 8 + 16")}
     if want("scheme1_cn_gmres"):
         progress("variant: Scheme I")
-        variants["scheme1_cn_gmres"] = bench_cn(D, spec)
+        variants["scheme1_cn_gmres"] = bench_cn(D, spec512)
     if want("em_potentials_fp64"):
         progress("variant: potentials")
-        variants["em_potentials_fp64"] = bench_em(D, W, spec)
+        variants["em_potentials_fp64"] = bench_em(D, W, spec512)
     if want("fp32_3d_flat_256"):
         progress("variant: 3-D 256^3 FP32")
         variants["fp32_3d_flat_256"] = bench_3d(D, W, 256, D.FP32, False)
     if want("fp64_3d_curved_128"):
         progress("variant: 3-D 128^3 FP64")
         variants["fp64_3d_curved_128"] = bench_3d(D, W, 128, D.FP64, True)
-    if want("batch_256_mixed"):
-        progress("variant: batch of 256 solves")
-        bt = bench_batch(D, W)
-        variants["batch_256_mixed"] = bt
-        if want("serve_poisson"):
-            # serving at ~0.7x the measured batch capacity
-            mean_work = np.mean([n * n for n in (64, 128, 256, 512, 1024)]) * (200 + 5000) / 2.0
-            rate = 0.7 * bt["value"] / mean_work
-            progress("variant: serving, 288 GB budget")
-            variants["serve_poisson"] = bench_serve(100, rate, 288 << 30)
-            progress("variant: serving, 2 GB budget")
-            variants["serve_poisson_2GB"] = bench_serve(40, rate, 2 << 30, seed=5001)
-            out["latency"] = {"p50_s": variants["serve_poisson"]["p50_s"],
-                              "p99_s": variants["serve_poisson"]["p99_s"], "source": "serve_poisson"}
+    if want("serve_poisson"):
+        # serving at ~0.7x the measured batch capacity
+        mean_work = np.mean([n * n for n in (64, 128, 256, 512, 1024)]) * (200 + 5000) / 2.0
+        rate = 0.7 * hb["value"] / mean_work
+        progress("variant: serving, 288 GB budget")
+        variants["serve_poisson"] = bench_serve(100, rate, 288 << 30)
+        progress("variant: serving, 2 GB budget")
+        variants["serve_poisson_2GB"] = bench_serve(40, rate, 2 << 30, seed=5001)
+        out["latency"] = {"p50_s": variants["serve_poisson"]["p50_s"],
+                          "p99_s": variants["serve_poisson"]["p99_s"], "source": "serve_poisson"}
     out["variants"] = variants
     if not args.skip_cpu:
         progress("oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline_batch(W, args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -376,6 +376,25 @@ dirac_status dirac_batch_get_schedule(const dirac_batch* b, int32_t n, int32_t d
 dirac_status dirac_batch_set_schedule(dirac_batch* b, int32_t n, int32_t dir, const dirac_schedule* sch);
 dirac_status dirac_batch_autotune(dirac_batch* b, int32_t reps);
 
+/* Prepare the run dirac_batch_run(b, steps) would launch -- upload its
+ * descriptors and record and instantiate its HIP graph -- without launching
+ * it or advancing any solve; the next dirac_batch_run with the same step
+ * counts (and no slot change in between) only replays the graph.  No-op when
+ * graphs are off.  Asynchronous on the batch stream. */
+dirac_status dirac_batch_prepare(dirac_batch* b, const int64_t* steps);
+
+/* dirac_batch_run with one kernel launch per size group and phase (no graph),
+ * each launched with its own start/stop HIP events, then a synchronisation:
+ * the durations are the kernels' execution times in the order of a real run.
+ * Per kernel class c = direction * 9 + k (k = log2(n) - 4 for the kernel of the
+ * size group of transform length n, k = 8 for the kernel shared by the small
+ * groups): ms_out[c] = summed duration in milliseconds, counts_out[c] = number
+ * of launches, bytes_out[c] = their algorithmic HBM bytes (each solve's state
+ * read and written once per phase, plus its per-point tables: E and a in x, a
+ * in y, for curved solves).  The three arrays have 18 caller-owned entries. */
+dirac_status dirac_batch_run_timed(dirac_batch* b, const int64_t* steps, double* ms_out, int64_t* counts_out,
+                                   double* bytes_out);
+
 /* Wait for everything enqueued on the batch stream. */
 dirac_status dirac_batch_sync(dirac_batch* b);
 

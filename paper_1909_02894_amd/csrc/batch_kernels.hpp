@@ -66,6 +66,8 @@ __host__ __device__ constexpr int bsched_lines(int n, int s) { return kBatchThre
 __host__ __device__ constexpr int batch_lines(int n) { return bsched_lines(n, 0); }
 
 constexpr int kBatchMaxGroups = 8;
+// kernel classes of the timed run: 2 directions x (8 group lengths + the multi-group kernel)
+constexpr int kBatchTimingClasses = 18;
 
 // One launch covering several size groups (used when some group is too small
 // to fill the GPU on its own): group g owns tiles [start[g], start[g+1]).

@@ -1,6 +1,7 @@
 // batch_runtime.hip -- host side of the batched multi-solve engine: slot table,
 // descriptor upload (pinned, double buffered), per-run phase schedule and its
 // HIP graph.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -65,6 +66,7 @@ struct dirac_batch {
     uint64_t version = 0;
     uint64_t graph_version = ~0ull;
     int sched[2][12] = {};          // batch schedule per (direction, log2 n)
+    std::vector<hipEvent_t> events; // start/stop pairs of the timed runs
 };
 
 static dirac_status bhip(hipError_t e, const char* what) {
@@ -210,7 +212,28 @@ dirac_status dirac_batch_set_graph(dirac_batch* b, int32_t use_graph) {
     return DIRAC_OK;
 }
 
-dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
+}  // extern "C"
+
+// Per-launch timing of a run: durations and launch counts per kernel class,
+// class = direction * 9 + (log2 n - 4) for a size group's own kernel, or
+// direction * 9 + 8 for the multi-group kernel.
+struct BatchTiming {
+    double ms[kBatchTimingClasses];
+    int64_t count[kBatchTimingClasses];
+    double bytes[kBatchTimingClasses];     // algorithmic bytes of the launches (whole run)
+};
+
+// Algorithmic bytes per grid point of one phase launch: state read and written
+// once, plus the per-point tables read (x: E and a, y: a; curved solves only).
+static double phase_bytes_per_point(const dirac_solver* s, int dir) {
+    const double sz = s->prec == DIRAC_FP32 ? 4.0 : 8.0;
+    return 8.0 * sz + (s->curved ? (dir == 0 ? 5.0 * sz : sz) : 0.0);
+}
+
+// launch = false (graph mode only): record and instantiate the run's graph
+// without launching it, so that a later dirac_batch_run with the same step
+// counts only replays it.
+static dirac_status batch_run_impl(dirac_batch* b, const int64_t* steps, BatchTiming* tm, bool launch = true) {
     if (!b || !steps) return fail(DIRAC_E_ARG, "null argument");
     std::vector<int> act;
     for (int i = 0; i < b->capacity; ++i) {
@@ -229,7 +252,7 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
     sig.push_back((int64_t)b->version);
     for (int i : act) { sig.push_back(i); sig.push_back(steps[i]); }
 
-    const bool reuse = b->use_graph && b->gexec && sig == b->sig;
+    const bool reuse = !tm && b->use_graph && b->gexec && sig == b->sig;
     int h = reuse ? b->graph_half : b->which;
     char* dev = b->base + (size_t)h * b->half;
     const size_t desc_bytes = align256b((size_t)b->capacity * sizeof(BatchDesc<double>));
@@ -354,7 +377,52 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
     static_assert(sizeof(BatchMultiPhase<double>) == sizeof(BatchMultiPhase<float>), "phase layout");
 
     std::vector<GroupLaunch> gl;
-    if (!b->use_graph) {
+    // algorithmic bytes of one launch: its solves' points times the bytes per point
+    auto launch_bytes = [&](int d, const GroupLaunch& L) -> double {
+        double by = 0;
+        auto add_group = [&](const int* idx_dev, int nactive) {
+            const int* idx = reinterpret_cast<const int*>(b->host_stage[h] + desc_bytes) +
+                             (idx_dev - dints);
+            for (int q = 0; q < nactive; ++q) {
+                const dirac_solver* s = b->slots[act[idx[q]]];
+                by += (double)s->g.n1 * s->g.n2 * phase_bytes_per_point(s, d);
+            }
+        };
+        if (L.multi)
+            for (int g = 0; g < L.mph.ngroups; ++g) add_group(L.mph.index[g], L.mph.nactive[g]);
+        else
+            add_group(L.ph.index, L.ph.nactive);
+        return by;
+    };
+    if (tm) {
+        // one launch per group with its own start/stop events (hipExtLaunchKernel):
+        // kernel execution times in the order of a real run
+        std::vector<std::pair<int, double>> cls;     // class and bytes of launch i
+        for (int64_t k = 0; k < qmax; ++k)
+            for (int d = 0; d < 2; ++d) {
+                phase_launches(d, k, gl);
+                for (auto& L : gl) {
+                    const size_t i = cls.size();
+                    while (b->events.size() < 2 * (i + 1)) {
+                        hipEvent_t ev;
+                        BTRY(hipEventCreate(&ev), "hipEventCreate");
+                        b->events.push_back(ev);
+                    }
+                    void* args[] = {L.multi ? static_cast<void*>(&L.mph) : static_cast<void*>(&L.ph)};
+                    BTRY(hipExtLaunchKernel(L.fn, dim3(L.tiles), dim3(kBatchThreads), args, L.smem, b->stream,
+                                            b->events[2 * i], b->events[2 * i + 1], 0), "launch batch phase");
+                    cls.push_back({d * 9 + (L.multi ? 8 : L.mph.logn[0] - 4), launch_bytes(d, L)});
+                }
+            }
+        BTRY(hipStreamSynchronize(b->stream), "synchronise batch stream");
+        for (size_t i = 0; i < cls.size(); ++i) {
+            float ms = 0;
+            BTRY(hipEventElapsedTime(&ms, b->events[2 * i], b->events[2 * i + 1]), "hipEventElapsedTime");
+            tm->ms[cls[i].first] += ms;
+            tm->count[cls[i].first] += 1;
+            tm->bytes[cls[i].first] += cls[i].second;
+        }
+    } else if (!b->use_graph) {
         for (int64_t k = 0; k < qmax; ++k) {
             for (int d = 0; d < 2; ++d) {
                 phase_launches(d, k, gl);
@@ -393,10 +461,36 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
             b->sig = sig;
             b->graph_half = h;
         }
+        if (!launch) return DIRAC_OK;
         BTRY(hipGraphLaunch(b->gexec, b->stream), "hipGraphLaunch");
         BTRY(hipEventRecord(b->graph_done, b->stream), "record graph event");
     }
     for (int i : act) b->slots[i]->step += steps[i];
+    return DIRAC_OK;
+}
+
+extern "C" {
+
+dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps) {
+    return batch_run_impl(b, steps, nullptr);
+}
+
+dirac_status dirac_batch_prepare(dirac_batch* b, const int64_t* steps) {
+    if (b && !b->use_graph) return DIRAC_OK;
+    return batch_run_impl(b, steps, nullptr, false);
+}
+
+dirac_status dirac_batch_run_timed(dirac_batch* b, const int64_t* steps, double* ms_out, int64_t* counts_out,
+                                   double* bytes_out) {
+    if (!b || !steps || !ms_out || !counts_out || !bytes_out) return fail(DIRAC_E_ARG, "null argument");
+    BatchTiming tm{};
+    dirac_status r = batch_run_impl(b, steps, &tm);
+    if (r != DIRAC_OK) return r;
+    for (int i = 0; i < kBatchTimingClasses; ++i) {
+        ms_out[i] = tm.ms[i];
+        counts_out[i] = tm.count[i];
+        bytes_out[i] = tm.bytes[i];
+    }
     return DIRAC_OK;
 }
 
@@ -533,6 +627,7 @@ dirac_status dirac_batch_destroy(dirac_batch* b) {
         if (b->stage_done[h]) (void)hipEventDestroy(b->stage_done[h]);
     }
     if (b->graph_done) (void)hipEventDestroy(b->graph_done);
+    for (hipEvent_t ev : b->events) (void)hipEventDestroy(ev);
     delete b;
     return DIRAC_OK;
 }

@@ -137,6 +137,8 @@ SIGNATURES = {
     "dirac_batch_add": (C.c_int32, [_vp, _vp, C.POINTER(C.c_int32)]),
     "dirac_batch_remove": (C.c_int32, [_vp, C.c_int32]),
     "dirac_batch_run": (C.c_int32, [_vp, C.POINTER(C.c_int64)]),
+    "dirac_batch_prepare": (C.c_int32, [_vp, C.POINTER(C.c_int64)]),
+    "dirac_batch_run_timed": (C.c_int32, [_vp, C.POINTER(C.c_int64), _dp, C.POINTER(C.c_int64), _dp]),
     "dirac_batch_sync": (C.c_int32, [_vp]),
     "dirac_batch_set_graph": (C.c_int32, [_vp, C.c_int32]),
     "dirac_batch_destroy": (C.c_int32, [_vp]),
@@ -535,6 +537,9 @@ class Batch:
 
     def run(self, steps):
         """steps: dict slot -> n, or a sequence of capacity entries."""
+        _check(lib.dirac_batch_run(self.h, self._steps_array(steps)))
+
+    def _steps_array(self, steps):
         arr = (C.c_int64 * self.capacity)()
         if isinstance(steps, dict):
             for k, v in steps.items():
@@ -542,7 +547,26 @@ class Batch:
         else:
             for k, v in enumerate(steps):
                 arr[k] = int(v)
-        _check(lib.dirac_batch_run(self.h, arr))
+        return arr
+
+    def prepare(self, steps):
+        """Record and instantiate the graph of run(steps) without launching it."""
+        _check(lib.dirac_batch_prepare(self.h, self._steps_array(steps)))
+
+    def run_timed(self, steps):
+        """Run with per-launch events (synchronises).  Returns {(direction, n or
+        'multi'): (ms summed, launches, algorithmic bytes)} for the kernel classes
+        that ran."""
+        ms = (C.c_double * 18)()
+        cnt = (C.c_int64 * 18)()
+        byt = (C.c_double * 18)()
+        _check(lib.dirac_batch_run_timed(self.h, self._steps_array(steps), ms, cnt, byt))
+        out = {}
+        for c in range(18):
+            if cnt[c]:
+                d, k = divmod(c, 9)
+                out[(d, "multi" if k == 8 else 1 << (k + 4))] = (ms[c], int(cnt[c]), byt[c])
+        return out
 
     def sync(self):
         _check(lib.dirac_batch_sync(self.h))
