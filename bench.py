@@ -162,7 +162,7 @@ def batch_schedule_index(radix: int, cpt: int, n: int) -> int:
     return (0 if radix == default else 2) + (1 if cpt == 1 else 0)
 
 
-def bench_batch(D, W, precision, steps, warmup, timed_steps, count=256):
+def bench_batch(D, W, precision, steps, warmup, timed_steps, count=256, direct=False):
     """The batch workload: autotuned schedules, `warmup` untimed steps, the
     graph of the K-step run recorded and instantiated untimed, then the timed
     replay (HIP events on the batch stream).  A second pass of `timed_steps`
@@ -171,6 +171,8 @@ def bench_batch(D, W, precision, steps, warmup, timed_steps, count=256):
     import torch
     specs = W.batch_mix(count, 4000, BATCH_SIZES, steps)
     b = D.Batch(precision=precision, capacity=count)
+    if direct:
+        b.set_graph(False)          # one launch per phase kernel (counter passes)
     solvers = []
     for sp in specs:
         s = D.Solver.from_spec(sp, precision=precision, stream=b.stream)
@@ -222,7 +224,8 @@ def bench_batch(D, W, precision, steps, warmup, timed_steps, count=256):
                       "events on the batch stream (x and y phases in the order of a real run)",
             "kernels": classes, "phase_frac": phase,
             "step_frac": round(step_bytes * steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "step_timing": f"one HIP graph replay of {steps} steps (the timed region)"}
+            "step_timing": (f"direct launches of {steps} steps (the timed region)" if direct else
+                            f"one HIP graph replay of {steps} steps (the timed region)")}
     hist = {str(n): sum(1 for sp in specs if sp.n1 == n) for n in BATCH_SIZES}
     return {"value": pts * steps / (ms * 1e-3), "ms": ms, "ms_per_step": ms / steps, "dtype": "f64" if sz == 8 else "f32",
             "solves": count, "points": pts, "state_bytes": pts * 4 * sz, "grid_sizes": hist, "finite": fin,
@@ -401,6 +404,8 @@ def main():
     ap.add_argument("--variants", default=None,
                     help="comma-separated variant names to run (default: all)")
     ap.add_argument("--cpu-steps", type=int, default=250)
+    ap.add_argument("--batch-direct", action="store_true",
+                    help="run the batch with one launch per phase kernel instead of graph replay (counter passes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB three times (counter calibration)")
     args = ap.parse_args()
@@ -429,7 +434,7 @@ def main():
     K = args.steps
     timed = max(1, min(K, 50))
     progress(f"headline: batch of 256 curved solves, FP32, {K} steps")
-    hb = bench_batch(D, W, D.FP32, K, args.warmup, timed)
+    hb = bench_batch(D, W, D.FP32, K, args.warmup, timed, direct=args.batch_direct)
     out = {
         "metric": "grid-point*steps/s on 1 MI355X (FP32 vs FP64), % HBM peak; p50/p99 latency",
         "value": hb["value"],

@@ -15,7 +15,8 @@ counter-collection CSVs (KiB per dispatch) of a solve, and the same two
 counters for a plain 1 GiB device copy, scales each counter by
 (bytes the copy moves) / (what the counter reads for the copy), and writes the
 median HBM bytes per launch for every direction kernel, keyed by the names
-bench.py uses (e.g. ``y_stage_f64_512x512_curved``), plus a digest of the
+bench.py uses (e.g. ``y_stage_f64_512x512_curved``), and for every batch phase
+kernel, keyed by its instantiation (``batch_kernels``), plus a digest of the
 kernel sources so that stale numbers are not reported.
 """
 from __future__ import annotations
@@ -39,7 +40,8 @@ def kernel_sources_digest() -> str:
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1909_02894_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f in ("fft_line.hpp", "stage_kernels.hpp") or (f.startswith("stages_") and f.endswith(".hip")):
+        if f in ("fft_line.hpp", "stage_kernels.hpp", "batch_kernels.hpp") or \
+                (f.startswith(("stages_", "batch_f")) and f.endswith(".hip")):
             h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -112,6 +114,16 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, grid, out_json
         rec["bytes"] = rec["fetch_bytes"] + rec["write_bytes"]
         ent = out["kernels"].setdefault(name, {"by_instantiation": {}})
         ent["by_instantiation"][short_name(k)] = rec
+    # batch phase kernels, keyed by instantiation (one per direction, length and schedule)
+    out["batch_kernels"] = {}
+    for k in fe:
+        sk = short_name(k)
+        if not sk.startswith(("batch_group_kernel", "batch_multi_kernel")) or k not in wr:
+            continue
+        rec = {"fetch_bytes": round(statistics.median(fe[k]) * f_scale),
+               "write_bytes": round(statistics.median(wr[k]) * w_scale), "dispatches": len(fe[k])}
+        rec["bytes"] = rec["fetch_bytes"] + rec["write_bytes"]
+        out["batch_kernels"][sk] = rec
     for name, ent in out["kernels"].items():
         top = max(ent["by_instantiation"].items(), key=lambda kv: kv[1]["dispatches"])
         ent.update(top[1])

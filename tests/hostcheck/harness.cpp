@@ -96,8 +96,15 @@ static void batch_bench(int count, int prec) {
     }
     OK(dirac_batch_autotune(b, 2));
     std::vector<int64_t> steps(count, 30);
-    OK(dirac_batch_run(b, steps.data()));
+    OK(dirac_batch_prepare(b, steps.data()));
+    OK(dirac_batch_run(b, steps.data()));       // replays the prepared graph
     OK(dirac_batch_run(b, steps.data()));       // graph reuse
+    {
+        double ms[18], byt[18];
+        int64_t cnt[18];
+        OK(dirac_batch_run_timed(b, steps.data(), ms, cnt, byt));
+    }
+    OK(dirac_batch_run(b, steps.data()));       // graph rebuilt after the timed run
     OK(dirac_batch_sync(b));
     OK(dirac_batch_set_graph(b, 0));
     OK(dirac_batch_run(b, steps.data()));
