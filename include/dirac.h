@@ -247,6 +247,17 @@ dirac_status dirac_step_n(dirac_solver* s, int64_t nsteps);
  * stream.  DIRAC_E_STATE before an initial spinor. */
 dirac_status dirac_observables(dirac_solver* s, dirac_obs* out);
 
+/* Allocation-free observables, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same results as dirac_observables, bit for bit, but the
+ * reduction partials and sums live in a static device array of the library
+ * (1 MiB per GPU, held until the process ends; room for the 2 x 8192 workgroups
+ * of the largest grid, DIRAC_E_SIZE beyond it) instead of the solver's buffer.
+ * It calls no allocating routine.  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (solvers on different streams, or threads)
+ * race and must be serialised by the caller.  Synchronises the solver's stream. */
+dirac_status dirac_observables_static(dirac_solver* s, dirac_obs* out);
+
 /* Copy the state psi^n at the grid points of Sec. 5 to host memory
  * (caller-owned, 4 n1 n2 doubles) as complex128 [n2][n1][2] (FP32 states are
  * widened exactly).  Synchronises. */

@@ -696,7 +696,16 @@ dirac_status dirac_step_n(dirac_solver* s, int64_t nsteps) {
     return DIRAC_OK;
 }
 
-dirac_status dirac_observables(dirac_solver* s, dirac_obs* out) {
+}  // extern "C"
+
+namespace dirac {
+
+// Observables with the reduction partials (8 doubles per workgroup of the two
+// derivative passes) at `parts` and the 8 reduced sums at `dout`: the solver's
+// own buffer, or the library's static scratch array.  max_parts bounds the
+// workgroup count (DIRAC_E_SIZE beyond it, before anything is launched).
+static dirac_status observables_into(dirac_solver* s, dirac_obs* out, double* parts, double* dout,
+                                     size_t max_parts) {
     if (!s || !out) return fail(DIRAC_E_ARG, "null solver or output");
     if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
     const size_t N = (size_t)s->g.n1 * s->g.n2;
@@ -714,7 +723,15 @@ dirac_status dirac_observables(dirac_solver* s, dirac_obs* out) {
     p.n1 = s->g.n1; p.n2 = s->g.n2;
     p.a1 = s->g.a1; p.a2 = s->g.a2;
     p.h1 = 2.0 * s->g.a1 / s->g.n1; p.h2 = 2.0 * s->g.a2 / s->g.n2;
-    double* parts = reinterpret_cast<double*>(b + s->lay.partials);
+    size_t need = 0;
+    for (int dir = 0; dir < 2; ++dir) {
+        const KernelEntry* e = obs_entry(s->prec, dir == 0 ? s->g.n1 : s->g.n2, dir);
+        const int nl = dir == 0 ? s->g.n2 : s->g.n1;
+        need += (size_t)((nl + e->lines - 1) / e->lines);
+    }
+    if (need > max_parts)
+        return fail(DIRAC_E_SIZE, "observables need %zu reduction partials, more than the %zu available", need,
+                    max_parts);
     int nparts = 0;
     for (int dir = 0; dir < 2; ++dir) {
         const KernelEntry* e = obs_entry(s->prec, dir == 0 ? s->g.n1 : s->g.n2, dir);
@@ -727,7 +744,6 @@ dirac_status dirac_observables(dirac_solver* s, dirac_obs* out) {
         HIP_TRY(hipLaunchKernel(e->obs_fn, dim3(nb), dim3(e->nthreads), args, 0, s->stream), "launch observables");
         nparts += nb;
     }
-    double* dout = reinterpret_cast<double*>(b + s->lay.out);
     HIP_TRY(launch_reduce_partials(parts, nparts, dout, s->stream), "reduce observables");
     double h[8];
     HIP_TRY(hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s->stream), "read observables");
@@ -744,6 +760,57 @@ dirac_status dirac_observables(dirac_solver* s, dirac_obs* out) {
     out->finite = h[6] == 0.0 && std::isfinite(h[0]);
     out->reserved = 0;
     return DIRAC_OK;
+}
+
+// Static scratch of the allocation-free observables: the reduction partials of
+// at most kObsStaticParts workgroups (one per line of each direction at the
+// largest grid, 8192 x 8192) followed by the 8 reduced sums, 1 MiB in all.
+// Every GPU the library runs on holds its own copy until the process ends.  In
+// host code the array's name is not a device address: kernels and copies use
+// the address hipGetSymbolAddress returns for the device, kept per device.
+constexpr size_t kObsStaticParts = 2 * 8192;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[(kObsStaticParts + 1) * 8];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up once per device with
+// that device current.
+static dirac_status static_scratch(int device, double** out) {
+    if (device < 0 || device >= kMaxDevices) return fail(DIRAC_E_DEVICE, "device index %d out of range", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        HIP_TRY(hipGetDevice(&cur), "hipGetDevice");
+        if (cur != device) HIP_TRY(hipSetDevice(device), "hipSetDevice");
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(DIRAC_E_DEVICE, "hipGetSymbolAddress(scratch) returned null");
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return DIRAC_OK;
+}
+
+}  // namespace dirac
+
+extern "C" {
+
+dirac_status dirac_observables(dirac_solver* s, dirac_obs* out) {
+    if (!s) return fail(DIRAC_E_ARG, "null solver or output");
+    char* b = s->base;
+    return observables_into(s, out, reinterpret_cast<double*>(b + s->lay.partials),
+                            reinterpret_cast<double*>(b + s->lay.out), SIZE_MAX);
+}
+
+dirac_status dirac_observables_static(dirac_solver* s, dirac_obs* out) {
+    if (!s || !out) return fail(DIRAC_E_ARG, "null solver or output");
+    double* sc = nullptr;
+    dirac_status r = static_scratch(s->device, &sc);
+    if (r != DIRAC_OK) return r;
+    return observables_into(s, out, sc, sc + kObsStaticParts * 8, kObsStaticParts);
 }
 
 dirac_status dirac_get_spinor(dirac_solver* s, double* psi_host_out) {

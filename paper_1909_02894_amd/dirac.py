@@ -117,6 +117,7 @@ SIGNATURES = {
     "dirac_set_initial_spinor_device": (C.c_int32, [_vp, _vp]),
     "dirac_step_n": (C.c_int32, [_vp, C.c_int64]),
     "dirac_observables": (C.c_int32, [_vp, C.POINTER(Obs)]),
+    "dirac_observables_static": (C.c_int32, [_vp, C.POINTER(Obs)]),
     "dirac_get_spinor": (C.c_int32, [_vp, _dp]),
     "dirac_destroy": (C.c_int32, [_vp]),
     "dirac_last_error": (C.c_char_p, []),
@@ -288,6 +289,14 @@ def step_n(h, nsteps: int):
 def observables(h) -> dict:
     o = Obs()
     _check(lib.dirac_observables(h, C.byref(o)))
+    return o.as_dict()
+
+
+def observables_static(h) -> dict:
+    """dirac_observables_static: the same values, reduced in the library's static
+    device scratch (no allocation)."""
+    o = Obs()
+    _check(lib.dirac_observables_static(h, C.byref(o)))
     return o.as_dict()
 
 

@@ -30,6 +30,7 @@ static void solve2d(int n, int prec, int kind, int pml, int scheme, bool em, int
     OK(dirac_step_n(s, steps));
     dirac_obs o{};
     OK(dirac_observables(s, &o));
+    OK(dirac_observables_static(s, &o));
     if (scheme != DIRAC_SCHEME_CN_GMRES) {
         double ms[2]; int64_t c[2];
         OK(dirac_step_n_timed(s, 50, ms, c));

@@ -21,6 +21,12 @@ hipError_t hipHostMalloc(void** p, size_t n, unsigned int) { *p = std::calloc(1,
 hipError_t hipHostFree(void* p) { std::free(p); return hipSuccess; }
 hipError_t hipPointerGetAttributes(hipPointerAttribute_t* a, const void*) { std::memset(a, 0, sizeof *a); a->type = hipMemoryTypeDevice; return hipSuccess; }
 hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+hipError_t hipSetDevice(int d) { if (d != 0) die("set device", nullptr); return hipSuccess; }
+// the library's static device arrays: one host block stands in for each symbol
+hipError_t hipGetSymbolAddress(void** p, const void* sym) {
+    static std::vector<char> block(2u << 20);
+    if (!sym) die("null symbol", nullptr);
+    *p = block.data(); return hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t* e) { std::lock_guard<std::mutex> l(mu); *e = (hipEvent_t) new int(1); live_events.insert(*e); return hipSuccess; }
 hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { return hipEventCreate(e); }
 hipError_t hipEventDestroy(hipEvent_t e) { std::lock_guard<std::mutex> l(mu); if (!live_events.erase(e)) die("event destroy", e); delete (int*)e; return hipSuccess; }
@@ -53,6 +59,7 @@ const char* hipGetErrorString(hipError_t) { return "stub"; }
 void** __hipRegisterFatBinary(const void*) { static void* h = nullptr; return &h; }
 void __hipRegisterFunction(void**, const void*, char*, const char*, unsigned int, void*, void*, void*, void*, int*) {}
 void __hipUnregisterFatBinary(void**) {}
+void __hipRegisterVar(void**, void*, char*, const char*, int, size_t, int, int) {}
 hipError_t __hipPushCallConfiguration(dim3, dim3, size_t, hipStream_t) { return hipSuccess; }
 hipError_t __hipPopCallConfiguration(dim3* g, dim3* b, size_t* s, hipStream_t* st) { *g = dim3(1); *b = dim3(1); *s = 0; *st = nullptr; return hipSuccess; }
 }
