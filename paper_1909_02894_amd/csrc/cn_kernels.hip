@@ -1,11 +1,21 @@
 // cn_kernels.hip -- Numerical Scheme I (Sec. 5.1): the Crank-Nicolson transport
-// step G psi* = G~ psi^{n+1/2}, G = I + (dt/2) alpha(x).T, G~ = I - (dt/2) alpha(x).T,
-// solved with restarted GMRES whose matrix-vector product runs on the same line
-// transforms as the direction kernels (FP64).
+// step G psi* = G~ psi^{n+1/2}, G = I + (dt/2) A, G~ = I - (dt/2) A with
+// A psi = alpha(x).T psi = c (b_x sigma_x [[d_x]] psi + b_y sigma_y [[d_y]] psi)
+// (spectral derivative of eq. (trick), b_i = a / S^i: Appendix A with layers),
+// solved by restarted GMRES (FP64).
 //
-// alpha(x).T psi = c (b_x sigma_x [[d_x]] psi + b_y sigma_y [[d_y]] psi), with the
-// spectral derivative of eq. (trick) and b_i = a / S^i (Appendix A, with layers).
+// The Krylov space of G is that of A, so the Arnoldi process runs on A: A v is
+// far from parallel to v (A is close to skew-adjoint), so one classical
+// Gram-Schmidt pass does not cancel and keeps the basis orthonormal to rounding
+// over a cycle (on G = I + (dt/2) A almost all of G v lies along v and one pass
+// loses orthogonality completely).  The Hessenberg matrix of G is
+// I + (dt/2) H_A.  Each reduction ends in one workgroup that sums the
+// per-workgroup partials in a fixed order (bitwise reproducible) and updates the
+// device-resident least-squares state (Givens rotations), so a whole GMRES cycle
+// needs no host round trip.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "cn_kernels.hpp"
 #include "stage_kernels.hpp"
@@ -21,31 +31,50 @@ __host__ __device__ constexpr int cn_lines(int n, bool cols) {
                                          : (cols && 64 / (n / cn_radix(n, cols)) < 2 ? 2 : 64 / (n / cn_radix(n, cols)));
 }
 
-// out = in + s h c b_x sigma_x [[d_x]] in          (x pass, rows)
-// out = out + s h c b_y sigma_y [[d_y]] in         (y pass, columns)
-template <int N, bool COLS>
-__global__ void __launch_bounds__((N / cn_radix(N, COLS)) * cn_lines(N, COLS)) cn_apply_kernel(CnApplyParams p) {
+// Radix and lines per workgroup of both directions in the merged kernel: the
+// column rule, one workgroup shape (radix 4 with one line per workgroup at 512
+// points, twice the waves, measured 15% slower).
+__host__ __device__ constexpr int cn2_radix(int n) { return cn_radix(n, true); }
+__host__ __device__ constexpr int cn2_lines(int n) { return cn_lines(n, true); }
+
+// Tile shape of a pass: the row or column rule, or (M2) the merged kernel's.
+template <int N, bool COLS, bool M2 = false>
+struct CnTile {
+    static constexpr int R = M2 ? cn2_radix(N) : cn_radix(N, COLS), L = M2 ? cn2_lines(N) : cn_lines(N, COLS);
+    using F = LineFFT<double, N, R, L, COLS, 2>;
+    static constexpr int NT = F::NT;
+    static constexpr int LDS = F::LDS_ELEMS;
+    static constexpr int TW = TwStage<double, N>::ELEMS;
+};
+
+// One tile of one direction of the transport operator (see CnApplyParams);
+// lds / twl: the workgroup's exchange buffer and twiddle stage.
+template <int N, bool COLS, bool M2 = false>
+__device__ __forceinline__ void cn_apply_tile(const CnApplyParams& p, int tile, cpx<double>* lds, cpx<double>* twl) {
     using T = double;
-    constexpr int R = cn_radix(N, COLS), L = cn_lines(N, COLS);
+    constexpr int R = CnTile<N, COLS, M2>::R, L = CnTile<N, COLS, M2>::L;
     using F = LineFFT<T, N, R, L, COLS, 2>;
     using TS = TwStage<T, N>;
     constexpr int P = F::P;
-    __shared__ cpx<T> lds[F::LDS_ELEMS];
-    __shared__ cpx<T> twl[TS::ELEMS];
     const typename F::Coord c = F::coord(threadIdx.x);
-    const int line = xcd_tile(blockIdx.x, gridDim.x) * L + c.l;
+    const int line = tile * L + c.l;
     const bool valid = line < p.nlines;
     const int lline = valid ? line : p.nlines - 1;     // loads: clamped, branch-free
     const uint32_t n1 = (uint32_t)p.n1;
     auto gidx = [&](int ln, int pos) -> uint32_t {
         return COLS ? (uint32_t)pos * n1 + ln : (uint32_t)ln * n1 + pos;
     };
-    // every global load goes out before the first wait: the vector, twiddles,
-    // derivative symbol, blend factors and (y pass) the x pass's output
-    cpx<T> v[2][R], in[2][R], o[2][R];
+    // every global load goes out before the first wait
+    cpx<T> v[2][R], bq[COLS ? 1 : 2][COLS ? 1 : R];
     T d[R], bf[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) load_point(p.in, gidx(lline, c.j + r * P), v[0][r], v[1][r]);
+    if constexpr (!COLS) {
+        if (p.base == 2) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) load_point(p.b, gidx(lline, c.j + r * P), bq[0][r], bq[1][r]);
+        }
+    }
     const cpx<T>* tw = p.tw;
     cpx<T> twv[TS::ON ? F::TW_ITER : 1];
     if constexpr (TS::ON) F::tw_load(twv, p.tw, threadIdx.x);
@@ -58,18 +87,33 @@ __global__ void __launch_bounds__((N / cn_radix(N, COLS)) * cn_lines(N, COLS)) c
 #pragma unroll
         for (int r = 0; r < R; ++r) bf[r] = ld_at(p.a, gidx(lline, c.j + r * P)) * bf[r];
     }
-    if constexpr (COLS) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) load_point(p.out, gidx(lline, c.j + r * P), o[0][r], o[1][r]);
+    T inv = 1.0;
+    if (p.in_norm) {
+        const T nv = p.in_norm[0];
+        inv = nv > 0.0 ? 1.0 / nv : 0.0;
     }
     if constexpr (TS::ON) {
         F::tw_store(twv, twl, threadIdx.x);
         tw = twl;
     }
+    if (p.in_norm) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        in[0][r] = v[0][r];
-        in[1][r] = v[1][r];
+        for (int r = 0; r < R; ++r) {
+            v[0][r] = scal(inv, v[0][r]);
+            v[1][r] = scal(inv, v[1][r]);
+        }
+    }
+    cpx<T> in[COLS ? 1 : 2][COLS ? 1 : R];
+    if constexpr (!COLS) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            in[0][r] = v[0][r];
+            in[1][r] = v[1][r];
+        }
+        if (p.vout && valid) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) store_point(p.vout, gidx(line, c.j + r * P), v[0][r], v[1][r]);
+        }
     }
     F::template fft<false, TS::ON>(v, lds, c, tw);
 #pragma unroll
@@ -82,8 +126,8 @@ __global__ void __launch_bounds__((N / cn_radix(N, COLS)) * cn_lines(N, COLS)) c
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t q = gidx(line, c.j + r * P);
-        const T f = p.scale * bf[r];               // s (dt/2) c b
-        cpx<T> t0, t1;                             // sigma_i [[d_i]] psi
+        const T f = p.scale * bf[r];               // f c b
+        cpx<T> t0, t1;                             // sigma_i [[d_i]] v
         if constexpr (!COLS) {
             t0 = v[1][r];
             t1 = v[0][r];
@@ -91,16 +135,46 @@ __global__ void __launch_bounds__((N / cn_radix(N, COLS)) * cn_lines(N, COLS)) c
             t0 = mul_mi(v[1][r]);
             t1 = mul_i(v[0][r]);
         }
-        cpx<T> o0, o1;
+        cpx<T> o0 = scal(f, t0), o1 = scal(f, t1);
         if constexpr (!COLS) {
-            o0 = in[0][r];
-            o1 = in[1][r];
-        } else {
-            o0 = o[0][r];
-            o1 = o[1][r];
+            if (p.base == 1) {
+                o0 = in[0][r] + o0;
+                o1 = in[1][r] + o1;
+            } else if (p.base == 2) {
+                o0 = (bq[0][r] - in[0][r]) + o0;
+                o1 = (bq[1][r] - in[1][r]) + o1;
+            }
         }
-        store_point(p.out, q, o0 + scal(f, t0), o1 + scal(f, t1));
+        store_point(p.out, q, o0, o1);
     }
+}
+
+// One direction of the transport operator.
+template <int N, bool COLS>
+__global__ void __launch_bounds__((CnTile<N, COLS>::NT)) cn_apply_kernel(CnApplyParams p) {
+    if (p.gate && p.gate[0] == 0) return;
+    __shared__ cpx<double> lds[CnTile<N, COLS>::LDS];
+    __shared__ cpx<double> twl[CnTile<N, COLS>::TW];
+    cn_apply_tile<N, COLS>(p, xcd_tile(blockIdx.x, gridDim.x), lds, twl);
+}
+
+// Both directions of a square grid in one launch: the first ntx tiles of the
+// (XCD-aware) tile order are row tiles, the rest column tiles, with one
+// workgroup shape (cn2_radix, cn2_lines).  The two write separate outputs, so
+// they run side by side.
+template <int N>
+__global__ void __launch_bounds__((CnTile<N, true, true>::NT)) cn_apply2_kernel(CnApplyParams px, CnApplyParams py,
+                                                                                int ntx) {
+    using TX = CnTile<N, false, true>;
+    using TY = CnTile<N, true, true>;
+    static_assert(TX::NT == TY::NT, "row and column tiles need the same workgroup");
+    if (px.gate && px.gate[0] == 0) return;
+    constexpr int LDS = TX::LDS > TY::LDS ? TX::LDS : TY::LDS;
+    __shared__ cpx<double> lds[LDS];
+    __shared__ cpx<double> twl[TY::TW];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    if (t < ntx) cn_apply_tile<N, false, true>(px, t, lds, twl);
+    else cn_apply_tile<N, true, true>(py, t - ntx, lds, twl);
 }
 
 // psi <- E psi (times = 1 or 2), E = [[e0, e1], [conj e1, conj e0]] per point, or the
@@ -120,11 +194,17 @@ __global__ void cn_exp_kernel(double* psi, const double* E, double2 e0u, size_t 
     store_point(psi, (uint32_t)i, u, v);
 }
 
-// Fixed-order workgroup sum of NS complex values per thread (a 64-lane butterfly,
-// then the four waves in order); slot k of the result goes to out[2k], out[2k+1].
+// ------------------------------------------------------------ reductions
+
+constexpr int kCnThreads = 256;
+constexpr int kCnSlots = kCnMaxRestart + 2;      // partial slots per workgroup (complex)
+static_assert(kCnDotBlocks % 32 == 0, "the final sums take 32 workgroups per lane");
+
+// Fixed-order workgroup sum of NS complex values per thread: a 64-lane
+// butterfly, then the four waves in order; slot s0 + k of this workgroup's
+// partials receives value k.
 template <int NS>
-__device__ __forceinline__ void block_sum_store(double (&ar)[NS], double (&ai)[NS], double* out) {
-    static_assert(NS >= 1 && NS <= 9, "slots per launch");
+__device__ __forceinline__ void store_partials(double (&ar)[NS], double (&ai)[NS], double* partials, int s0) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
@@ -145,90 +225,299 @@ __device__ __forceinline__ void block_sum_store(double (&ar)[NS], double (&ai)[N
     __syncthreads();
     if ((int)threadIdx.x < NS) {
         const int k = threadIdx.x;
-        out[2 * k] = ((sr[k][0] + sr[k][1]) + sr[k][2]) + sr[k][3];
-        out[2 * k + 1] = ((si[k][0] + si[k][1]) + si[k][2]) + si[k][3];
+        double* o = partials + 2 * ((size_t)blockIdx.x * kCnSlots + s0 + k);
+        o[0] = ((sr[k][0] + sr[k][1]) + sr[k][2]) + sr[k][3];
+        o[1] = ((si[k][0] + si[k][1]) + si[k][2]) + si[k][3];
     }
 }
 
-// Partial sums of <V_k, w> = sum_i conj(V_k[i]) w[i] for the NK vectors k0 .. k0+NK-1
-// and, with SELF, of ||w||^2 (slot k0+NK, real) over a grid-stride range of complex
-// elements: partials[block][slot] (complex), fixed order.  All loads of an element
-// are issued together.
-template <int NK, bool SELF>
-__global__ void __launch_bounds__(256) cn_dots_kernel(const double* V, size_t vstride, int k0, const double* w,
-                                                      size_t ncplx, double* partials, int ldp) {
-    constexpr int NS = NK + (SELF ? 1 : 0);
-    double ar[NS], ai[NS];
+// out[s] = sum over the kCnDotBlocks workgroups' partial slot s (complex),
+// s < nslots, by one workgroup into shared memory: 32 lanes per slot each load
+// the partials of workgroups lane, lane + 32, ... at once and add them in that
+// order, then a fixed 32-lane butterfly (bitwise reproducible).
+__device__ void final_sums(const double* partials, int nslots, double* out) {
+    constexpr int PER = kCnDotBlocks / 32;
+    const int lane = threadIdx.x & 31;
+    for (int s0 = 0; s0 < nslots; s0 += kCnThreads / 32) {
+        const int sl = s0 + (int)(threadIdx.x >> 5);
+        double r = 0.0, i = 0.0;
+        if (sl < nslots) {
+            double2 v[PER];
 #pragma unroll
-    for (int k = 0; k < NS; ++k) ar[k] = ai[k] = 0.0;
-    const double2* W = reinterpret_cast<const double2*>(w);
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
-        const double2 x = W[i];
-        double2 y[NK > 0 ? NK : 1];
+            for (int q = 0; q < PER; ++q)
+                v[q] = *reinterpret_cast<const double2*>(partials + 2 * ((size_t)(lane + 32 * q) * kCnSlots + sl));
 #pragma unroll
-        for (int k = 0; k < NK; ++k) y[k] = reinterpret_cast<const double2*>(V + (size_t)(k0 + k) * vstride)[i];
-#pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            ar[k] += y[k].x * x.x + y[k].y * x.y;
-            ai[k] += y[k].x * x.y - y[k].y * x.x;
+            for (int q = 0; q < PER; ++q) {
+                r += v[q].x;
+                i += v[q].y;
+            }
         }
-        if constexpr (SELF) ar[NK] += x.x * x.x + x.y * x.y;
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) {
+            r += __shfl_xor(r, off, 32);
+            i += __shfl_xor(i, off, 32);
+        }
+        if (lane == 0 && sl < nslots) {
+            out[2 * sl] = r;
+            out[2 * sl + 1] = i;
+        }
     }
-    block_sum_store<NS>(ar, ai, partials + 2 * ((size_t)blockIdx.x * ldp + k0));
+    __syncthreads();
 }
 
-// The first Gram-Schmidt update fused with the second pass's dots:
-// w <- w - sum_{k<NK} coef_k V_k in place, and partial sums of <V_k, w> (slots 0..NK-1)
-// and ||w||^2 (slot NK) of the updated w, as cn_dots_kernel writes them.
-template <int NK>
-__global__ void __launch_bounds__(256) cn_axpy_dots_kernel(const double* V, size_t vstride, const double* coef,
-                                                           double* w, size_t ncplx, double* partials, int ldp) {
-    constexpr int NS = NK + 1;
-    double ar[NS], ai[NS];
+// Complex arithmetic of the least-squares state.
+struct zc { double re, im; };
+__device__ __forceinline__ zc zmul(zc a, zc b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ zc zconj(zc a) { return {a.re, -a.im}; }
+__device__ __forceinline__ zc zadd(zc a, zc b) { return {a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ zc zsub(zc a, zc b) { return {a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ zc zscal(double s, zc a) { return {s * a.re, s * a.im}; }
+__device__ __forceinline__ double zabs(zc a) { return hypot(a.re, a.im); }
+__device__ __forceinline__ zc zdiv(zc a, zc b) {
+    const double d = b.re * b.re + b.im * b.im;
+    return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// Givens update of column j of the cycle's least-squares problem, by the whole
+// last workgroup (the state is staged in shared memory, thread 0 computes).
+// h: H_A(0..j, j) (complex, shared memory), hn: the norm of the new Arnoldi
+// vector.  Column j of H_G = I + (dt/2) H_A is rotated by the earlier
+// rotations, a new rotation zeroes its subdiagonal (dt/2) hn, and g, k, the
+// iteration count and the end-of-cycle flag are updated.
+__device__ void givens_column(CnCtrl* c, int j, const double* h, double hn) {
+    constexpr int M1 = kCnMaxRestart + 1;
+    __shared__ double cs[M1], sn[2 * M1], col[2 * M1];
+    __shared__ int skip;
+    if (threadIdx.x == 0) skip = c->done;
+    __syncthreads();
+    if (skip) return;                              // the cycle has already ended
+    const double hd = c->hdt;
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        cs[i] = c->cs[i];
+        sn[2 * i] = c->sn[2 * i];
+        sn[2 * i + 1] = c->sn[2 * i + 1];
+        col[2 * i] = hd * h[2 * i] + (i == j ? 1.0 : 0.0);
+        col[2 * i + 1] = hd * h[2 * i + 1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (!isfinite(hn)) {
+            c->nonfinite = 1;
+            c->done = 1;
+        } else {
+            const double sub = hd * hn;
+            for (int i = 0; i < j; ++i) {
+                const zc a{col[2 * i], col[2 * i + 1]}, b{col[2 * i + 2], col[2 * i + 3]};
+                const zc r{sn[2 * i], sn[2 * i + 1]};
+                const zc na = zadd(zscal(cs[i], a), zmul(r, b));
+                const zc nb = zadd(zscal(-1.0, zmul(zconj(r), a)), zscal(cs[i], b));
+                col[2 * i] = na.re; col[2 * i + 1] = na.im;
+                col[2 * i + 2] = nb.re; col[2 * i + 3] = nb.im;
+            }
+            const zc a{col[2 * j], col[2 * j + 1]};
+            const double aa = zabs(a), rr = hypot(aa, sub);
+            double cj;
+            zc sj;
+            if (aa == 0.0) {
+                cj = 0.0;
+                sj = {1.0, 0.0};
+            } else {
+                cj = aa / rr;
+                sj = zscal(sub / rr, zscal(1.0 / aa, a));
+            }
+            const zc d = zadd(zscal(cj, a), zscal(sub, sj));
+            col[2 * j] = d.re; col[2 * j + 1] = d.im;
+            c->cs[j] = cj;
+            c->sn[2 * j] = sj.re; c->sn[2 * j + 1] = sj.im;
+            const zc gj{c->g[2 * j], c->g[2 * j + 1]};
+            const zc g1 = zscal(-1.0, zmul(zconj(sj), gj));
+            c->g[2 * j + 2] = g1.re; c->g[2 * j + 3] = g1.im;
+            c->g[2 * j] = cj * gj.re; c->g[2 * j + 1] = cj * gj.im;
+            c->k = j + 1;
+            c->used += 1;
+            const double est = zabs(g1);
+            if (sub == 0.0 || est <= c->tol || c->used >= c->max_iter || j + 1 >= c->m) c->done = 1;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        c->R[2 * ((size_t)j * M1 + i)] = col[2 * i];
+        c->R[2 * ((size_t)j * M1 + i) + 1] = col[2 * i + 1];
+    }
+}
+
+// A new cycle from the residual of norm beta (thread 0).
+__device__ void start_cycle(CnCtrl* c, double beta) {
+    c->beta = beta;
+    c->k = 0;
+    c->done = 0;
+    c->state = 0;
+    c->g[0] = beta;
+    c->g[1] = 0.0;
+}
+
+// Solver constants for the calls that follow; clears the ticket and the flags.
+__global__ void cn_init_kernel(CnCtrl* c, double hdt, double rtol, int max_iter, int m) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c->hdt = hdt;
+        c->rtol = rtol;
+        c->max_iter = max_iter;
+        c->m = m;
+        c->ticket = 0u;
+        c->nonfinite = 0;
+        c->done = 0;
+        c->state = 0;
+        c->k = 0;
+    }
+}
+
+// rhs <- rx + ry, x <- 2 rhs - x (the first-order predictor of the solution,
+// psi - dt A psi), ||rhs||; the step's counters are reset.
+__global__ void __launch_bounds__(kCnThreads) cn_rhs_kernel(const double* rx, const double* ry, double* rhs,
+                                                             double* x, size_t ncplx, double* partials) {
+    double ar[1] = {0.0}, ai[1] = {0.0};
+    const double2* RX = reinterpret_cast<const double2*>(rx);
+    const double2* RY = reinterpret_cast<const double2*>(ry);
+    double2* B = reinterpret_cast<double2*>(rhs);
+    double2* X = reinterpret_cast<double2*>(x);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
+        const double2 a = RX[i], b = RY[i], h = X[i];
+        const double2 r = {a.x + b.x, a.y + b.y};
+        B[i] = r;
+        X[i] = make_double2(2.0 * r.x - h.x, 2.0 * r.y - h.y);
+        ar[0] += r.x * r.x + r.y * r.y;
+    }
+    store_partials<1>(ar, ai, partials, 0);
+}
+
+// r <- rx + ry (in ry) and ||r||^2; see launch_cn_residual.
+template <bool START>
+__global__ void __launch_bounds__(kCnThreads) cn_residual_kernel(const double* rx, double* ry, size_t ncplx,
+                                                                  double* partials, const CnCtrl* c) {
+    if (!START && c->done == 0) return;
+    double ar[1] = {0.0}, ai[1] = {0.0};
+    const double2* RX = reinterpret_cast<const double2*>(rx);
+    double2* RY = reinterpret_cast<double2*>(ry);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
+        const double2 a = RX[i], b = RY[i];
+        const double2 r = {a.x + b.x, a.y + b.y};
+        RY[i] = r;
+        ar[0] += r.x * r.x + r.y * r.y;
+    }
+    store_partials<1>(ar, ai, partials, 0);
+}
+
+// First Gram-Schmidt pass of Arnoldi iteration j, basis vectors k0 .. k0+NK-1 of
+// this launch: dots with w (FIRST: w = wx + wy is formed and stored to wx, and
+// ||w||^2 goes to slot j + 1).  The last workgroup of the last launch stores the
+// coefficients and decides: a second pass, or the Givens update of column j.
+template <int NK, bool FIRST>
+__global__ void __launch_bounds__(kCnThreads) cn_gs1_kernel(const double* V, size_t vstride, int k0, int j,
+                                                             double* wx, const double* wy, size_t ncplx,
+                                                             double* partials) {
+    double ar[NK], ai[NK], nr[1] = {0.0}, ni[1] = {0.0};
 #pragma unroll
-    for (int k = 0; k < NS; ++k) ar[k] = ai[k] = 0.0;
-    double2* W = reinterpret_cast<double2*>(w);
+    for (int k = 0; k < NK; ++k) ar[k] = ai[k] = 0.0;
+    double2* W = reinterpret_cast<double2*>(wx);
+    const double2* WY = reinterpret_cast<const double2*>(wy);
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
         double2 x = W[i];
         double2 y[NK];
 #pragma unroll
-        for (int k = 0; k < NK; ++k) y[k] = reinterpret_cast<const double2*>(V + (size_t)k * vstride)[i];
-#pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            const double cr = coef[2 * k], ci = coef[2 * k + 1];
-            x.x -= cr * y[k].x - ci * y[k].y;
-            x.y -= cr * y[k].y + ci * y[k].x;
+        for (int k = 0; k < NK; ++k) y[k] = reinterpret_cast<const double2*>(V + (size_t)(k0 + k) * vstride)[i];
+        if constexpr (FIRST) {
+            if (WY) {
+                const double2 b = WY[i];
+                x.x += b.x;
+                x.y += b.y;
+                W[i] = x;
+            }
         }
-        W[i] = x;
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             ar[k] += y[k].x * x.x + y[k].y * x.y;
             ai[k] += y[k].x * x.y - y[k].y * x.x;
         }
-        ar[NK] += x.x * x.x + x.y * x.y;
+        if constexpr (FIRST) nr[0] += x.x * x.x + x.y * x.y;
     }
-    block_sum_store<NS>(ar, ai, partials + 2 * (size_t)blockIdx.x * ldp);
+    store_partials<NK>(ar, ai, partials, k0);
+    if constexpr (FIRST) {
+        __syncthreads();
+        store_partials<1>(nr, ni, partials, j + 1);
+    }
 }
 
-// out <- alpha (w - sign sum_{k<nk} coef_k V_k), nk = 8 nfull + NKR, coef complex on the
-// device (out may be w).  alpha = 1, or with NORM the reciprocal norm of the result:
-// coef[nk] holds ||w||^2 and the V_k are orthonormal, so the result's squared norm is
-// ||w||^2 - sum |coef_k|^2 (clamped at 0; alpha = 0 then); block 0 stores it to norm_out.
-template <int NKR, bool NORM>
-__global__ void __launch_bounds__(256) cn_axpy_kernel(const double* V, size_t vstride, int nfull, const double* coef,
-                                                      const double* w, double* out, size_t ncplx, double sign,
-                                                      double* norm_out) {
-    double alpha = 1.0;
-    if constexpr (NORM) {
-        const int nk = 8 * nfull + NKR;
-        double n2 = coef[2 * nk];
-        for (int k = 0; k < nk; ++k) n2 -= coef[2 * k] * coef[2 * k] + coef[2 * k + 1] * coef[2 * k + 1];
-        n2 = n2 > 0.0 ? n2 : 0.0;
-        alpha = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
-        if (blockIdx.x == 0 && threadIdx.x == 0) norm_out[0] = n2;
+// What the finishing workgroup does with the final sums of a reduction.
+enum CnFinish { kFinRhs = 0, kFinResStart = 1, kFinRes = 2, kFinGs = 3 };
+
+// One workgroup after each reduction kernel: the final sums of its partials,
+// then the solve-state update of `kind` (thread 0) and, after the Gram-Schmidt
+// dots of an Arnoldi iteration, the Givens update of column j.
+__global__ void __launch_bounds__(kCnThreads) cn_finish_kernel(const double* partials, int nslots, int kind, int j,
+                                                                double* rec, CnCtrl* c) {
+    if (kind == kFinRes && c->done == 0) return;
+    __shared__ double s[2 * kCnSlots];
+    __shared__ double h[2 * (kCnMaxRestart + 1)];
+    __shared__ double hn_s;
+    __shared__ int rotate;
+    final_sums(partials, nslots, s);
+    if (threadIdx.x == 0) {
+        rotate = 0;
+        if (kind == kFinRhs) {
+            c->bnorm = sqrt(s[0]);
+            c->tol = c->rtol * c->bnorm;
+            c->used = 0;
+            c->k = 0;
+            c->nonfinite = isfinite(s[0]) ? 0 : 1;
+        } else if (kind == kFinResStart || kind == kFinRes) {
+            const double r2 = s[0];
+            c->res2 = r2;
+            if (!isfinite(r2) || c->nonfinite) {
+                c->nonfinite = 1;
+                c->done = 1;
+                c->state = 3;
+            } else if (sqrt(r2) <= c->tol) {
+                c->done = 1;
+                if (kind == kFinResStart) c->k = 0;   // no column: the update leaves x as it is
+                c->state = 2;
+            } else if (kind == kFinRes && c->used >= c->max_iter) {
+                c->state = 3;
+            } else {
+                start_cycle(c, sqrt(r2));
+                if (kind == kFinRes) c->state = 1;
+            }
+        } else {
+            double* h1 = rec;                      // Gram-Schmidt coefficients, slots 0..j
+            double p2 = 0.0;
+            for (int k = 0; k <= j; ++k) {
+                h1[2 * k] = h[2 * k] = s[2 * k];
+                h1[2 * k + 1] = h[2 * k + 1] = s[2 * k + 1];
+                p2 += s[2 * k] * s[2 * k] + s[2 * k + 1] * s[2 * k + 1];
+            }
+            const double w2 = s[2 * (j + 1)];
+            const double n2 = w2 - p2;             // ||w - V h||^2 with an orthonormal basis
+            hn_s = isfinite(w2) ? sqrt(n2 > 0.0 ? n2 : 0.0) : NAN;
+            c->hn = hn_s;
+            h1[2 * (j + 1)] = hn_s;                // the subdiagonal entry, for the residual
+            h1[2 * (j + 1) + 1] = 0.0;
+            rotate = 1;
+        }
     }
+    __syncthreads();
+    if (rotate) givens_column(c, j, h, hn_s);
+}
+
+// V_{j+1} <- (w - sum_{k<=j} h_k V_k) / ctrl->hn (0 for hn = 0), j + 1 = 8 nfull +
+// NKR coefficients.
+template <int NKR>
+__global__ void __launch_bounds__(kCnThreads) cn_gs_update_kernel(double* V, size_t vstride, int nfull, int j,
+                                                                   const double* w, size_t ncplx, const double* rec,
+                                                                   const CnCtrl* c) {
+    const double* coef = rec;
+    const double hn = c->hn;
+    const double alpha = hn > 0.0 ? 1.0 / hn : 0.0;
+    double2* out = reinterpret_cast<double2*>(V + (size_t)(j + 1) * vstride);
     const double2* Wi = reinterpret_cast<const double2*>(w);
-    double2* O = reinterpret_cast<double2*>(out);
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
         double2 x = Wi[i];
         for (int c8 = 0; c8 < nfull; ++c8) {
@@ -238,8 +527,8 @@ __global__ void __launch_bounds__(256) cn_axpy_kernel(const double* V, size_t vs
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const double cr = coef[2 * (8 * c8 + k)], ci = coef[2 * (8 * c8 + k) + 1];
-                x.x -= sign * (cr * y[k].x - ci * y[k].y);
-                x.y -= sign * (cr * y[k].y + ci * y[k].x);
+                x.x -= cr * y[k].x - ci * y[k].y;
+                x.y -= cr * y[k].y + ci * y[k].x;
             }
         }
         double2 y[NKR > 0 ? NKR : 1];
@@ -248,52 +537,104 @@ __global__ void __launch_bounds__(256) cn_axpy_kernel(const double* V, size_t vs
 #pragma unroll
         for (int k = 0; k < NKR; ++k) {
             const double cr = coef[2 * (8 * nfull + k)], ci = coef[2 * (8 * nfull + k) + 1];
-            x.x -= sign * (cr * y[k].x - ci * y[k].y);
-            x.y -= sign * (cr * y[k].y + ci * y[k].x);
+            x.x -= cr * y[k].x - ci * y[k].y;
+            x.y -= cr * y[k].y + ci * y[k].x;
         }
-        if constexpr (NORM) {
-            x.x *= alpha;
-            x.y *= alpha;
-        }
-        O[i] = x;
+        x.x *= alpha;
+        x.y *= alpha;
+        out[i] = x;
     }
 }
 
-// out[k] = sum over blocks of partials[block][k] (complex), one workgroup per slot, fixed order.
-__global__ void __launch_bounds__(256) cn_reduce_kernel(const double* partials, int nblocks, int ldp, double* out) {
-    const int k = blockIdx.x;
-    double r = 0, i = 0;
-    for (int b = threadIdx.x; b < nblocks; b += 256) {
-        r += partials[2 * ((size_t)b * ldp + k)];
-        i += partials[2 * ((size_t)b * ldp + k) + 1];
+// The end of a cycle (gated on done): x += sum_{i<k} y_i V_i with R y = g (upper
+// triangular, k x k, solved by each workgroup in shared memory), and the new
+// residual r = rhs - G x = V_{k+1} (beta e_0 - H_G y) from the Arnoldi relation
+// G V_k = V_{k+1} H_G (no operator product), written to r_out with fixed-order
+// partial sums of ||r||^2.  nv = 8 nfull + NKR basis vectors are read (nv - 1 =
+// the columns queued, >= k; coefficients beyond k are 0).
+template <int NKR>
+__global__ void __launch_bounds__(kCnThreads) cn_update_kernel(const double* V, size_t vstride, int nfull,
+                                                                double* x, double* r_out, size_t ncplx,
+                                                                const double* rec, double* partials,
+                                                                const CnCtrl* c) {
+    if (c->done == 0 || c->nonfinite) return;
+    constexpr int M1 = kCnMaxRestart + 1;
+    __shared__ double y[2 * M1], g[2 * M1], cr[2 * (M1 + 1)];
+    __shared__ double R[2 * M1 * M1];
+    const int k = c->k;
+    for (int i = threadIdx.x; i < 2 * M1; i += blockDim.x) {
+        y[i] = 0.0;
+        g[i] = i < 2 * k ? c->g[i] : 0.0;
     }
-    __shared__ double sr[256], si[256];
-    sr[threadIdx.x] = r;
-    si[threadIdx.x] = i;
+    for (int i = threadIdx.x; i < 2 * (M1 + 1); i += blockDim.x) cr[i] = 0.0;
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {       // R(i, l), column-major
+        const int i = e % k, l = e / k;
+        R[2 * (l * M1 + i)] = c->R[2 * ((size_t)l * M1 + i)];
+        R[2 * (l * M1 + i) + 1] = c->R[2 * ((size_t)l * M1 + i) + 1];
+    }
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            sr[threadIdx.x] += sr[threadIdx.x + off];
-            si[threadIdx.x] += si[threadIdx.x + off];
-        }
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        out[2 * k] = sr[0];
-        out[2 * k + 1] = si[0];
+        for (int i = k - 1; i >= 0; --i) {
+            zc acc{g[2 * i], g[2 * i + 1]};
+            for (int l = i + 1; l < k; ++l)
+                acc = zsub(acc, zmul(zc{R[2 * (l * M1 + i)], R[2 * (l * M1 + i) + 1]}, zc{y[2 * l], y[2 * l + 1]}));
+            const zc q = zdiv(acc, zc{R[2 * (i * M1 + i)], R[2 * (i * M1 + i) + 1]});
+            y[2 * i] = q.re;
+            y[2 * i + 1] = q.im;
+        }
+        // residual coefficients: beta e_0 - H_G y, H_G(i, j) = delta_ij + hdt H_A(i, j) (i <= j),
+        // H_G(j + 1, j) = hdt hn_j, with column j of H_A and hn_j in record j
+        const double hd = c->hdt;
+        cr[0] = c->beta;
+        for (int j = 0; j < k; ++j) {
+            const double* hj = rec + (size_t)j * kCnRecDoubles;
+            const zc yj{y[2 * j], y[2 * j + 1]};
+            for (int i = 0; i <= j; ++i) {
+                const zc h = zadd(zscal(hd, zc{hj[2 * i], hj[2 * i + 1]}), zc{i == j ? 1.0 : 0.0, 0.0});
+                const zc t = zmul(h, yj);
+                cr[2 * i] -= t.re;
+                cr[2 * i + 1] -= t.im;
+            }
+            const zc t = zscal(hd * hj[2 * (j + 1)], yj);
+            cr[2 * (j + 1)] -= t.re;
+            cr[2 * (j + 1) + 1] -= t.im;
+        }
     }
-}
-
-// y <- alpha x (alpha real), or y <- x when alpha == 1.
-__global__ void cn_scale_kernel(const double* x, double* y, size_t n, double alpha) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        y[i] = alpha * x[i];
-}
-
-// y <- x - y  (residual r = b - A x0 with y = A x0)
-__global__ void cn_sub_kernel(const double* x, double* y, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        y[i] = x[i] - y[i];
+    __syncthreads();
+    double rr[1] = {0.0}, ri[1] = {0.0};
+    double2* X = reinterpret_cast<double2*>(x);
+    double2* RO = reinterpret_cast<double2*>(r_out);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncplx; i += (size_t)gridDim.x * blockDim.x) {
+        double2 v = X[i], r = {0.0, 0.0};
+        for (int c8 = 0; c8 < nfull; ++c8) {
+            double2 b[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) b[q] = reinterpret_cast<const double2*>(V + (size_t)(8 * c8 + q) * vstride)[i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int l = 8 * c8 + q;
+                v.x += y[2 * l] * b[q].x - y[2 * l + 1] * b[q].y;
+                v.y += y[2 * l] * b[q].y + y[2 * l + 1] * b[q].x;
+                r.x += cr[2 * l] * b[q].x - cr[2 * l + 1] * b[q].y;
+                r.y += cr[2 * l] * b[q].y + cr[2 * l + 1] * b[q].x;
+            }
+        }
+        double2 b[NKR > 0 ? NKR : 1];
+#pragma unroll
+        for (int q = 0; q < NKR; ++q) b[q] = reinterpret_cast<const double2*>(V + (size_t)(8 * nfull + q) * vstride)[i];
+#pragma unroll
+        for (int q = 0; q < NKR; ++q) {
+            const int l = 8 * nfull + q;
+            v.x += y[2 * l] * b[q].x - y[2 * l + 1] * b[q].y;
+            v.y += y[2 * l] * b[q].y + y[2 * l + 1] * b[q].x;
+            r.x += cr[2 * l] * b[q].x - cr[2 * l + 1] * b[q].y;
+            r.y += cr[2 * l] * b[q].y + cr[2 * l + 1] * b[q].x;
+        }
+        X[i] = v;
+        RO[i] = r;
+        rr[0] += r.x * r.x + r.y * r.y;
+    }
+    store_partials<1>(rr, ri, partials, 0);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -320,104 +661,121 @@ hipError_t launch_cn_apply(int dir, int n, int nlines, const CnApplyParams& p, h
     return dir == 0 ? launch_apply_dir<false>(n, nlines, p, s) : launch_apply_dir<true>(n, nlines, p, s);
 }
 
+hipError_t launch_cn_apply2(int n, const CnApplyParams& px, const CnApplyParams& py, hipStream_t s) {
+    const int ntx = (px.nlines + cn2_lines(n) - 1) / cn2_lines(n);
+    const int nty = (py.nlines + cn2_lines(n) - 1) / cn2_lines(n);
+    const dim3 grid(ntx + nty);
+    switch (n) {
+        case 16: hipLaunchKernelGGL(cn_apply2_kernel<16>, grid, dim3(CnTile<16, true, true>::NT), 0, s, px, py, ntx); break;
+        case 32: hipLaunchKernelGGL(cn_apply2_kernel<32>, grid, dim3(CnTile<32, true, true>::NT), 0, s, px, py, ntx); break;
+        case 64: hipLaunchKernelGGL(cn_apply2_kernel<64>, grid, dim3(CnTile<64, true, true>::NT), 0, s, px, py, ntx); break;
+        case 128: hipLaunchKernelGGL(cn_apply2_kernel<128>, grid, dim3(CnTile<128, true, true>::NT), 0, s, px, py, ntx); break;
+        case 256: hipLaunchKernelGGL(cn_apply2_kernel<256>, grid, dim3(CnTile<256, true, true>::NT), 0, s, px, py, ntx); break;
+        case 512: hipLaunchKernelGGL(cn_apply2_kernel<512>, grid, dim3(CnTile<512, true, true>::NT), 0, s, px, py, ntx); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_cn_exp(double* psi, const double* E, double e0r, double e0i, size_t npts, int times, hipStream_t s) {
     hipLaunchKernelGGL(cn_exp_kernel, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, psi, E,
                        make_double2(e0r, e0i), npts, times);
     return hipGetLastError();
 }
 
-template <bool SELF>
-static void launch_dots_chunk(int nk, const double* V, size_t vstride, int k0, const double* w, size_t ncplx,
-                              double* partials, int nblocks, int ldp, hipStream_t s) {
-#define DIRAC_CN_DOTS(NK)                                                                                    \
-    case NK:                                                                                                 \
-        hipLaunchKernelGGL((cn_dots_kernel<NK, SELF>), dim3(nblocks), dim3(256), 0, s, V, vstride, k0, w,   \
-                           ncplx, partials, ldp);                                                           \
-        break;
-    if constexpr (SELF) {
-        if (nk == 0) {
-            hipLaunchKernelGGL((cn_dots_kernel<0, true>), dim3(nblocks), dim3(256), 0, s, V, vstride, k0, w, ncplx,
-                               partials, ldp);
-            return;
-        }
-    }
-    switch (nk) {
-        DIRAC_CN_DOTS(1) DIRAC_CN_DOTS(2) DIRAC_CN_DOTS(3) DIRAC_CN_DOTS(4)
-        DIRAC_CN_DOTS(5) DIRAC_CN_DOTS(6) DIRAC_CN_DOTS(7) DIRAC_CN_DOTS(8)
-        default: break;
-    }
-#undef DIRAC_CN_DOTS
+hipError_t launch_cn_init(CnCtrl* ctrl, double hdt, double rtol, int max_iter, int m, hipStream_t s) {
+    hipLaunchKernelGGL(cn_init_kernel, dim3(1), dim3(64), 0, s, ctrl, hdt, rtol, max_iter, m);
+    return hipGetLastError();
 }
 
-hipError_t launch_cn_dots(const double* V, size_t vstride, int nk, bool self, const double* w, size_t ncplx,
-                          double* partials, int nblocks, int ldp, double* out, hipStream_t s) {
-    const int slots = nk + (self ? 1 : 0);
-    if (slots < 1 || slots > ldp || nblocks < 1) return hipErrorInvalidValue;
-    int k0 = 0;
-    for (; nk - k0 > 8; k0 += 8) launch_dots_chunk<false>(8, V, vstride, k0, w, ncplx, partials, nblocks, ldp, s);
-    if (self)
-        launch_dots_chunk<true>(nk - k0, V, vstride, k0, w, ncplx, partials, nblocks, ldp, s);
+static hipError_t finish(const double* partials, int nslots, CnFinish kind, int j, double* rec, CnCtrl* ctrl,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(cn_finish_kernel, dim3(1), dim3(kCnThreads), 0, s, partials, nslots, (int)kind, j, rec, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_cn_rhs(const double* rx, const double* ry, double* rhs, double* x, size_t ncplx, double* partials,
+                         CnCtrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(cn_rhs_kernel, dim3(kCnDotBlocks), dim3(kCnThreads), 0, s, rx, ry, rhs, x, ncplx, partials);
+    return finish(partials, 1, kFinRhs, 0, nullptr, ctrl, s);
+}
+
+hipError_t launch_cn_residual(const double* rx, double* ry, size_t ncplx, double* partials, CnCtrl* ctrl,
+                              bool start, hipStream_t s) {
+    if (start)
+        hipLaunchKernelGGL(cn_residual_kernel<true>, dim3(kCnDotBlocks), dim3(kCnThreads), 0, s, rx, ry, ncplx,
+                           partials, (const CnCtrl*)ctrl);
     else
-        launch_dots_chunk<false>(nk - k0, V, vstride, k0, w, ncplx, partials, nblocks, ldp, s);
-    hipLaunchKernelGGL(cn_reduce_kernel, dim3(slots), dim3(256), 0, s, (const double*)partials, nblocks, ldp, out);
-    return hipGetLastError();
+        hipLaunchKernelGGL(cn_residual_kernel<false>, dim3(kCnDotBlocks), dim3(kCnThreads), 0, s, rx, ry, ncplx,
+                           partials, (const CnCtrl*)ctrl);
+    return finish(partials, 1, start ? kFinResStart : kFinRes, 0, nullptr, ctrl, s);
 }
 
-hipError_t launch_cn_axpy_dots(const double* V, size_t vstride, int nk, const double* coef, double* w, size_t ncplx,
-                               double* partials, int nblocks, int ldp, double* out, hipStream_t s) {
-    if (nk < 1 || nk > kCnFusedMax || nk + 1 > ldp || nblocks < 1) return hipErrorInvalidValue;
-#define DIRAC_CN_AXD(NK)                                                                                     \
-    case NK:                                                                                                 \
-        hipLaunchKernelGGL((cn_axpy_dots_kernel<NK>), dim3(nblocks), dim3(256), 0, s, V, vstride, coef, w,  \
-                           ncplx, partials, ldp);                                                           \
+// Gram-Schmidt dots of Arnoldi iteration j: with V_0 .. V_j in chunks of kCnChunk
+// vectors, one launch each (the first also forms w = wx + wy and its norm),
+// then the finishing workgroup.
+hipError_t launch_cn_gs1(const double* V, size_t vstride, int j, double* wx, const double* wy, size_t ncplx,
+                         double* partials, double* rec, CnCtrl* ctrl, hipStream_t s) {
+    if (j < 0 || j >= kCnMaxRestart) return hipErrorInvalidValue;
+    const int nk = j + 1;
+    const int nchunks = (nk + kCnChunk - 1) / kCnChunk;
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int k0 = ch * kCnChunk, cnt = std::min(kCnChunk, nk - k0);
+#define DIRAC_CN_GS(NK)                                                                                          \
+    case NK:                                                                                                     \
+        if (ch == 0)                                                                                             \
+            hipLaunchKernelGGL((cn_gs1_kernel<NK, true>), dim3(kCnDotBlocks), dim3(kCnThreads), 0, s, V, vstride,\
+                               k0, j, wx, wy, ncplx, partials);                                                  \
+        else                                                                                                     \
+            hipLaunchKernelGGL((cn_gs1_kernel<NK, false>), dim3(kCnDotBlocks), dim3(kCnThreads), 0, s, V,        \
+                               vstride, k0, j, wx, wy, ncplx, partials);                                         \
         break;
-    switch (nk) {
-        DIRAC_CN_AXD(1) DIRAC_CN_AXD(2) DIRAC_CN_AXD(3) DIRAC_CN_AXD(4)
-        DIRAC_CN_AXD(5) DIRAC_CN_AXD(6) DIRAC_CN_AXD(7) DIRAC_CN_AXD(8)
-        default: break;
+        switch (cnt) {
+            DIRAC_CN_GS(1) DIRAC_CN_GS(2) DIRAC_CN_GS(3) DIRAC_CN_GS(4)
+            DIRAC_CN_GS(5) DIRAC_CN_GS(6) DIRAC_CN_GS(7) DIRAC_CN_GS(8)
+            default: return hipErrorInvalidValue;
+        }
+#undef DIRAC_CN_GS
     }
-#undef DIRAC_CN_AXD
-    hipLaunchKernelGGL(cn_reduce_kernel, dim3(nk + 1), dim3(256), 0, s, (const double*)partials, nblocks, ldp, out);
-    return hipGetLastError();
+    return finish(partials, j + 2, kFinGs, j, rec, ctrl, s);
 }
 
-template <bool NORM>
-static hipError_t launch_axpy_t(const double* V, size_t vstride, int nk, const double* coef, const double* w,
-                                double* out, size_t ncplx, double sign, double* norm_out, hipStream_t s) {
-    if (nk < 0 || (NORM && !norm_out)) return hipErrorInvalidValue;
-    const int nfull = nk / 8;
-#define DIRAC_CN_AXPY(R)                                                                                     \
-    case R:                                                                                                  \
-        hipLaunchKernelGGL((cn_axpy_kernel<R, NORM>), dim3(1024), dim3(256), 0, s, V, vstride, nfull, coef,  \
-                           w, out, ncplx, sign, norm_out);                                                  \
+hipError_t launch_cn_gs_update(double* V, size_t vstride, int j, const double* w, size_t ncplx, const double* rec,
+                               CnCtrl* ctrl, hipStream_t s) {
+    if (j < 0 || j >= kCnMaxRestart) return hipErrorInvalidValue;
+    const int nk = j + 1, nfull = nk / 8;
+#define DIRAC_CN_UP(R)                                                                                           \
+    case R:                                                                                                      \
+        hipLaunchKernelGGL((cn_gs_update_kernel<R>), dim3(1024), dim3(kCnThreads), 0, s, V, vstride, nfull, j, w,\
+                           ncplx, rec, (const CnCtrl*)ctrl);                                                     \
         break;
     switch (nk % 8) {
-        DIRAC_CN_AXPY(0) DIRAC_CN_AXPY(1) DIRAC_CN_AXPY(2) DIRAC_CN_AXPY(3)
-        DIRAC_CN_AXPY(4) DIRAC_CN_AXPY(5) DIRAC_CN_AXPY(6) DIRAC_CN_AXPY(7)
+        DIRAC_CN_UP(0) DIRAC_CN_UP(1) DIRAC_CN_UP(2) DIRAC_CN_UP(3)
+        DIRAC_CN_UP(4) DIRAC_CN_UP(5) DIRAC_CN_UP(6) DIRAC_CN_UP(7)
         default: break;
     }
-#undef DIRAC_CN_AXPY
+#undef DIRAC_CN_UP
     return hipGetLastError();
 }
 
-hipError_t launch_cn_axpy(const double* V, size_t vstride, int nk, const double* coef, const double* w, double* out,
-                          size_t ncplx, double sign, hipStream_t s) {
-    return launch_axpy_t<false>(V, vstride, nk, coef, w, out, ncplx, sign, nullptr, s);
-}
-
-hipError_t launch_cn_axpy_normalise(const double* V, size_t vstride, int nk, const double* coef, const double* w,
-                                    double* out, size_t ncplx, double* norm2_out, hipStream_t s) {
-    return launch_axpy_t<true>(V, vstride, nk, coef, w, out, ncplx, 1.0, norm2_out, s);
-}
-
-hipError_t launch_cn_scale(const double* x, double* y, size_t n, double alpha, hipStream_t s) {
-    hipLaunchKernelGGL(cn_scale_kernel, dim3(1024), dim3(256), 0, s, x, y, n, alpha);
-    return hipGetLastError();
-}
-
-hipError_t launch_cn_sub(const double* x, double* y, size_t n, hipStream_t s) {
-    hipLaunchKernelGGL(cn_sub_kernel, dim3(1024), dim3(256), 0, s, x, y, n);
-    return hipGetLastError();
+hipError_t launch_cn_update(const double* V, size_t vstride, int nk, double* x, double* r_out, size_t ncplx,
+                            const double* rec, double* partials, CnCtrl* ctrl, hipStream_t s) {
+    if (nk < 0 || nk > kCnMaxRestart) return hipErrorInvalidValue;
+    const int nv = nk + 1, nfull = nv / 8;
+#define DIRAC_CN_XU(R)                                                                                           \
+    case R:                                                                                                      \
+        hipLaunchKernelGGL((cn_update_kernel<R>), dim3(kCnDotBlocks), dim3(kCnThreads), 0, s, V, vstride, nfull, \
+                           x, r_out, ncplx, rec, partials, (const CnCtrl*)ctrl);                                 \
+        break;
+    switch (nv % 8) {
+        DIRAC_CN_XU(0) DIRAC_CN_XU(1) DIRAC_CN_XU(2) DIRAC_CN_XU(3)
+        DIRAC_CN_XU(4) DIRAC_CN_XU(5) DIRAC_CN_XU(6) DIRAC_CN_XU(7)
+        default: break;
+    }
+#undef DIRAC_CN_XU
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finish(partials, 1, kFinRes, 0, nullptr, ctrl, s);
 }
 
 }  // namespace dirac

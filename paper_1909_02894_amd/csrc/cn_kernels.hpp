@@ -8,39 +8,100 @@
 
 namespace dirac {
 
+constexpr int kCnDotBlocks = 512;     // workgroups of the reduction kernels
+constexpr int kCnMaxRestart = 63;     // Krylov vectors per cycle (validated on creation)
+constexpr int kCnChunk = 8;           // basis vectors one reduction launch handles
+
+// Device-resident state of the GMRES solve of one step: the Hessenberg
+// least-squares problem after Givens rotations (R, cs, sn, g), the cycle's
+// counters and the stopping rule.  Written by the last workgroup of the
+// reduction kernels (and the init kernel) and read by the other kernels.
+struct CnCtrl {
+    double beta;          // norm of the current cycle's starting residual
+    double bnorm;         // ||rhs||
+    double tol;           // rtol ||rhs||
+    double res2;          // squared norm of the last explicit residual
+    double hn;            // norm of the newest Arnoldi vector before normalisation
+    double hdt;           // dt / 2 (G = I + hdt A)
+    double rtol;
+    double pad0;
+    int k;                // columns of the current cycle
+    int done;             // the cycle has ended (converged estimate, breakdown, full or out of iterations)
+    int used;             // iterations of this step
+    int max_iter;
+    int m;                // restart length
+    int state;            // 0 iterating, 1 restart needed, 2 converged, 3 out of iterations
+    int nonfinite;
+    int pad1;
+    unsigned ticket;      // last-workgroup counter of the reduction kernels (0 between kernels)
+    unsigned pad[3];
+    double cs[kCnMaxRestart + 1];
+    double sn[2 * (kCnMaxRestart + 1)];        // complex
+    double g[2 * (kCnMaxRestart + 2)];         // complex
+    double R[2 * (kCnMaxRestart + 1) * (kCnMaxRestart + 1)];   // complex, R(i, j) at 2 (j (m_max + 1) + i)
+};
+
+// Arnoldi coefficient record of iteration j: H_A(0..j, j) and the subdiagonal
+// entry H_A(j + 1, j) = hn_j in slot j + 1 (kCnMaxRestart + 1 complex slots).
+constexpr size_t kCnRecDoubles = 2 * (kCnMaxRestart + 1);
+
+// out_x = base + f c b_x sigma_x [[d_x]] v    (rows)
+// out_y =        f c b_y sigma_y [[d_y]] v    (columns)
+// with v = in, or in / in_norm[0] when in_norm is given (the x pass then also
+// stores that v to vout), and base = 0, v or (b - v) by `base`.  G v = out_x +
+// out_y for base = v, f = dt/2; the A of the Arnoldi process for base = 0, f = 1.
 struct CnApplyParams {
-    const double* in;        // vector the transport operator acts on
-    double* out;             // x pass: out = in + term; y pass: out += term
+    const double* in;
+    const double* in_norm;   // divide the input by in_norm[0] (0 -> zero vector), or null
+    double* vout;            // x pass: the (divided) input, or null
+    const double* b;         // base 2: b - v
+    double* out;             // out_x (x pass) or out_y (y pass)
     const double* a;         // a(x) per point, or null (a = 1)
     const double* inv_s;     // 1/S along the line direction (ones without a layer)
     const double* D;         // xi / n along the line direction
     const cpx<double>* tw;   // twiddles
+    const int* gate;         // skip the launch when gate[0] == 0 (null: always run)
     int n1;                  // points per row
     int nlines;
-    double scale;            // s (dt / 2) c, s = +1 for G, -1 for G~
+    int base;                // 0: none, 1: v, 2: b - v (x pass only)
+    double scale;            // f c
 };
 
-constexpr int kCnDotBlocks = 512;
-constexpr int kCnFusedMax = 8;      // basis vectors the fused update + dots kernel holds in registers
-
 hipError_t launch_cn_apply(int dir, int n, int nlines, const CnApplyParams& p, hipStream_t s);
+// Both directions of a square n x n grid (n <= 512) in one launch (px: x pass,
+// py: y pass); the gate is px's.
+hipError_t launch_cn_apply2(int n, const CnApplyParams& px, const CnApplyParams& py, hipStream_t s);
 hipError_t launch_cn_exp(double* psi, const double* E, double e0r, double e0i, size_t npts, int times, hipStream_t s);
-// out[k] = <V_k, w> for k < nk, and out[nk] = ||w||^2 when self (complex slots, fixed-order sums);
-// partials: nblocks x ldp complex scratch.
-hipError_t launch_cn_dots(const double* V, size_t vstride, int nk, bool self, const double* w, size_t ncplx,
-                          double* partials, int nblocks, int ldp, double* out, hipStream_t s);
-// w <- w - sum_{k<nk} coef_k V_k, then out[k] = <V_k, w> (k < nk), out[nk] = ||w||^2;
-// nk <= kCnFusedMax.
-hipError_t launch_cn_axpy_dots(const double* V, size_t vstride, int nk, const double* coef, double* w, size_t ncplx,
-                               double* partials, int nblocks, int ldp, double* out, hipStream_t s);
-// out <- w - sign sum_{k<nk} coef_k V_k (out may be w)
-hipError_t launch_cn_axpy(const double* V, size_t vstride, int nk, const double* coef, const double* w, double* out,
-                          size_t ncplx, double sign, hipStream_t s);
-// out <- (w - sum_{k<nk} coef_k V_k) / norm with norm^2 = coef[nk] - sum |coef_k|^2 (coef[nk] = ||w||^2,
-// V_k orthonormal), stored to norm2_out[0]
-hipError_t launch_cn_axpy_normalise(const double* V, size_t vstride, int nk, const double* coef, const double* w,
-                                    double* out, size_t ncplx, double* norm2_out, hipStream_t s);
-hipError_t launch_cn_scale(const double* x, double* y, size_t n, double alpha, hipStream_t s);
-hipError_t launch_cn_sub(const double* x, double* y, size_t n, hipStream_t s);
+
+// The reductions below run kCnDotBlocks workgroups of 256 threads over the ncplx
+// complex entries of the vectors; each workgroup writes fixed-order partial
+// sums, and the workgroup that finishes last sums them in workgroup order
+// (bitwise reproducible) and updates `ctrl`.
+
+// Constants of the stopping rule and the Hessenberg matrix for the calls that follow.
+hipError_t launch_cn_init(CnCtrl* ctrl, double hdt, double rtol, int max_iter, int m, hipStream_t s);
+// rhs <- rx + ry; x <- 2 rhs - x; bnorm = ||rhs||, tol = rtol bnorm; the step's counters reset.
+hipError_t launch_cn_rhs(const double* rx, const double* ry, double* rhs, double* x, size_t ncplx, double* partials,
+                         CnCtrl* ctrl, hipStream_t s);
+// r <- rx + ry (in ry); res2 = ||r||^2.  start = true: the step's first residual
+// (a new cycle starts from it unless it is already below tol); start = false:
+// the explicit residual after a cycle's update (gated on ctrl->done): the state
+// becomes converged, out of iterations, or restart (a new cycle from r).
+hipError_t launch_cn_residual(const double* rx, double* ry, size_t ncplx, double* partials, CnCtrl* ctrl,
+                              bool start, hipStream_t s);
+// Arnoldi iteration j (basis V, vstride doubles apart), classical Gram-Schmidt:
+// w <- wx + wy (in wx); h_k = <V_k, w> (k <= j), hn = ||w - V h||; the Givens
+// update of column j.
+hipError_t launch_cn_gs1(const double* V, size_t vstride, int j, double* wx, const double* wy, size_t ncplx,
+                         double* partials, double* rec, CnCtrl* ctrl, hipStream_t s);
+// V_{j+1} = (w - sum h_k V_k) / hn.
+hipError_t launch_cn_gs_update(double* V, size_t vstride, int j, const double* w, size_t ncplx, const double* rec,
+                               CnCtrl* ctrl, hipStream_t s);
+// The end of a cycle (gated on ctrl->done): x += V y with R y = g solved per
+// workgroup, and the residual r = rhs - G x = V (beta e_0 - H_G y) from the
+// Arnoldi relation to r_out with its norm; then the verdict (converged, out of
+// iterations, or a restart from r).  nk = columns queued (>= the cycle's k).
+hipError_t launch_cn_update(const double* V, size_t vstride, int nk, double* x, double* r_out, size_t ncplx,
+                            const double* rec, double* partials, CnCtrl* ctrl, hipStream_t s);
 
 }  // namespace dirac

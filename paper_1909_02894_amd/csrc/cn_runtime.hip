@@ -2,22 +2,25 @@
 //   psi^{n+1/2} = E psi^n                                  (Step 1)
 //   G psi* = G~ psi^{n+1/2}, solved by restarted GMRES      (Step 2, Crank-Nicolson)
 //   psi^{n+1} = E psi*                                      (Step 3)
-// with G = I + (dt/2) alpha.T and G~ = I - (dt/2) alpha.T.  Every vector operation
-// runs on the device; the host holds only the small Hessenberg least-squares
-// problem of each GMRES cycle (Givens rotations, back substitution), and reads
-// its columns in batches (gmres below).
+// with G = I + (dt/2) A and G~ = I - (dt/2) A, A = alpha(x).T.
 //
-// GMRES(m): Arnoldi with classical Gram-Schmidt applied twice (CGS2), started
-// from x0 = psi^{n+1/2}; a cycle ends when the rotated residual estimate falls
-// below rtol ||G~ psi||, and the next cycle's explicit residual b - G x decides
-// convergence, so the reported residual is always a true one.
+// GMRES(m) from the first-order predictor x0 = psi - dt A psi (= 2 G~ psi - psi,
+// one Arnoldi iteration fewer than x0 = psi at the same tolerance).  Arnoldi runs
+// on A (same Krylov space as G) with one classical Gram-Schmidt pass (A v is far
+// from parallel to v, so the pass does not cancel); the least-squares problem
+// of I + (dt/2) H_A,
+// its Givens rotations, the back substitution and every vector operation stay
+// on the device.  The host queues a cycle's iterations (as many as the last
+// cycle needed) and the update, then reads the device state once.  The update
+// also forms the residual b - G x = V (beta e_0 - H_G y) from the Arnoldi
+// relation G V = V H_G, vector by vector (it does not assume an orthonormal
+// basis, unlike the rotated estimate |g_k|); its norm decides convergence and a
+// restart starts from it.  Iterations queued past convergence change nothing.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
-#include <complex>
 #include <string>
-#include <vector>
 
 #include "../../include/dirac.h"
 #include "cn_kernels.hpp"
@@ -28,7 +31,10 @@ namespace dirac {
 
 namespace {
 
-using zd = std::complex<double>;
+// Iterations queued for a solver's first cycle (later cycles: the last one's length).
+constexpr int kCnFirstBatch = 4;
+
+size_t align_up_256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct CnCtx {
     dirac_solver* s;
@@ -36,16 +42,15 @@ struct CnCtx {
     size_t npts, ncplx, vstride;      // vstride in doubles
     double* psi;
     double* rhs;
-    double* work;
+    double* wx;                       // x part of an operator product, then the Arnoldi vector w
+    double* wy;                       // y part; the cycle's starting residual
     double* V;                        // Krylov basis, m + 1 vectors
     double* part;
-    double* coef;                     // [5][64] complex: (unused), (unused), norm, update, rhs norm;
-                                      // then per Arnoldi iteration j: [3][64] h pass 1, h pass 2, norm
-    double h;                         // (dt / 2) c
+    double* rec;                      // Arnoldi coefficient records, one per iteration
+    CnCtrl* ctrl;
 
     double* vec(int k) const { return V + (size_t)k * vstride; }
-    double* coef_row(int r) const { return coef + (size_t)r * 128; }
-    double* rec_row(int j, int r) const { return coef + (size_t)(5 + 3 * j + r) * 128; }
+    double* rec_of(int j) const { return rec + (size_t)j * kCnRecDoubles; }
 };
 
 #define CN_TRY(expr, what)                                                                              \
@@ -54,163 +59,109 @@ struct CnCtx {
         if (e_ != hipSuccess) return fail(DIRAC_E_DEVICE, "%s: %s", (what), hipGetErrorString(e_));    \
     } while (0)
 
-// out = in + sign (dt/2) alpha.T in: the x pass writes out, the y pass accumulates.
-hipError_t apply_G(const CnCtx& c, const double* in, double* out, double sign) {
+// out_x / out_y of the transport operator on `in` (see CnApplyParams).
+hipError_t apply(const CnCtx& c, const double* in, const double* in_norm, double* vout, int base, const double* bvec,
+                 double f, const int* gate) {
     dirac_solver* s = c.s;
     char* b = s->base;
+    CnApplyParams pp[2];
     for (int dir = 0; dir < 2; ++dir) {
-        CnApplyParams p{};
+        CnApplyParams& p = pp[dir];
+        p = CnApplyParams{};
         p.in = in;
-        p.out = out;
+        p.in_norm = in_norm;
+        p.vout = dir == 0 ? vout : nullptr;
+        p.b = bvec;
+        p.out = dir == 0 ? c.wx : c.wy;
         p.a = s->curved ? reinterpret_cast<const double*>(b + s->lay.a) : nullptr;
         p.inv_s = reinterpret_cast<const double*>(b + s->lay.inv_s[dir]);   // ones without a layer
         p.D = reinterpret_cast<const double*>(b + s->lay.D[dir]);
         p.tw = reinterpret_cast<const cpx<double>*>(b + s->lay.tw[dir]);
+        p.gate = gate;
         p.n1 = s->g.n1;
         p.nlines = dir == 0 ? s->g.n2 : s->g.n1;
-        p.scale = sign * c.h;
-        hipError_t e = launch_cn_apply(dir, dir == 0 ? s->g.n1 : s->g.n2, p.nlines, p, c.st);
+        p.base = dir == 0 ? base : 0;
+        p.scale = f * s->g.c;
+    }
+    // square grids up to 512 points: both directions in one launch, side by side
+    if (s->g.n1 == s->g.n2 && s->g.n1 <= 512) return launch_cn_apply2(s->g.n1, pp[0], pp[1], c.st);
+    for (int dir = 0; dir < 2; ++dir) {
+        hipError_t e = launch_cn_apply(dir, dir == 0 ? s->g.n1 : s->g.n2, pp[dir].nlines, pp[dir], c.st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// ||v||^2 into coef row `row`, slot 0 (device), fixed-order reduction.
-hipError_t norm2_dev(const CnCtx& c, const double* v, int row) {
-    return launch_cn_dots(nullptr, 0, 0, true, v, c.ncplx, c.part, kCnDotBlocks, 64, c.coef_row(row), c.st);
+// Arnoldi iteration j: w = A V_j (V_0 = r / beta is formed by the x pass of
+// iteration 0 from the residual in wy), Gram-Schmidt dots and the Givens update
+// of column j, V_{j+1}.
+hipError_t arnoldi(const CnCtx& c, int j) {
+    hipError_t e;
+    if (j == 0) e = apply(c, c.wy, &c.ctrl->beta, c.vec(0), 0, nullptr, 1.0, nullptr);
+    else e = apply(c, c.vec(j), nullptr, nullptr, 0, nullptr, 1.0, nullptr);
+    if (e != hipSuccess) return e;
+    if ((e = launch_cn_gs1(c.V, c.vstride, j, c.wx, c.wy, c.ncplx, c.part, c.rec_of(j), c.ctrl, c.st)) != hipSuccess)
+        return e;
+    return launch_cn_gs_update(c.V, c.vstride, j, c.wx, c.ncplx, c.rec_of(j), c.ctrl, c.st);
 }
 
-dirac_status read_coef(const CnCtx& c, const double* src, double* host, size_t doubles) {
-    CN_TRY(hipMemcpyAsync(host, src, doubles * sizeof(double), hipMemcpyDeviceToHost, c.st), "read GMRES coefficients");
+// The host's copy of the solve state after a cycle.
+struct CtrlHead {
+    double beta, bnorm, tol, res2, hn, hdt, rtol, pad0;
+    int k, done, used, max_iter, m, state, nonfinite, pad1;
+};
+static_assert(sizeof(CtrlHead) <= sizeof(CnCtrl), "control head");
+
+dirac_status read_ctrl(const CnCtx& c, CtrlHead& h) {
+    CN_TRY(hipMemcpyAsync(&h, c.ctrl, sizeof h, hipMemcpyDeviceToHost, c.st), "read GMRES state");
     CN_TRY(hipStreamSynchronize(c.st), "synchronise GMRES");
     return DIRAC_OK;
 }
 
-// Solve G x = rhs in place (x = psi on entry is the initial guess).  The norm
-// of rhs is on the device (coef row 4) and read with the first residual.
-//
-// Arnoldi iterations are queued in batches without a host round trip: each
-// iteration's Hessenberg column and norm go to their own coefficient rows and
-// the next basis vector is normalised on the device by that norm; the host
-// then reads the batch's columns at once and applies the rotations column by
-// column.  A cycle that converges inside a batch uses only its first columns
-// (the later ones were computed and are dropped), so the iterate is the one
-// the column-by-column form gives.  The first batch of a cycle is the previous
-// cycle's length (steady solves converge at the same count); later batches are
-// single iterations.
+// Solve G x = rhs for the step: on entry psi holds psi^{n+1/2}; on exit the solution.
 dirac_status gmres(CnCtx& c, int64_t& iters, double& rel_res) {
     dirac_solver* s = c.s;
     const int m = s->scheme.gmres_restart;
-    std::vector<zd> H((size_t)(m + 1) * m), g(m + 1), sn(m), y(m);
-    std::vector<double> cs(m), host(5 * 128), cols((size_t)3 * 128 * m);
-    std::vector<double>& upload = s->cn_host;            // outlives the async upload
-    upload.assign(128, 0.0);
-    auto Hat = [&](int i, int j) -> zd& { return H[(size_t)i * m + j]; };
-    int64_t used = 0;
-    double tol = 0.0, bnorm = 0.0;
-    bool first = true;
+    const double hdt = 0.5 * s->g.dt;
+    // rhs = G~ psi, x0 = 2 rhs - psi, r0 = rhs - G x0 (to wy), a cycle starts from it
+    CN_TRY(apply(c, c.psi, nullptr, nullptr, 1, nullptr, -hdt, nullptr), "apply G~");
+    CN_TRY(launch_cn_rhs(c.wx, c.wy, c.rhs, c.psi, c.ncplx, c.part, c.ctrl, c.st), "right-hand side");
+    CN_TRY(apply(c, c.psi, nullptr, nullptr, 2, c.rhs, -hdt, nullptr), "residual");
+    CN_TRY(launch_cn_residual(c.wx, c.wy, c.ncplx, c.part, c.ctrl, true, c.st), "residual norm");
+    CtrlHead h{};
+    int j = 0;
+    int batch = std::min(m, std::max(1, s->cn_cycle_len > 0 ? s->cn_cycle_len : kCnFirstBatch));
     for (;;) {
-        // explicit residual r = rhs - G x
-        CN_TRY(apply_G(c, c.psi, c.work, +1.0), "apply G");
-        CN_TRY(launch_cn_sub(c.rhs, c.work, 4 * c.npts, c.st), "residual");
-        CN_TRY(norm2_dev(c, c.work, 2), "residual norm");
-        dirac_status r = read_coef(c, c.coef, host.data(), 5 * 128);
-        if (r != DIRAC_OK) return r;
-        if (first) {
-            bnorm = std::sqrt(host[512]);
-            tol = s->scheme.gmres_rtol * bnorm;
-            first = false;
-        }
-        const double beta = std::sqrt(host[256]);
-        if (!std::isfinite(beta)) return fail(DIRAC_E_NONFINITE, "GMRES residual is not finite");
-        rel_res = bnorm > 0 ? beta / bnorm : 0.0;
-        if (beta <= tol) break;
-        if (used >= s->scheme.gmres_max_iter)
-            return fail(DIRAC_E_NOCONV, "GMRES stopped after %lld iterations at relative residual %.3g",
-                        (long long)used, rel_res);
-        CN_TRY(launch_cn_scale(c.work, c.vec(0), 4 * c.npts, 1.0 / beta, c.st), "normalise");
-        std::fill(g.begin(), g.end(), zd(0));
-        g[0] = beta;
-        int k = 0, j = 0;
-        bool done = false;
-        int batch = std::max(1, s->cn_cycle_len);
-        while (!done && j < m) {
-            const int nb = (int)std::min<int64_t>({(int64_t)batch, (int64_t)(m - j),
-                                                   std::max<int64_t>(1, s->scheme.gmres_max_iter - used)});
-            batch = 1;
-            for (int q = 0; q < nb; ++q) {
-                const int jj = j + q;
-                CN_TRY(apply_G(c, c.vec(jj), c.work, +1.0), "apply G");
-                // classical Gram-Schmidt applied twice; the second pass's dots ride on the
-                // first update, and the second update writes the next basis vector, normalised
-                // by ||w1||^2 - ||h2||^2 (w1 after the first pass, V orthonormal)
-                const int nk = jj + 1;
-                CN_TRY(launch_cn_dots(c.V, c.vstride, nk, false, c.work, c.ncplx, c.part, kCnDotBlocks, 64,
-                                      c.rec_row(jj, 0), c.st), "Gram-Schmidt dots");
-                if (nk <= kCnFusedMax) {
-                    CN_TRY(launch_cn_axpy_dots(c.V, c.vstride, nk, c.rec_row(jj, 0), c.work, c.ncplx, c.part,
-                                               kCnDotBlocks, 64, c.rec_row(jj, 1), c.st), "Gram-Schmidt update");
-                } else {
-                    CN_TRY(launch_cn_axpy(c.V, c.vstride, nk, c.rec_row(jj, 0), c.work, c.work, c.ncplx, 1.0, c.st),
-                           "Gram-Schmidt update");
-                    CN_TRY(launch_cn_dots(c.V, c.vstride, nk, true, c.work, c.ncplx, c.part, kCnDotBlocks, 64,
-                                          c.rec_row(jj, 1), c.st), "Gram-Schmidt dots");
-                }
-                CN_TRY(launch_cn_axpy_normalise(c.V, c.vstride, nk, c.rec_row(jj, 1), c.work, c.vec(jj + 1),
-                                                c.ncplx, c.rec_row(jj, 2), c.st), "normalise");
-            }
-            r = read_coef(c, c.rec_row(j, 0), cols.data(), (size_t)3 * 128 * nb);
-            if (r != DIRAC_OK) return r;
-            for (int q = 0; q < nb && !done; ++q) {
-                const int jc = j + q;
-                const double* col = cols.data() + (size_t)3 * 128 * q;
-                ++used;
-                for (int i = 0; i <= jc; ++i)
-                    Hat(i, jc) = zd(col[2 * i] + col[128 + 2 * i], col[2 * i + 1] + col[128 + 2 * i + 1]);
-                const double hn = std::sqrt(col[256]);
-                if (!std::isfinite(hn)) return fail(DIRAC_E_NONFINITE, "Arnoldi vector is not finite");
-                // previous rotations on the new column
-                for (int i = 0; i < jc; ++i) {
-                    const zd a = Hat(i, jc), b2 = Hat(i + 1, jc);
-                    Hat(i, jc) = cs[i] * a + sn[i] * b2;
-                    Hat(i + 1, jc) = -std::conj(sn[i]) * a + cs[i] * b2;
-                }
-                // new rotation zeroing the subdiagonal hn (real, >= 0)
-                const zd a = Hat(jc, jc);
-                const double aa = std::abs(a), rr = std::hypot(aa, hn);
-                if (aa == 0.0) {
-                    cs[jc] = 0.0;
-                    sn[jc] = 1.0;
-                } else {
-                    cs[jc] = aa / rr;
-                    sn[jc] = (a / aa) * hn / rr;
-                }
-                Hat(jc, jc) = cs[jc] * a + sn[jc] * hn;
-                g[jc + 1] = -std::conj(sn[jc]) * g[jc];
-                g[jc] = cs[jc] * g[jc];
-                k = jc + 1;
-                const double est = std::abs(g[jc + 1]);
-                if (hn == 0.0 || est <= tol || used >= s->scheme.gmres_max_iter) done = true;
-            }
-            j += nb;
-        }
-        s->cn_cycle_len = k;
-        // back substitution H y = g and x += V y
-        for (int i = k - 1; i >= 0; --i) {
-            zd acc = g[i];
-            for (int l = i + 1; l < k; ++l) acc -= Hat(i, l) * y[l];
-            y[i] = acc / Hat(i, i);
-        }
-        for (int i = 0; i < k; ++i) {
-            upload[2 * i] = y[i].real();
-            upload[2 * i + 1] = y[i].imag();
-        }
-        CN_TRY(hipMemcpyAsync(c.coef_row(3), upload.data(), 2 * k * sizeof(double), hipMemcpyHostToDevice, c.st),
-               "upload update");
-        CN_TRY(launch_cn_axpy(c.V, c.vstride, k, c.coef_row(3), c.psi, c.psi, c.ncplx, -1.0, c.st),
+        const int nb = std::min(batch, m - j);
+        for (int q = 0; q < nb; ++q) CN_TRY(arnoldi(c, j + q), "Arnoldi iteration");
+        j += nb;
+        // gated on the cycle's end: x += V y, the residual and the verdict
+        CN_TRY(launch_cn_update(c.V, c.vstride, j, c.psi, c.wy, c.ncplx, c.rec, c.part, c.ctrl, c.st),
                "solution update");
+        dirac_status r = read_ctrl(c, h);
+        if (r != DIRAC_OK) return r;
+        rel_res = h.bnorm > 0 ? std::sqrt(h.res2) / h.bnorm : 0.0;
+        if (h.nonfinite) {
+            iters += h.used;
+            return fail(DIRAC_E_NONFINITE, "GMRES produced a non-finite value");
+        }
+        if (h.state == 2) break;                                 // converged
+        if (h.state == 3) {
+            iters += h.used;
+            return fail(DIRAC_E_NOCONV, "GMRES stopped after %d iterations at relative residual %.3g", h.used,
+                        rel_res);
+        }
+        if (h.state == 1) {                                      // restart from the new residual
+            s->cn_cycle_len = m;
+            j = 0;
+            batch = m;
+        } else {                                                 // the cycle goes on
+            if (j >= m) return fail(DIRAC_E_DEVICE, "GMRES cycle state is inconsistent");
+            batch = 1;
+        }
     }
-    iters += used;
+    if (h.k > 0) s->cn_cycle_len = h.k;
+    iters += h.used;
     return DIRAC_OK;
 }
 
@@ -228,11 +179,12 @@ dirac_status cn_step_n(dirac_solver* s, int64_t nsteps) {
     c.psi = reinterpret_cast<double*>(b + s->lay.psi);
     double* vecs = reinterpret_cast<double*>(b + s->lay.cn_vec);
     c.rhs = vecs;
-    c.work = vecs + c.vstride;
-    c.V = vecs + 2 * c.vstride;
+    c.wx = vecs + c.vstride;
+    c.wy = vecs + 2 * c.vstride;
+    c.V = vecs + 3 * c.vstride;
     c.part = reinterpret_cast<double*>(b + s->lay.cn_part);
-    c.coef = reinterpret_cast<double*>(b + s->lay.cn_coef);
-    c.h = 0.5 * s->g.dt * s->g.c;
+    c.ctrl = reinterpret_cast<CnCtrl*>(b + s->lay.cn_coef);
+    c.rec = reinterpret_cast<double*>(b + s->lay.cn_coef + align_up_256(sizeof(CnCtrl)));
     const double* E = s->curved ? reinterpret_cast<const double*>(b + s->lay.E) : nullptr;
     // Step 3 of the previous step, then Step 1 of this one (one application when
     // the step opens the call, or Step 3 alone after the last step); with
@@ -258,12 +210,12 @@ dirac_status cn_step_n(dirac_solver* s, int64_t nsteps) {
     const size_t state_bytes = c.npts * 32;
     char* saved = b + s->lay.scratch;
     CN_TRY(hipMemcpyAsync(saved, c.psi, state_bytes, hipMemcpyDeviceToDevice, c.st), "save state");
+    CN_TRY(launch_cn_init(c.ctrl, 0.5 * s->g.dt, s->scheme.gmres_rtol, s->scheme.gmres_max_iter,
+                          s->scheme.gmres_restart, c.st), "GMRES set-up");
     const int64_t step0 = s->step;
     auto steps = [&]() -> dirac_status {
         for (int64_t n = 0; n < nsteps; ++n) {
             CN_TRY(exp_steps(s->step, n == 0 ? 1 : 2, false), "Step 1");
-            CN_TRY(apply_G(c, c.psi, c.rhs, -1.0), "apply G~");
-            CN_TRY(norm2_dev(c, c.rhs, 4), "right-hand side norm");
             dirac_status r = gmres(c, s->cn_iters, s->cn_last_res);
             if (r != DIRAC_OK) return r;
             s->step += 1;

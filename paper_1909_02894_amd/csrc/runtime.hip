@@ -194,10 +194,12 @@ Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* 
     const size_t setup_parts = ((N + 255) / 256) * 3;
     const size_t obs_parts = ((size_t)g->n1 + g->n2) * 8;
     if (sc.scheme == DIRAC_SCHEME_CN_GMRES) {
+        // rhs, the two parts of an operator product, and the m + 1 basis vectors
         L.cn_vecbytes = align256(N * 32);
-        L.cn_vec = take(L.cn_vecbytes * (size_t)(sc.gmres_restart + 3));
-        L.cn_part = take((size_t)kCnDotBlocks * 64 * 2 * 8);
-        L.cn_coef = take((size_t)(5 + 3 * sc.gmres_restart) * 64 * 2 * 8);   // shared rows + one record per iteration
+        L.cn_vec = take(L.cn_vecbytes * (size_t)(sc.gmres_restart + 4));
+        L.cn_part = take((size_t)kCnDotBlocks * (kCnMaxRestart + 2) * 2 * 8);
+        // the device-resident solve state, then one coefficient record per iteration
+        L.cn_coef = take(align256(sizeof(CnCtrl)) + (size_t)sc.gmres_restart * kCnRecDoubles * 8);
     } else {
         L.cn_vec = L.cn_part = L.cn_coef = SIZE_MAX;
         L.cn_vecbytes = 0;

@@ -25,9 +25,9 @@ struct Layout {
     size_t K[2];       // directional symbols per axis (complex T)
     size_t D[2];       // derivative symbols per axis (T)
     size_t tw[2];      // FFT twiddles per axis (complex T)
-    size_t cn_vec;     // Scheme I: gmres_restart + 3 FP64 vectors (rhs, work, Krylov basis)
-    size_t cn_part;    // Scheme I: dot-product partials
-    size_t cn_coef;    // Scheme I: device coefficient vectors
+    size_t cn_vec;     // Scheme I: gmres_restart + 4 FP64 vectors (rhs, operator product x / y parts, basis)
+    size_t cn_part;    // Scheme I: reduction partials
+    size_t cn_coef;    // Scheme I: device solve state and Arnoldi coefficient records
     size_t cn_vecbytes;
     size_t partials;   // reduction partials (FP64)
     size_t out;        // small reduction outputs (FP64)
@@ -71,7 +71,6 @@ struct dirac_solver {
     int64_t cn_iters = 0;
     double cn_last_res = 0;
     int cn_cycle_len = 0;             // Arnoldi columns of the last GMRES cycle (batch size hint)
-    std::vector<double> cn_host;     // host source of the last GMRES update upload
     bool has_em = false;             // time-dependent potentials
     double em_charge = 0;
     dirac_envelope env_V{}, env_A{};

@@ -26,9 +26,21 @@ static void solve2d(int n, int prec, int kind, int pml, int scheme, bool em, int
     std::vector<double> psi((size_t)n * n * 4, 0.0);
     OK(dirac_set_initial_spinor(s, psi.data()));
     if (scheme == 0 && !em) OK(dirac_autotune(s, 2));
-    OK(dirac_step_n(s, 5));
-    OK(dirac_step_n(s, steps));
     dirac_obs o{};
+    if (scheme == DIRAC_SCHEME_CN_GMRES) {
+        // Scheme I keeps its solve state on the device; the stub runs no kernel, so
+        // the state read after the first cycle never shows convergence: the call
+        // must fail cleanly and put the solver back as it was
+        for (int k = 0; k < 2; ++k) {
+            const dirac_status r = dirac_step_n(s, k ? steps : 5);
+            if (r != DIRAC_OK && r != DIRAC_E_DEVICE) { std::printf("FAIL scheme I step: %d\n", r); std::exit(1); }
+            OK(dirac_observables(s, &o));
+            if (r != DIRAC_OK && o.step != 0) { std::printf("FAIL scheme I step count not restored\n"); std::exit(1); }
+        }
+    } else {
+        OK(dirac_step_n(s, 5));
+        OK(dirac_step_n(s, steps));
+    }
     OK(dirac_observables(s, &o));
     OK(dirac_observables_static(s, &o));
     if (scheme != DIRAC_SCHEME_CN_GMRES) {
