@@ -33,27 +33,32 @@ __host__ __device__ constexpr int cn_lines(int n, bool cols) {
 
 // Radix and lines per workgroup of both directions in the merged kernel: the
 // column rule, one workgroup shape (radix 4 with one line per workgroup at 512
-// points, twice the waves, measured 15% slower).
+// points, twice the waves, measured 15% slower), and one spinor component per
+// thread (kCn2Cpt).
 __host__ __device__ constexpr int cn2_radix(int n) { return cn_radix(n, true); }
 __host__ __device__ constexpr int cn2_lines(int n) { return cn_lines(n, true); }
+constexpr int kCn2Cpt = 1;
 
 // Tile shape of a pass: the row or column rule, or (M2) the merged kernel's.
 template <int N, bool COLS, bool M2 = false>
 struct CnTile {
     static constexpr int R = M2 ? cn2_radix(N) : cn_radix(N, COLS), L = M2 ? cn2_lines(N) : cn_lines(N, COLS);
-    using F = LineFFT<double, N, R, L, COLS, 2>;
+    static constexpr int CPT = M2 ? kCn2Cpt : 2;
+    using F = LineFFT<double, N, R, L, COLS, CPT>;
     static constexpr int NT = F::NT;
     static constexpr int LDS = F::LDS_ELEMS;
     static constexpr int TW = TwStage<double, N>::ELEMS;
 };
 
 // One tile of one direction of the transport operator (see CnApplyParams);
-// lds / twl: the workgroup's exchange buffer and twiddle stage.
+// lds / twl: the workgroup's exchange buffer and twiddle stage.  With one
+// component per thread (CPT = 1), a thread transforms its component k and
+// takes [[d]] v_{1-k}, which output component k needs, from its partner lane.
 template <int N, bool COLS, bool M2 = false>
 __device__ __forceinline__ void cn_apply_tile(const CnApplyParams& p, int tile, cpx<double>* lds, cpx<double>* twl) {
     using T = double;
-    constexpr int R = CnTile<N, COLS, M2>::R, L = CnTile<N, COLS, M2>::L;
-    using F = LineFFT<T, N, R, L, COLS, 2>;
+    constexpr int R = CnTile<N, COLS, M2>::R, L = CnTile<N, COLS, M2>::L, CPT = CnTile<N, COLS, M2>::CPT;
+    using F = typename CnTile<N, COLS, M2>::F;
     using TS = TwStage<T, N>;
     constexpr int P = F::P;
     const typename F::Coord c = F::coord(threadIdx.x);
@@ -65,14 +70,20 @@ __device__ __forceinline__ void cn_apply_tile(const CnApplyParams& p, int tile, 
         return COLS ? (uint32_t)pos * n1 + ln : (uint32_t)ln * n1 + pos;
     };
     // every global load goes out before the first wait
-    cpx<T> v[2][R], bq[COLS ? 1 : 2][COLS ? 1 : R];
+    cpx<T> v[CPT][R], bq[COLS ? 1 : CPT][COLS ? 1 : R];
     T d[R], bf[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) load_point(p.in, gidx(lline, c.j + r * P), v[0][r], v[1][r]);
+    for (int r = 0; r < R; ++r) {
+        if constexpr (CPT == 1) v[0][r] = load_comp(p.in, gidx(lline, c.j + r * P), c.comp);
+        else load_point(p.in, gidx(lline, c.j + r * P), v[0][r], v[1][r]);
+    }
     if constexpr (!COLS) {
         if (p.base == 2) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) load_point(p.b, gidx(lline, c.j + r * P), bq[0][r], bq[1][r]);
+            for (int r = 0; r < R; ++r) {
+                if constexpr (CPT == 1) bq[0][r] = load_comp(p.b, gidx(lline, c.j + r * P), c.comp);
+                else load_point(p.b, gidx(lline, c.j + r * P), bq[0][r], bq[1][r]);
+            }
         }
     }
     const cpx<T>* tw = p.tw;
@@ -98,54 +109,59 @@ __device__ __forceinline__ void cn_apply_tile(const CnApplyParams& p, int tile, 
     }
     if (p.in_norm) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            v[0][r] = scal(inv, v[0][r]);
-            v[1][r] = scal(inv, v[1][r]);
-        }
+        for (int cc = 0; cc < CPT; ++cc)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[cc][r] = scal(inv, v[cc][r]);
     }
-    cpx<T> in[COLS ? 1 : 2][COLS ? 1 : R];
+    cpx<T> in[COLS ? 1 : CPT][COLS ? 1 : R];
     if constexpr (!COLS) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            in[0][r] = v[0][r];
-            in[1][r] = v[1][r];
-        }
+        for (int cc = 0; cc < CPT; ++cc)
+#pragma unroll
+            for (int r = 0; r < R; ++r) in[cc][r] = v[cc][r];
         if (p.vout && valid) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) store_point(p.vout, gidx(line, c.j + r * P), v[0][r], v[1][r]);
+            for (int r = 0; r < R; ++r) {
+                if constexpr (CPT == 1) store_comp(p.vout, gidx(line, c.j + r * P), c.comp, v[0][r]);
+                else store_point(p.vout, gidx(line, c.j + r * P), v[0][r], v[1][r]);
+            }
         }
     }
     F::template fft<false, TS::ON>(v, lds, c, tw);
 #pragma unroll
-    for (int s = 0; s < R; ++s) {
-        v[0][s] = mul_i(scal(d[s], v[0][s]));
-        v[1][s] = mul_i(scal(d[s], v[1][s]));
-    }
+    for (int cc = 0; cc < CPT; ++cc)
+#pragma unroll
+        for (int s = 0; s < R; ++s) v[cc][s] = mul_i(scal(d[s], v[cc][s]));
     F::template fft<true, TS::ON>(v, lds, c, tw);
+    // sigma_i [[d_i]] v: rows (sigma_x) t0 = [[d]] v1, t1 = [[d]] v0; columns
+    // (sigma_y) t0 = -i [[d]] v1, t1 = i [[d]] v0
+    cpx<T> tq[CPT][R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if constexpr (CPT == 1) {
+            const cpx<T> w = partner(v[0][r]);         // [[d]] v_{1-k}
+            tq[0][r] = COLS ? (c.comp == 0 ? mul_mi(w) : mul_i(w)) : w;
+        } else {
+            tq[0][r] = COLS ? mul_mi(v[1][r]) : v[1][r];
+            tq[1][r] = COLS ? mul_i(v[0][r]) : v[0][r];
+        }
+    }
     if (!valid) return;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const uint32_t q = gidx(line, c.j + r * P);
         const T f = p.scale * bf[r];               // f c b
-        cpx<T> t0, t1;                             // sigma_i [[d_i]] v
-        if constexpr (!COLS) {
-            t0 = v[1][r];
-            t1 = v[0][r];
-        } else {
-            t0 = mul_mi(v[1][r]);
-            t1 = mul_i(v[0][r]);
-        }
-        cpx<T> o0 = scal(f, t0), o1 = scal(f, t1);
-        if constexpr (!COLS) {
-            if (p.base == 1) {
-                o0 = in[0][r] + o0;
-                o1 = in[1][r] + o1;
-            } else if (p.base == 2) {
-                o0 = (bq[0][r] - in[0][r]) + o0;
-                o1 = (bq[1][r] - in[1][r]) + o1;
+        cpx<T> o[CPT];
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+            o[cc] = scal(f, tq[cc][r]);
+            if constexpr (!COLS) {
+                if (p.base == 1) o[cc] = in[cc][r] + o[cc];
+                else if (p.base == 2) o[cc] = (bq[cc][r] - in[cc][r]) + o[cc];
             }
         }
-        store_point(p.out, q, o0, o1);
+        if constexpr (CPT == 1) store_comp(p.out, q, c.comp, o[0]);
+        else store_point(p.out, q, o[0], o[1]);
     }
 }
 
@@ -177,13 +193,13 @@ __global__ void __launch_bounds__((CnTile<N, true, true>::NT)) cn_apply2_kernel(
     else cn_apply_tile<N, true, true>(py, t - ntx, lds, twl);
 }
 
-// psi <- E psi (times = 1 or 2), E = [[e0, e1], [conj e1, conj e0]] per point, or the
-// uniform diagonal diag(e0u, conj e0u) when E is null.
-__global__ void cn_exp_kernel(double* psi, const double* E, double2 e0u, size_t npts, int times) {
+// psi <- E^times in (times = 1 or 2; psi may be in), E = [[e0, e1], [conj e1, conj e0]]
+// per point, or the uniform diagonal diag(e0u, conj e0u) when E is null.
+__global__ void cn_exp_kernel(const double* in, double* psi, const double* E, double2 e0u, size_t npts, int times) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
     cpx<double> u, v, e0{e0u.x, e0u.y}, e1{0, 0};
-    load_point(psi, (uint32_t)i, u, v);
+    load_point(in, (uint32_t)i, u, v);
     if (E) load_point(E, (uint32_t)i, e0, e1);
     for (int t = 0; t < times; ++t) {
         const cpx<double> nu = cmul(e0, u) + cmul(e1, v);
@@ -278,24 +294,42 @@ __device__ __forceinline__ zc zdiv(zc a, zc b) {
     return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
 }
 
-// Givens update of column j of the cycle's least-squares problem, by the whole
-// last workgroup (the state is staged in shared memory, thread 0 computes).
-// h: H_A(0..j, j) (complex, shared memory), hn: the norm of the new Arnoldi
-// vector.  Column j of H_G = I + (dt/2) H_A is rotated by the earlier
-// rotations, a new rotation zeroes its subdiagonal (dt/2) hn, and g, k, the
-// iteration count and the end-of-cycle flag are updated.
-__device__ void givens_column(CnCtrl* c, int j, const double* h, double hn) {
+// The scalars of the solve state a finishing workgroup reads, loaded by every
+// thread at the kernel's start together with the partial sums.
+struct CtrlSnap {
+    double hdt, tol, rtol;
+    zc gj;                // g_j (Givens update of column j)
+    int done, nonfinite, used, max_iter, m, k;
+};
+
+__device__ __forceinline__ CtrlSnap load_snap(const CnCtrl* c, int j, bool with_g) {
+    CtrlSnap q;
+    q.hdt = c->hdt;
+    q.tol = c->tol;
+    q.rtol = c->rtol;
+    q.gj = with_g ? zc{c->g[2 * j], c->g[2 * j + 1]} : zc{0.0, 0.0};
+    q.done = c->done;
+    q.nonfinite = c->nonfinite;
+    q.used = c->used;
+    q.max_iter = c->max_iter;
+    q.m = c->m;
+    q.k = c->k;
+    return q;
+}
+
+// Givens update of column j of the cycle's least-squares problem (thread 0; the
+// earlier rotations cs, sn are in shared memory).  h: H_A(0..j, j) (complex,
+// shared memory), hn: the norm of the new Arnoldi vector.  Column j of
+// H_G = I + (dt/2) H_A is rotated by the earlier rotations, a new rotation zeroes
+// its subdiagonal (dt/2) hn, and g, k, the iteration count and the end-of-cycle
+// flag are updated; the rotated column goes to R by the whole workgroup.
+__device__ void givens_column(CnCtrl* c, int j, const double* h, double hn, const CtrlSnap& q, const double* cs,
+                              const double* sn) {
     constexpr int M1 = kCnMaxRestart + 1;
-    __shared__ double cs[M1], sn[2 * M1], col[2 * M1];
-    __shared__ int skip;
-    if (threadIdx.x == 0) skip = c->done;
-    __syncthreads();
-    if (skip) return;                              // the cycle has already ended
-    const double hd = c->hdt;
+    __shared__ double col[2 * M1];
+    if (q.done) return;                            // the cycle has already ended (uniform)
+    const double hd = q.hdt;
     for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-        cs[i] = c->cs[i];
-        sn[2 * i] = c->sn[2 * i];
-        sn[2 * i + 1] = c->sn[2 * i + 1];
         col[2 * i] = hd * h[2 * i] + (i == j ? 1.0 : 0.0);
         col[2 * i + 1] = hd * h[2 * i + 1];
     }
@@ -329,14 +363,14 @@ __device__ void givens_column(CnCtrl* c, int j, const double* h, double hn) {
             col[2 * j] = d.re; col[2 * j + 1] = d.im;
             c->cs[j] = cj;
             c->sn[2 * j] = sj.re; c->sn[2 * j + 1] = sj.im;
-            const zc gj{c->g[2 * j], c->g[2 * j + 1]};
+            const zc gj = q.gj;
             const zc g1 = zscal(-1.0, zmul(zconj(sj), gj));
             c->g[2 * j + 2] = g1.re; c->g[2 * j + 3] = g1.im;
             c->g[2 * j] = cj * gj.re; c->g[2 * j + 1] = cj * gj.im;
             c->k = j + 1;
-            c->used += 1;
+            c->used = q.used + 1;
             const double est = zabs(g1);
-            if (sub == 0.0 || est <= c->tol || c->used >= c->max_iter || j + 1 >= c->m) c->done = 1;
+            if (sub == 0.0 || est <= q.tol || q.used + 1 >= q.max_iter || j + 1 >= q.m) c->done = 1;
         }
     }
     __syncthreads();
@@ -356,14 +390,13 @@ __device__ void start_cycle(CnCtrl* c, double beta) {
     c->g[1] = 0.0;
 }
 
-// Solver constants for the calls that follow; clears the ticket and the flags.
+// Solver constants for the calls that follow; clears the flags.
 __global__ void cn_init_kernel(CnCtrl* c, double hdt, double rtol, int max_iter, int m) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         c->hdt = hdt;
         c->rtol = rtol;
         c->max_iter = max_iter;
         c->m = m;
-        c->ticket = 0u;
         c->nonfinite = 0;
         c->done = 0;
         c->state = 0;
@@ -387,14 +420,12 @@ __global__ void __launch_bounds__(kCnThreads) cn_rhs_kernel(const double* rx, co
         X[i] = make_double2(2.0 * r.x - h.x, 2.0 * r.y - h.y);
         ar[0] += r.x * r.x + r.y * r.y;
     }
-    store_partials<1>(ar, ai, partials, 0);
+    store_partials<1>(ar, ai, partials, 1);       // slot 1: read with the first residual's (slot 0)
 }
 
 // r <- rx + ry (in ry) and ||r||^2; see launch_cn_residual.
-template <bool START>
 __global__ void __launch_bounds__(kCnThreads) cn_residual_kernel(const double* rx, double* ry, size_t ncplx,
-                                                                  double* partials, const CnCtrl* c) {
-    if (!START && c->done == 0) return;
+                                                                  double* partials) {
     double ar[1] = {0.0}, ai[1] = {0.0};
     const double2* RX = reinterpret_cast<const double2*>(rx);
     double2* RY = reinterpret_cast<double2*>(ry);
@@ -448,41 +479,68 @@ __global__ void __launch_bounds__(kCnThreads) cn_gs1_kernel(const double* V, siz
 }
 
 // What the finishing workgroup does with the final sums of a reduction.
-enum CnFinish { kFinRhs = 0, kFinResStart = 1, kFinRes = 2, kFinGs = 3 };
+// kFinStart: ||rhs||^2 in slot 1 and the first residual's norm in slot 0;
+// kFinRes: the residual after a cycle; kFinGs: the Gram-Schmidt dots of an iteration.
+enum CnFinish { kFinStart = 1, kFinRes = 2, kFinGs = 3 };
 
 // One workgroup after each reduction kernel: the final sums of its partials,
 // then the solve-state update of `kind` (thread 0) and, after the Gram-Schmidt
-// dots of an Arnoldi iteration, the Givens update of column j.
+// dots of an Arnoldi iteration, the Givens update of column j.  Every load of
+// the solve state is issued with the partials' loads (one memory round trip).
+// After a cycle (kFinRes), the head of the state is also written to `host`
+// (pinned host memory) for the host's verdict.
 __global__ void __launch_bounds__(kCnThreads) cn_finish_kernel(const double* partials, int nslots, int kind, int j,
-                                                                double* rec, CnCtrl* c) {
-    if (kind == kFinRes && c->done == 0) return;
+                                                                double* rec, CnCtrl* c, CnHead* host) {
+    constexpr int M1 = kCnMaxRestart + 1;
     __shared__ double s[2 * kCnSlots];
-    __shared__ double h[2 * (kCnMaxRestart + 1)];
+    __shared__ double h[2 * M1], cs[M1], sn[2 * M1];
     __shared__ double hn_s;
-    __shared__ int rotate;
+    const int t = threadIdx.x;
+    const bool gs = kind == kFinGs;
+    double pc = 0.0, pr = 0.0, pi = 0.0;
+    if (gs && t < j) {
+        pc = c->cs[t];
+        pr = c->sn[2 * t];
+        pi = c->sn[2 * t + 1];
+    }
+    const CtrlSnap q = load_snap(c, j, gs);
     final_sums(partials, nslots, s);
-    if (threadIdx.x == 0) {
-        rotate = 0;
-        if (kind == kFinRhs) {
-            c->bnorm = sqrt(s[0]);
-            c->tol = c->rtol * c->bnorm;
-            c->used = 0;
-            c->k = 0;
-            c->nonfinite = isfinite(s[0]) ? 0 : 1;
-        } else if (kind == kFinResStart || kind == kFinRes) {
+    // after a cycle's end: nothing to decide while the cycle goes on, nor when it
+    // ended with no column (the first residual met the tolerance; the update
+    // kernel wrote nothing)
+    const bool decide = kind != kFinRes || !(q.done == 0 || (q.k == 0 && !q.nonfinite));
+    if (gs && t < j) {
+        cs[t] = pc;
+        sn[2 * t] = pr;
+        sn[2 * t + 1] = pi;
+    }
+    if (t == 0 && decide) {
+        if (kind == kFinStart || kind == kFinRes) {
             const double r2 = s[0];
+            double tol = q.tol;
+            int nonfinite = q.nonfinite;
+            if (kind == kFinStart) {               // the step's right-hand side: counters reset
+                const double b2 = s[2];
+                tol = q.rtol * sqrt(b2);
+                nonfinite = isfinite(b2) ? 0 : 1;
+                c->bnorm = sqrt(b2);
+                c->tol = tol;
+                c->used = 0;
+                c->k = 0;                          // no column yet: the update leaves x as it is
+            }
             c->res2 = r2;
-            if (!isfinite(r2) || c->nonfinite) {
+            if (!isfinite(r2) || nonfinite) {
                 c->nonfinite = 1;
                 c->done = 1;
                 c->state = 3;
-            } else if (sqrt(r2) <= c->tol) {
+            } else if (sqrt(r2) <= tol) {
+                c->nonfinite = 0;
                 c->done = 1;
-                if (kind == kFinResStart) c->k = 0;   // no column: the update leaves x as it is
                 c->state = 2;
-            } else if (kind == kFinRes && c->used >= c->max_iter) {
+            } else if (kind == kFinRes && q.used >= q.max_iter) {
                 c->state = 3;
             } else {
+                c->nonfinite = 0;
                 start_cycle(c, sqrt(r2));
                 if (kind == kFinRes) c->state = 1;
             }
@@ -500,11 +558,14 @@ __global__ void __launch_bounds__(kCnThreads) cn_finish_kernel(const double* par
             c->hn = hn_s;
             h1[2 * (j + 1)] = hn_s;                // the subdiagonal entry, for the residual
             h1[2 * (j + 1) + 1] = 0.0;
-            rotate = 1;
         }
     }
     __syncthreads();
-    if (rotate) givens_column(c, j, h, hn_s);
+    if (gs) givens_column(c, j, h, hn_s, q, cs, sn);
+    if (host && t == 0) {                          // this thread wrote c's head above
+        const CnHead* hd = reinterpret_cast<const CnHead*>(c);
+        *host = *hd;
+    }
 }
 
 // V_{j+1} <- (w - sum_{k<=j} h_k V_k) / ctrl->hn (0 for hn = 0), j + 1 = 8 nfull +
@@ -557,37 +618,55 @@ __global__ void __launch_bounds__(kCnThreads) cn_update_kernel(const double* V, 
                                                                 double* x, double* r_out, size_t ncplx,
                                                                 const double* rec, double* partials,
                                                                 const CnCtrl* c) {
-    if (c->done == 0 || c->nonfinite) return;
     constexpr int M1 = kCnMaxRestart + 1;
+    // the least-squares state of up to nq = nv - 1 columns, packed: R column l
+    // (rows 0..l) at l (l + 1) / 2, H_A column j (rows 0..j + 1) at j (j + 3) / 2;
+    // loaded with the flags in one round before the gate
     __shared__ double y[2 * M1], g[2 * M1], cr[2 * (M1 + 1)];
-    __shared__ double R[2 * M1 * M1];
-    const int k = c->k;
+    __shared__ double Rp[M1 * (M1 - 1)], Hp[(M1 - 1) * (M1 + 2)];
+    const int nq = 8 * nfull + NKR - 1;
+    const int done = c->done, nonfinite = c->nonfinite, k = c->k;
+    const double beta = c->beta, hd = c->hdt;
     for (int i = threadIdx.x; i < 2 * M1; i += blockDim.x) {
         y[i] = 0.0;
-        g[i] = i < 2 * k ? c->g[i] : 0.0;
+        g[i] = i < 2 * nq ? c->g[i] : 0.0;
     }
     for (int i = threadIdx.x; i < 2 * (M1 + 1); i += blockDim.x) cr[i] = 0.0;
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {       // R(i, l), column-major
-        const int i = e % k, l = e / k;
-        R[2 * (l * M1 + i)] = c->R[2 * ((size_t)l * M1 + i)];
-        R[2 * (l * M1 + i) + 1] = c->R[2 * ((size_t)l * M1 + i) + 1];
+    for (int e = threadIdx.x; e < nq * nq; e += blockDim.x) {
+        const int i = e % nq, l = e / nq;
+        if (i <= l) {
+            const int o = l * (l + 1) / 2 + i;
+            Rp[2 * o] = c->R[2 * ((size_t)l * M1 + i)];
+            Rp[2 * o + 1] = c->R[2 * ((size_t)l * M1 + i) + 1];
+        }
     }
+    for (int e = threadIdx.x; e < nq * (nq + 1); e += blockDim.x) {
+        const int i = e % (nq + 1), j = e / (nq + 1);
+        if (i <= j + 1) {
+            const int o = j * (j + 3) / 2 + i;
+            Hp[2 * o] = rec[(size_t)j * kCnRecDoubles + 2 * i];
+            Hp[2 * o + 1] = rec[(size_t)j * kCnRecDoubles + 2 * i + 1];
+        }
+    }
+    if (done == 0 || nonfinite || k == 0) return;  // uniform; k = 0: converged before the cycle
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = k - 1; i >= 0; --i) {
             zc acc{g[2 * i], g[2 * i + 1]};
-            for (int l = i + 1; l < k; ++l)
-                acc = zsub(acc, zmul(zc{R[2 * (l * M1 + i)], R[2 * (l * M1 + i) + 1]}, zc{y[2 * l], y[2 * l + 1]}));
-            const zc q = zdiv(acc, zc{R[2 * (i * M1 + i)], R[2 * (i * M1 + i) + 1]});
+            for (int l = i + 1; l < k; ++l) {
+                const int o = l * (l + 1) / 2 + i;
+                acc = zsub(acc, zmul(zc{Rp[2 * o], Rp[2 * o + 1]}, zc{y[2 * l], y[2 * l + 1]}));
+            }
+            const int o = i * (i + 1) / 2 + i;
+            const zc q = zdiv(acc, zc{Rp[2 * o], Rp[2 * o + 1]});
             y[2 * i] = q.re;
             y[2 * i + 1] = q.im;
         }
         // residual coefficients: beta e_0 - H_G y, H_G(i, j) = delta_ij + hdt H_A(i, j) (i <= j),
-        // H_G(j + 1, j) = hdt hn_j, with column j of H_A and hn_j in record j
-        const double hd = c->hdt;
-        cr[0] = c->beta;
+        // H_G(j + 1, j) = hdt hn_j, with column j of H_A and hn_j from record j
+        cr[0] = beta;
         for (int j = 0; j < k; ++j) {
-            const double* hj = rec + (size_t)j * kCnRecDoubles;
+            const double* hj = Hp + j * (j + 3);
             const zc yj{y[2 * j], y[2 * j + 1]};
             for (int i = 0; i <= j; ++i) {
                 const zc h = zadd(zscal(hd, zc{hj[2 * i], hj[2 * i + 1]}), zc{i == j ? 1.0 : 0.0, 0.0});
@@ -677,8 +756,9 @@ hipError_t launch_cn_apply2(int n, const CnApplyParams& px, const CnApplyParams&
     return hipGetLastError();
 }
 
-hipError_t launch_cn_exp(double* psi, const double* E, double e0r, double e0i, size_t npts, int times, hipStream_t s) {
-    hipLaunchKernelGGL(cn_exp_kernel, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, psi, E,
+hipError_t launch_cn_exp(const double* in, double* out, const double* E, double e0r, double e0i, size_t npts,
+                         int times, hipStream_t s) {
+    hipLaunchKernelGGL(cn_exp_kernel, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, in, out, E,
                        make_double2(e0r, e0i), npts, times);
     return hipGetLastError();
 }
@@ -689,26 +769,24 @@ hipError_t launch_cn_init(CnCtrl* ctrl, double hdt, double rtol, int max_iter, i
 }
 
 static hipError_t finish(const double* partials, int nslots, CnFinish kind, int j, double* rec, CnCtrl* ctrl,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(cn_finish_kernel, dim3(1), dim3(kCnThreads), 0, s, partials, nslots, (int)kind, j, rec, ctrl);
+                         hipStream_t s, CnHead* host = nullptr) {
+    hipLaunchKernelGGL(cn_finish_kernel, dim3(1), dim3(kCnThreads), 0, s, partials, nslots, (int)kind, j, rec, ctrl,
+                       host);
     return hipGetLastError();
 }
 
 hipError_t launch_cn_rhs(const double* rx, const double* ry, double* rhs, double* x, size_t ncplx, double* partials,
-                         CnCtrl* ctrl, hipStream_t s) {
+                         hipStream_t s) {
     hipLaunchKernelGGL(cn_rhs_kernel, dim3(kCnDotBlocks), dim3(kCnThreads), 0, s, rx, ry, rhs, x, ncplx, partials);
-    return finish(partials, 1, kFinRhs, 0, nullptr, ctrl, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_cn_residual(const double* rx, double* ry, size_t ncplx, double* partials, CnCtrl* ctrl,
-                              bool start, hipStream_t s) {
-    if (start)
-        hipLaunchKernelGGL(cn_residual_kernel<true>, dim3(kCnDotBlocks), dim3(kCnThreads), 0, s, rx, ry, ncplx,
-                           partials, (const CnCtrl*)ctrl);
-    else
-        hipLaunchKernelGGL(cn_residual_kernel<false>, dim3(kCnDotBlocks), dim3(kCnThreads), 0, s, rx, ry, ncplx,
-                           partials, (const CnCtrl*)ctrl);
-    return finish(partials, 1, start ? kFinResStart : kFinRes, 0, nullptr, ctrl, s);
+                              hipStream_t s) {
+    hipLaunchKernelGGL(cn_residual_kernel, dim3(kCnDotBlocks), dim3(kCnThreads), 0, s, rx, ry, ncplx, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finish(partials, 2, kFinStart, 0, nullptr, ctrl, s);
 }
 
 // Gram-Schmidt dots of Arnoldi iteration j: with V_0 .. V_j in chunks of kCnChunk
@@ -759,7 +837,7 @@ hipError_t launch_cn_gs_update(double* V, size_t vstride, int j, const double* w
 }
 
 hipError_t launch_cn_update(const double* V, size_t vstride, int nk, double* x, double* r_out, size_t ncplx,
-                            const double* rec, double* partials, CnCtrl* ctrl, hipStream_t s) {
+                            const double* rec, double* partials, CnCtrl* ctrl, CnHead* host, hipStream_t s) {
     if (nk < 0 || nk > kCnMaxRestart) return hipErrorInvalidValue;
     const int nv = nk + 1, nfull = nv / 8;
 #define DIRAC_CN_XU(R)                                                                                           \
@@ -775,7 +853,7 @@ hipError_t launch_cn_update(const double* V, size_t vstride, int nk, double* x, 
 #undef DIRAC_CN_XU
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return finish(partials, 1, kFinRes, 0, nullptr, ctrl, s);
+    return finish(partials, 1, kFinRes, 0, nullptr, ctrl, s, host);
 }
 
 }  // namespace dirac

@@ -14,9 +14,10 @@ constexpr int kCnChunk = 8;           // basis vectors one reduction launch hand
 
 // Device-resident state of the GMRES solve of one step: the Hessenberg
 // least-squares problem after Givens rotations (R, cs, sn, g), the cycle's
-// counters and the stopping rule.  Written by the last workgroup of the
-// reduction kernels (and the init kernel) and read by the other kernels.
+// counters and the stopping rule.  Written by the single-workgroup finish
+// kernels (and the init kernel) and read by the other kernels.
 struct CnCtrl {
+    // head (CnHead): the fields the host reads after a cycle
     double beta;          // norm of the current cycle's starting residual
     double bnorm;         // ||rhs||
     double tol;           // rtol ||rhs||
@@ -33,13 +34,20 @@ struct CnCtrl {
     int state;            // 0 iterating, 1 restart needed, 2 converged, 3 out of iterations
     int nonfinite;
     int pad1;
-    unsigned ticket;      // last-workgroup counter of the reduction kernels (0 between kernels)
-    unsigned pad[3];
+    // the least-squares problem and the rest
+    unsigned pad2[4];
     double cs[kCnMaxRestart + 1];
     double sn[2 * (kCnMaxRestart + 1)];        // complex
     double g[2 * (kCnMaxRestart + 2)];         // complex
     double R[2 * (kCnMaxRestart + 1) * (kCnMaxRestart + 1)];   // complex, R(i, j) at 2 (j (m_max + 1) + i)
 };
+
+// The first 96 bytes of CnCtrl, which the host reads after a cycle.
+struct CnHead {
+    double beta, bnorm, tol, res2, hn, hdt, rtol, pad0;
+    int k, done, used, max_iter, m, state, nonfinite, pad1;
+};
+static_assert(sizeof(CnHead) == 96 && offsetof(CnCtrl, pad2) == sizeof(CnHead), "CnCtrl head layout");
 
 // Arnoldi coefficient record of iteration j: H_A(0..j, j) and the subdiagonal
 // entry H_A(j + 1, j) = hn_j in slot j + 1 (kCnMaxRestart + 1 complex slots).
@@ -71,7 +79,9 @@ hipError_t launch_cn_apply(int dir, int n, int nlines, const CnApplyParams& p, h
 // Both directions of a square n x n grid (n <= 512) in one launch (px: x pass,
 // py: y pass); the gate is px's.
 hipError_t launch_cn_apply2(int n, const CnApplyParams& px, const CnApplyParams& py, hipStream_t s);
-hipError_t launch_cn_exp(double* psi, const double* E, double e0r, double e0i, size_t npts, int times, hipStream_t s);
+// out <- E^times in per point (E = diag(e0, conj e0) when E is null); out may be in.
+hipError_t launch_cn_exp(const double* in, double* out, const double* E, double e0r, double e0i, size_t npts,
+                         int times, hipStream_t s);
 
 // The reductions below run kCnDotBlocks workgroups of 256 threads over the ncplx
 // complex entries of the vectors; each workgroup writes fixed-order partial
@@ -80,15 +90,15 @@ hipError_t launch_cn_exp(double* psi, const double* E, double e0r, double e0i, s
 
 // Constants of the stopping rule and the Hessenberg matrix for the calls that follow.
 hipError_t launch_cn_init(CnCtrl* ctrl, double hdt, double rtol, int max_iter, int m, hipStream_t s);
-// rhs <- rx + ry; x <- 2 rhs - x; bnorm = ||rhs||, tol = rtol bnorm; the step's counters reset.
+// rhs <- rx + ry; x <- 2 rhs - x; the partial sums of ||rhs||^2 (finished with
+// the first residual's).
 hipError_t launch_cn_rhs(const double* rx, const double* ry, double* rhs, double* x, size_t ncplx, double* partials,
-                         CnCtrl* ctrl, hipStream_t s);
-// r <- rx + ry (in ry); res2 = ||r||^2.  start = true: the step's first residual
-// (a new cycle starts from it unless it is already below tol); start = false:
-// the explicit residual after a cycle's update (gated on ctrl->done): the state
-// becomes converged, out of iterations, or restart (a new cycle from r).
+                         hipStream_t s);
+// The step's first residual r <- rx + ry (in ry), then with ||rhs|| (bnorm,
+// tol = rtol bnorm, the step's counters reset): converged if ||r|| <= tol, else
+// a new cycle from r.
 hipError_t launch_cn_residual(const double* rx, double* ry, size_t ncplx, double* partials, CnCtrl* ctrl,
-                              bool start, hipStream_t s);
+                              hipStream_t s);
 // Arnoldi iteration j (basis V, vstride doubles apart), classical Gram-Schmidt:
 // w <- wx + wy (in wx); h_k = <V_k, w> (k <= j), hn = ||w - V h||; the Givens
 // update of column j.
@@ -101,7 +111,8 @@ hipError_t launch_cn_gs_update(double* V, size_t vstride, int j, const double* w
 // workgroup, and the residual r = rhs - G x = V (beta e_0 - H_G y) from the
 // Arnoldi relation to r_out with its norm; then the verdict (converged, out of
 // iterations, or a restart from r).  nk = columns queued (>= the cycle's k).
+// Then the state head is written to `host` (pinned host memory), every time.
 hipError_t launch_cn_update(const double* V, size_t vstride, int nk, double* x, double* r_out, size_t ncplx,
-                            const double* rec, double* partials, CnCtrl* ctrl, hipStream_t s);
+                            const double* rec, double* partials, CnCtrl* ctrl, CnHead* host, hipStream_t s);
 
 }  // namespace dirac

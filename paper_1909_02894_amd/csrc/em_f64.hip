@@ -17,10 +17,10 @@ const EmEntry* em_entries_f64(int* count) {
     return e;
 }
 
-hipError_t launch_em_exp(double* psi, const double* rec, size_t npts, int times, const double* fA, const double* fV,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(em_exp_kernel<double>, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, psi, rec, npts,
-                       times, fA[0], fV[0], fA[1], fV[1]);
+hipError_t launch_em_exp(const double* in, double* out, const double* rec, size_t npts, int times, const double* fA,
+                         const double* fV, hipStream_t s) {
+    hipLaunchKernelGGL(em_exp_kernel<double>, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, in, out, rec,
+                       npts, times, fA[0], fV[0], fA[1], fV[1]);
     return hipGetLastError();
 }
 

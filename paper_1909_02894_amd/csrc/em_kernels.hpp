@@ -40,8 +40,8 @@ __host__ __device__ constexpr int em_lines(int n, bool cols) {
 __host__ __device__ constexpr int em_threads(int n, bool cols) { return (n / em_radix(n)) * em_lines(n, cols); }
 
 const EmEntry* em_entry(int prec, int n, int dir);
-hipError_t launch_em_exp(double* psi, const double* rec, size_t npts, int times, const double* fA, const double* fV,
-                         hipStream_t s);
+hipError_t launch_em_exp(const double* in, double* out, const double* rec, size_t npts, int times, const double* fA,
+                         const double* fV, hipStream_t s);
 
 struct Mat2 {
     cpx<double> m00, m01, m10, m11;
@@ -223,15 +223,16 @@ __global__ void __launch_bounds__(em_threads(N, COLS)) em_stage_kernel(EmParams<
     }
 }
 
-// psi <- E(t_k) psi for k < times (Scheme I with potentials), one thread per point.
+// out <- E(t_k) in for k < times (Scheme I with potentials), one thread per point
+// (out may be in).
 template <typename T>
-__global__ void em_exp_kernel(T* psi, const T* rec, size_t npts, int times, double fA0, double fV0, double fA1,
-                              double fV1) {
+__global__ void em_exp_kernel(const T* in, T* psi, const T* rec, size_t npts, int times, double fA0, double fV0,
+                              double fA1, double fV1) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
     cpx<T> u, v;
     double q[6], a;
-    load_point(psi, (uint32_t)i, u, v);
+    load_point(in, (uint32_t)i, u, v);
     load_record(rec, (uint32_t)i, q, a);
     if (times > 0) apply_mat(em_exponential(q, fA0, fV0), u, v);
     if (times > 1) apply_mat(em_exponential(q, fA1, fV1), u, v);

@@ -194,12 +194,13 @@ Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* 
     const size_t setup_parts = ((N + 255) / 256) * 3;
     const size_t obs_parts = ((size_t)g->n1 + g->n2) * 8;
     if (sc.scheme == DIRAC_SCHEME_CN_GMRES) {
-        // rhs, the two parts of an operator product, and the m + 1 basis vectors
+        // two sets (consecutive steps alternate) of: rhs, the two parts of an
+        // operator product and the m + 1 basis vectors; then the second state
         L.cn_vecbytes = align256(N * 32);
-        L.cn_vec = take(L.cn_vecbytes * (size_t)(sc.gmres_restart + 4));
+        L.cn_vec = take(L.cn_vecbytes * (2 * (size_t)(sc.gmres_restart + 4) + 1));
         L.cn_part = take((size_t)kCnDotBlocks * (kCnMaxRestart + 2) * 2 * 8);
-        // the device-resident solve state, then one coefficient record per iteration
-        L.cn_coef = take(align256(sizeof(CnCtrl)) + (size_t)sc.gmres_restart * kCnRecDoubles * 8);
+        // per set: the device-resident solve state, then one coefficient record per iteration
+        L.cn_coef = take(2 * (align256(sizeof(CnCtrl)) + (size_t)sc.gmres_restart * kCnRecDoubles * 8));
     } else {
         L.cn_vec = L.cn_part = L.cn_coef = SIZE_MAX;
         L.cn_vecbytes = 0;
@@ -836,6 +837,9 @@ dirac_status dirac_destroy(dirac_solver* s) {
     (void)hipStreamSynchronize(s->stream);      // nothing of this solve may be in flight
     drop_graph(s);
     for (auto& ev : s->events) (void)hipEventDestroy(ev);
+    for (auto& ev : s->cn_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (s->cn_head) (void)hipHostFree(s->cn_head);
     delete s;
     return DIRAC_OK;
 }

@@ -25,9 +25,10 @@ struct Layout {
     size_t K[2];       // directional symbols per axis (complex T)
     size_t D[2];       // derivative symbols per axis (T)
     size_t tw[2];      // FFT twiddles per axis (complex T)
-    size_t cn_vec;     // Scheme I: gmres_restart + 4 FP64 vectors (rhs, operator product x / y parts, basis)
+    size_t cn_vec;     // Scheme I: 2 sets of gmres_restart + 4 FP64 vectors (rhs, operator product x / y
+                       // parts, basis), then a second state vector
     size_t cn_part;    // Scheme I: reduction partials
-    size_t cn_coef;    // Scheme I: device solve state and Arnoldi coefficient records
+    size_t cn_coef;    // Scheme I: 2 sets of the device solve state and Arnoldi coefficient records
     size_t cn_vecbytes;
     size_t partials;   // reduction partials (FP64)
     size_t out;        // small reduction outputs (FP64)
@@ -71,6 +72,8 @@ struct dirac_solver {
     int64_t cn_iters = 0;
     double cn_last_res = 0;
     int cn_cycle_len = 0;             // Arnoldi columns of the last GMRES cycle (batch size hint)
+    void* cn_head = nullptr;          // pinned host copies of the two GMRES state heads
+    hipEvent_t cn_ev[2] = {nullptr, nullptr};
     bool has_em = false;             // time-dependent potentials
     double em_charge = 0;
     dirac_envelope env_V{}, env_A{};

@@ -162,3 +162,40 @@ def test_cn_reports_no_convergence(D):
         s.cn_set_limits(0, 1e-14)
     with pytest.raises(D.DiracError):
         s.autotune(2)
+
+
+def test_cn_zero_state_converges_before_any_iteration(D):
+    """psi = 0: every step's right-hand side and first residual are 0, which meets
+    the stopping rule with no Krylov column; the state stays exactly 0."""
+    spec = W.curved_bump(n=32, steps=4, m=1.0)
+    s = cn_solver(D, spec)
+    s.set_initial_spinor(np.zeros_like(W.initial_spinor(spec)))
+    s.step_n(4)
+    assert not np.any(s.get_spinor())
+    assert s.observables()["step"] == 4
+    assert s.cn_stats()[0] == 0
+
+
+def test_cn_loose_tolerance_keeps_the_initial_guess(D):
+    """A stopping rule that the first residual already meets (rtol 0.5; the
+    predictor's residual is 2 (dt/2)^2 A^2 psi): each step is Step 1, the initial
+    guess 2 G~ psi - psi of the solve, Step 3 -- built here from the oracle's
+    operators -- and no iteration runs.  Then the same solver with a tight rule
+    continues as the oracle does."""
+    spec = W.curved_bump(n=32, steps=3, m=1.0)
+    s = cn_solver(D, spec, rtol=0.5)
+    psi0 = W.initial_spinor(spec)
+    s.set_initial_spinor(psi0)
+    s.step_n(3)
+    assert s.cn_stats()[0] == 0
+    T = O.build_tables(oracle_problem(spec))
+    _, Gt = O.cn_operators(T)
+    psi = np.array(psi0, dtype=np.complex128)
+    for n in range(3):
+        E = O.step_exponential(T, n)
+        half = O.apply_pointwise(E, psi)
+        psi = O.apply_pointwise(E, 2.0 * Gt(half) - half)
+    assert O.rel_l2(s.get_spinor(), psi) < 1e-13
+    s.cn_set_limits(400, 1e-14)
+    s.step_n(2)
+    assert O.rel_l2(s.get_spinor(), O.cn_run(psi, T, 2, start=3)) < TOL
