@@ -20,7 +20,7 @@ namespace dirac {
 template <typename T>
 struct BatchDesc {
     T* psi;
-    const T* a;
+    const T* a[2];          // a(x) along rows, and transposed (along columns); null when flat
     const T* E;
     const T* inv_s[2];
     const cpx<T>* K[2];
@@ -104,7 +104,7 @@ __device__ __forceinline__ void batch_tile(const BatchDesc<T>& d, int tile, int 
     constexpr int dir = COLS ? 1 : 0;
     StageParams<T> p;
     p.psi = d.psi;
-    p.a = d.a;
+    p.a = d.a[dir];
     p.E = d.E;
     p.inv_s = d.inv_s[dir];
     p.K = d.K[dir];

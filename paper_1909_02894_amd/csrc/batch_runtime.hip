@@ -92,7 +92,8 @@ template <typename T>
 static void fill_desc(BatchDesc<T>& d, const dirac_solver* s, int steps, const int (&sched)[2][12]) {
     char* base = s->base;
     d.psi = reinterpret_cast<T*>(base + s->lay.psi);
-    d.a = s->curved ? reinterpret_cast<const T*>(base + s->lay.a) : nullptr;
+    d.a[0] = s->curved ? reinterpret_cast<const T*>(base + s->lay.a) : nullptr;
+    d.a[1] = s->curved ? reinterpret_cast<const T*>(base + s->lay.aT) : nullptr;
     d.E = s->curved ? reinterpret_cast<const T*>(base + s->lay.E) : nullptr;
     for (int ax = 0; ax < 2; ++ax) {
         d.inv_s[ax] = reinterpret_cast<const T*>(base + s->lay.inv_s[ax]);   // ones without a layer

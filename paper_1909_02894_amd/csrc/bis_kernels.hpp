@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(bis_threads(N, COLS)) bis_stage_kernel(BisPara
         T a = T(1), da = T(0);
         if constexpr (MODE == 2) {
             const uint32_t q = gidx(lline, pos);
-            a = ld_at(p.a, q);
+            a = ld_at(p.a, (uint32_t)lline * N + pos);   // a along this direction's lines
             da = ld_at(bp.da, 2 * q + dir);
         }
         b[r] = a * s;

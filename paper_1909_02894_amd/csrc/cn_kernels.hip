@@ -96,7 +96,7 @@ __device__ __forceinline__ void cn_apply_tile(const CnApplyParams& p, int tile, 
     }
     if (p.a) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) bf[r] = ld_at(p.a, gidx(lline, c.j + r * P)) * bf[r];
+        for (int r = 0; r < R; ++r) bf[r] = ld_at(p.a, (uint32_t)lline * N + c.j + r * P) * bf[r];
     }
     T inv = 1.0;
     if (p.in_norm) {

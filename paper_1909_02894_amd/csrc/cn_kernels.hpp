@@ -64,7 +64,7 @@ struct CnApplyParams {
     double* vout;            // x pass: the (divided) input, or null
     const double* b;         // base 2: b - v
     double* out;             // out_x (x pass) or out_y (y pass)
-    const double* a;         // a(x) per point, or null (a = 1)
+    const double* a;         // a(x) along this direction's lines (a[line * n + pos]), or null (a = 1)
     const double* inv_s;     // 1/S along the line direction (ones without a layer)
     const double* D;         // xi / n along the line direction
     const cpx<double>* tw;   // twiddles

@@ -78,7 +78,8 @@ hipError_t apply(const CnCtx& c, const double* in, const double* in_norm, double
         p.vout = dir == 0 ? vout : nullptr;
         p.b = bvec;
         p.out = dir == 0 ? c.wx : c.wy;
-        p.a = s->curved ? reinterpret_cast<const double*>(b + s->lay.a) : nullptr;
+        // a along this direction's lines (the transposed table for columns)
+        p.a = s->curved ? reinterpret_cast<const double*>(b + (dir == 0 ? s->lay.a : s->lay.aT)) : nullptr;
         p.inv_s = reinterpret_cast<const double*>(b + s->lay.inv_s[dir]);   // ones without a layer
         p.D = reinterpret_cast<const double*>(b + s->lay.D[dir]);
         p.tw = reinterpret_cast<const cpx<double>*>(b + s->lay.tw[dir]);

@@ -154,6 +154,13 @@ __host__ __device__ constexpr int ilog(int n, int r) {  // largest e with r^e | 
 }
 __host__ __device__ constexpr int ipow(int r, int e) { int v = 1; for (int i = 0; i < e; ++i) v *= r; return v; }
 
+// Largest LDS exchange buffer (bytes) that holds both spinor components of a
+// tile at once; larger tiles of threads carrying both exchange them one at a time.
+#ifndef DIRAC_LDS_BOTH_MAX
+#define DIRAC_LDS_BOTH_MAX (160 * 1024)
+#endif
+constexpr size_t kLdsBothMax = DIRAC_LDS_BOTH_MAX;
+
 // Exchange of a 32-bit value with the partner lane (lane xor 32) of the same
 // wave, with gfx950's v_permlane32_swap (upper half of the first operand <->
 // lower half of the second): lanes 0..31 find the partner's value in the second
@@ -199,10 +206,19 @@ struct LineFFT {
     // tile writes element (R j + s) L + l from lane (j, l): with 16 / R pads per
     // 16 elements, neighbouring j land L R + L elements apart, so the lanes of
     // one access cover distinct banks (one pad suffices for a single line).
+    // SEQ: when the layout of both components would not fit kLdsBothMax bytes, a
+    // thread carrying both (CPT = 2) exchanges them one after the other through
+    // a one-component buffer (twice the barriers, half the LDS; every value takes
+    // the same path, so results are bitwise the same).
     static constexpr int ROW_STRIDE = N + N / R;
-    static constexpr int COL_RAW = 2 * N * L;
     static constexpr int COL_PAD = (L == 1 || R >= 16) ? 1 : 16 / R;
-    static constexpr int LDS_ELEMS = (NPASS > 1) ? (COLS ? COL_RAW + (COL_RAW / 16) * COL_PAD : L * 2 * ROW_STRIDE) : 1;
+    __host__ __device__ static constexpr int lds_elems(int ncomp) {
+        return (NPASS > 1) ? (COLS ? ncomp * N * L + (ncomp * N * L / 16) * COL_PAD : L * ncomp * ROW_STRIDE) : 1;
+    }
+    static constexpr bool SEQ = CPT == 2 && lds_elems(2) * sizeof(cpx<T>) > kLdsBothMax;
+    static constexpr int NCL = SEQ ? 1 : 2;        // components held in LDS at once
+    static constexpr int LDS_ELEMS = lds_elems(NCL);
+    static_assert(LDS_ELEMS * sizeof(cpx<T>) <= 160 * 1024, "exchange buffer exceeds the LDS");
     static_assert(CPT == 1 || CPT == 2, "components per thread");
     static_assert(N % R == 0, "R must divide N");
     static_assert(NPASS == 1 ? N == R : E >= 2, "schedule needs radix-R first and last passes");
@@ -215,11 +231,12 @@ struct LineFFT {
         return ns;
     }
     __device__ static __forceinline__ int lidx(int l, int comp, int pos) {
+        const int cm = SEQ ? 0 : comp;
         if constexpr (COLS) {
-            const int a = (comp * N + pos) * L + l;
+            const int a = (cm * N + pos) * L + l;
             return a + (a / 16) * COL_PAD;
         } else {
-            return (l * 2 + comp) * ROW_STRIDE + pos + pos / R;
+            return (l * NCL + cm) * ROW_STRIDE + pos + pos / R;
         }
     }
     // Coordinates of physical thread t: component (CPT = 1), line within the
@@ -289,27 +306,36 @@ struct LineFFT {
                                                 const cpx<T>* __restrict__ tw) {
         constexpr int Rq = radix_of(PASS - 1), Nq = ns_of(PASS - 1);
         constexpr int Rp = radix_of(PASS), Ns = ns_of(PASS);
+        // components [c0, c1) through the buffer: all at once, or one at a time (SEQ)
+        auto exchange = [&](int c0, int c1) {
 #pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) {
+            for (int cc = c0; cc < c1; ++cc) {
 #pragma unroll
-            for (int t = 0; t < R / Rq; ++t) {
-                const int jj = c.j + t * P;
-                const int base = (jj / Nq) * Nq * Rq + (jj % Nq);
+                for (int t = 0; t < R / Rq; ++t) {
+                    const int jj = c.j + t * P;
+                    const int base = (jj / Nq) * Nq * Rq + (jj % Nq);
 #pragma unroll
-                for (int s = 0; s < Rq; ++s) lds[lidx(c.l, slot(c, cc), base + s * Nq)] = v[cc][t * Rq + s];
+                    for (int s = 0; s < Rq; ++s) lds[lidx(c.l, slot(c, cc), base + s * Nq)] = v[cc][t * Rq + s];
+                }
             }
-        }
-        __syncthreads();
+            __syncthreads();
 #pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) {
+            for (int cc = c0; cc < c1; ++cc) {
 #pragma unroll
-            for (int t = 0; t < R / Rp; ++t) {
-                const int jj = c.j + t * P;
+                for (int t = 0; t < R / Rp; ++t) {
+                    const int jj = c.j + t * P;
 #pragma unroll
-                for (int r = 0; r < Rp; ++r) v[cc][t * Rp + r] = lds[lidx(c.l, slot(c, cc), jj + r * (N / Rp))];
+                    for (int r = 0; r < Rp; ++r) v[cc][t * Rp + r] = lds[lidx(c.l, slot(c, cc), jj + r * (N / Rp))];
+                }
             }
+            __syncthreads();
+        };
+        if constexpr (SEQ) {
+            exchange(0, 1);
+            exchange(1, 2);
+        } else {
+            exchange(0, CPT);
         }
-        __syncthreads();
 #pragma unroll
         for (int t = 0; t < R / Rp; ++t) {
             const int jj = c.j + t * P;

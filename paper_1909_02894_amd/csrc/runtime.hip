@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cassert>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -178,6 +179,7 @@ Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* 
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     L.psi = take(N * 4 * sz);
     L.a = curved ? take(N * sz) : SIZE_MAX;
+    L.aT = curved ? take(N * sz) : SIZE_MAX;
     L.E = curved ? take(N * 4 * sz) : SIZE_MAX;
     L.da = curved && sc.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS ? take(N * 2 * sz) : SIZE_MAX;
     L.em = em ? take(N * 8 * sz) : SIZE_MAX;
@@ -280,13 +282,15 @@ StageParams<T> stage_params(const dirac_solver* s, int dir, int e_pre, int e_pos
     StageParams<T> p{};
     char* b = s->base;
     p.psi = reinterpret_cast<T*>(b + s->lay.psi);
-    p.a = s->curved ? reinterpret_cast<const T*>(b + s->lay.a) : nullptr;
+    // along this direction's lines: rows read a, columns its transpose
+    p.a = s->curved ? reinterpret_cast<const T*>(b + (dir == 0 ? s->lay.a : s->lay.aT)) : nullptr;
     p.E = s->curved ? reinterpret_cast<const T*>(b + s->lay.E) : nullptr;
     p.inv_s = reinterpret_cast<const T*>(b + s->lay.inv_s[dir]);     // ones without a layer
     p.K = reinterpret_cast<const cpx<T>*>(b + s->lay.K[dir]);
     p.tw = reinterpret_cast<const cpx<T>*>(b + s->lay.tw[dir]);
     p.n1 = s->g.n1;
     p.nlines = dir == 0 ? s->g.n2 : s->g.n1;
+    assert(dir == 0 || e_pre == 0);                 // Step 1 belongs to the row launch
     p.e_pre = e_pre;
     p.e_post = e_post;
     p.e0u = cpx<T>{(T)s->e0u_re, (T)s->e0u_im};
@@ -632,6 +636,10 @@ dirac_status dirac_create_solver(const dirac_grid* g, const dirac_metric* m, con
     double* fold = reinterpret_cast<double*>(b + lay.out);
     hipError_t e = launch_setup_points(pp, fold, s->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "setup point tables"));
+    if (s->curved) {
+        e = launch_transpose(b + lay.a, b + lay.aT, g->n1, g->n2, fp32 ? 4 : 8, s->stream);
+        if (e != hipSuccess) return bail(hip_fail(e, "transpose a"));
+    }
     double host_fold[3];
     e = hipMemcpyAsync(host_fold, fold, sizeof host_fold, hipMemcpyDeviceToHost, s->stream);
     if (e != hipSuccess) return bail(hip_fail(e, "read setup check"));

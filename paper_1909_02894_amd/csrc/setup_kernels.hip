@@ -267,6 +267,37 @@ __global__ void reduce_partials_kernel(const double* part, int nparts, double* o
 
 namespace dirac {
 
+// 32 x 32 tiles through LDS (one padding column against bank conflicts):
+// coalesced reads of in's rows and writes of out's rows.
+template <typename T>
+__global__ void transpose_kernel(const T* in, T* out, int n1, int n2) {
+    __shared__ T tile[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    for (int k = 0; k < 32; k += 8) {
+        const int r = r0 + ty + k, c = c0 + tx;
+        if (r < n2 && c < n1) tile[ty + k][tx] = in[(size_t)r * n1 + c];
+    }
+    __syncthreads();
+    for (int k = 0; k < 32; k += 8) {
+        const int c = c0 + ty + k, r = r0 + tx;
+        if (c < n1 && r < n2) out[(size_t)c * n2 + r] = tile[tx][ty + k];
+    }
+}
+
+hipError_t launch_transpose(const void* in, void* out, int n1, int n2, int elem, hipStream_t s) {
+    const dim3 grid((unsigned)((n1 + 31) / 32), (unsigned)((n2 + 31) / 32)), block(32, 8);
+    if (elem == 8)
+        hipLaunchKernelGGL(transpose_kernel<double>, grid, block, 0, s, static_cast<const double*>(in),
+                           static_cast<double*>(out), n1, n2);
+    else if (elem == 4)
+        hipLaunchKernelGGL(transpose_kernel<float>, grid, block, 0, s, static_cast<const float*>(in),
+                           static_cast<float*>(out), n1, n2);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_setup_axis(const SetupAxisParams& p, hipStream_t s) {
     hipLaunchKernelGGL(setup_axis_kernel, dim3((p.n + 255) / 256), dim3(256), 0, s, p);
     return hipGetLastError();

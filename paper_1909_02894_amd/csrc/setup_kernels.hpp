@@ -41,6 +41,8 @@ struct SetupPointParams {
 
 hipError_t launch_setup_axis(const SetupAxisParams& p, hipStream_t s);
 hipError_t launch_setup_points(const SetupPointParams& p, double* fold_out, hipStream_t s);
+// out[i][j] = in[j][i] for an n2 x n1 row-major array of `elem`-byte (4 or 8) values.
+hipError_t launch_transpose(const void* in, void* out, int n1, int n2, int elem, hipStream_t s);
 hipError_t launch_c128_to_f32(const double* src, float* dst, size_t count, hipStream_t s);
 hipError_t launch_f32_to_c128(const float* src, double* dst, size_t count, hipStream_t s);
 hipError_t launch_reduce_partials(const double* part, int nparts, double* out, hipStream_t s);

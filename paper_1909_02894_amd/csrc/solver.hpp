@@ -15,6 +15,7 @@ namespace dirac {
 struct Layout {
     size_t psi;        // state, n1 n2 points x 2 components x complex (T)
     size_t a;          // a(x) per point (T), curved metrics only
+    size_t aT;         // the same, transposed ([n1][n2]: contiguous along columns), for the y direction
     size_t E;          // Step-1 exponential per point, 4 T (curved only)
     size_t da;         // (d_x a, d_y a) per point, 2 T (second-order directional step, curved only)
     size_t em;         // per-point record of the time-dependent exponential, 8 T (potentials only)

@@ -22,7 +22,8 @@ namespace dirac {
 template <typename T>
 struct StageParams {
     T* psi;                      // state, 4 T per point, row pitch n1 points
-    const T* a;                  // a(x) per point, or null (a = 1)
+    const T* a;                  // a(x) per point along this direction's lines (row-major for x,
+                                 // the transposed table for y: a[line * n + pos]), or null (a = 1)
     const T* E;                  // half-step exponential per point (e0 re, im, e1 re, im), or null
     const T* inv_s;              // 1/S along the line direction (n entries; ones without a layer)
     const cpx<T>* K;             // symbol per mode, already scaled by 1/n
@@ -30,7 +31,8 @@ struct StageParams {
     int n1;                      // points per row
     int nlines;                  // lines of this direction
     int e_pre;                   // Step-1 exponentials applied before the transform: 1 or 2 in
-                                 // direction-x launches (which load E up front), 0 in direction y
+                                 // direction-x launches (which load E up front); direction-y
+                                 // kernels ignore it (0 there)
     int e_post;                  // Step-5 exponential applied after the blend (0, 1)
     cpx<T> e0u;                  // uniform e0 when E is null (flat: e^{-i dt m c^2 / 2})
     int wt;                      // 1: write-through state stores (rows; columns of n <= 1024)
@@ -60,6 +62,10 @@ struct ObsParams {
 template <typename T>
 __device__ __forceinline__ T ld_at(const T* base, uint32_t elem) {
     return gld(reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + elem * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* p) {
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) T*)p);
 }
 template <typename T>
 __device__ __forceinline__ const T* at(const T* base, uint32_t elem) {
@@ -170,6 +176,8 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     auto gidx = [&](int ln, int pos) -> uint32_t {
         return COLS ? (uint32_t)pos * n1 + ln : (uint32_t)ln * n1 + pos;
     };
+    // the a table is laid out along this direction's lines (transposed for columns)
+    auto aidx = [&](int ln, int pos) -> uint32_t { return (uint32_t)ln * N + pos; };
     // v[cc][r] <- f(own, other, component, r) for every carried component
     auto mix = [&](cpx<T> (&a)[CPT][R], auto&& f) {
 #pragma unroll
@@ -235,7 +243,9 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const T sv = gld(p.inv_s + c.j + r * P);
-                bb[r] = MODE == 2 ? ld_at(p.a, gidx(lline, c.j + r * P)) * sv : sv;
+                // a is read once per step: a streaming load keeps it from evicting
+                // the partly written row segments of neighbouring column tiles
+                bb[r] = MODE == 2 ? ld_nt(p.a + aidx(lline, c.j + r * P)) * sv : sv;
             }
         }
     };
@@ -251,12 +261,20 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     if constexpr (PRELOAD_E) {
         applyE(1);                                 // e_pre is 1 or 2 here
         if (p.e_pre > 1) applyE(1);
-    } else if (p.e_pre > 0) {
-        loadE();
-        applyE(p.e_pre);
+    } else if constexpr (!COLS) {                  // column launches never open with Step 1
+        if (p.e_pre > 0) {
+            loadE();
+            applyE(p.e_pre);
+        }
     }
+    // The blend needs the state before the transform.  Long column tiles, whose
+    // registers are the tightest, read it again from memory at the blend
+    // instead of holding it through both transforms (no other workgroup writes
+    // these points, and this one stores them only after the blend, and column
+    // launches apply no E before the transform, so the values are the same).
+    constexpr bool REREAD = BLEND && COLS && N * sizeof(cpx<T>) >= 32768;
     cpx<T> old[BLEND ? CPT : 1][BLEND ? R : 1];
-    if constexpr (BLEND) {
+    if constexpr (BLEND && !REREAD) {
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc)
 #pragma unroll
@@ -277,6 +295,14 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     F::template fft<true, TS::ON>(v, lds, c, tw);
 
     if constexpr (BLEND) {
+        if constexpr (REREAD) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t q = gidx(lline, c.j + r * P);
+                if constexpr (CPT == 1) old[0][r] = load_comp(p.psi, q, c.comp);
+                else load_point(p.psi, q, old[0][r], old[1][r]);
+            }
+        }
         if constexpr (!PF) blend_weights();
 #pragma unroll
         for (int r = 0; r < R; ++r) {

@@ -24,3 +24,4 @@ REG(4096, 16, 2, 1)
 REG(4096, 8, 2, 2)
 REGO(8192, 16, 1, 2)
 REG(8192, 16, 1, 1)
+REG(8192, 16, 2, 2)

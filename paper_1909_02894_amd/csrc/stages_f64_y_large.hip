@@ -21,3 +21,4 @@ REG(2048, 8, 1, 2)
 REG(2048, 8, 2, 1)
 REGO(4096, 8, 1, 2)
 REG(4096, 8, 1, 1)
+REG(4096, 8, 2, 2)
