@@ -308,6 +308,17 @@ dirac_status dirac_get_store_mode(const dirac_solver* s, int32_t* write_through)
  * HIP graph of 2 * graph_chunk stage kernels (default, chunk 32). */
 dirac_status dirac_set_launch_mode(dirac_solver* s, int32_t use_graph, int32_t graph_chunk);
 
+/* Where a solve with potentials (Sec. 2, F(t, x)) evaluates the Step-1 / Step-5
+ * exponentials E(t): form 1 = inside the direction kernels (one memory round
+ * trip per direction), 2 = in a pointwise pass of their own before the x kernel
+ * (and after the last y kernel) with the direction kernels in their plain
+ * form, 0 = by size (default: the pass when the state and the potential record,
+ * 12 reals a point, fit 128 MiB).  The two forms apply the same arithmetic in
+ * the same order.  DIRAC_E_ARG for a solver without potentials or another
+ * form.  dirac_get_potential_form reports 1 when the pass is in use, else 0. */
+dirac_status dirac_set_potential_form(dirac_solver* s, int32_t form);
+dirac_status dirac_get_potential_form(const dirac_solver* s, int32_t* pass);
+
 /* Advance nsteps like dirac_step_n with one kernel launch per stage, each
  * launched with its own start/stop HIP events (hipExtLaunchKernel), so the
  * durations are the kernels' execution times in the x, y, x, y ... order of a

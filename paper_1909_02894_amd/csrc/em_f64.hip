@@ -19,9 +19,15 @@ const EmEntry* em_entries_f64(int* count) {
 
 hipError_t launch_em_exp(const double* in, double* out, const double* rec, size_t npts, int times, const double* fA,
                          const double* fV, hipStream_t s) {
-    hipLaunchKernelGGL(em_exp_kernel<double>, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, in, out, rec,
-                       npts, times, fA[0], fV[0], fA[1], fV[1]);
+    if (times < 1 || times > 2) return hipErrorInvalidValue;
+    EmExpParams<double> p{in, out, rec, npts, times, {fA[0], fA[1]}, {fV[0], fV[1]}};
+    hipLaunchKernelGGL(em_exp_kernel<double>, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, s, p);
     return hipGetLastError();
+}
+
+const void* em_exp_fn(int prec) {
+    return prec == 0 ? reinterpret_cast<const void*>(&em_exp_kernel<double>)
+                     : reinterpret_cast<const void*>(&em_exp_kernel<float>);
 }
 
 }  // namespace dirac

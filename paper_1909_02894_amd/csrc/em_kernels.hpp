@@ -42,6 +42,9 @@ __host__ __device__ constexpr int em_threads(int n, bool cols) { return (n / em_
 const EmEntry* em_entry(int prec, int n, int dir);
 hipError_t launch_em_exp(const double* in, double* out, const double* rec, size_t npts, int times, const double* fA,
                          const double* fV, hipStream_t s);
+// The pointwise exponential kernel (em_exp_kernel<double / float>), for launch
+// descriptions built by the runtime.
+const void* em_exp_fn(int prec);
 
 struct Mat2 {
     cpx<double> m00, m01, m10, m11;
@@ -223,20 +226,30 @@ __global__ void __launch_bounds__(em_threads(N, COLS)) em_stage_kernel(EmParams<
     }
 }
 
-// out <- E(t_k) in for k < times (Scheme I with potentials), one thread per point
-// (out may be in).
+// out <- E(t_1) E(t_0) in (times = 2) or E(t_0) in (times = 1), one thread per
+// point (out may be in): Steps 1 / 5 with potentials, as a pass of their own
+// (Scheme I, and Scheme II on states small enough to stay in the caches, where
+// the direction kernels then run in their plain form).
 template <typename T>
-__global__ void em_exp_kernel(const T* in, T* psi, const T* rec, size_t npts, int times, double fA0, double fV0,
-                              double fA1, double fV1) {
+struct EmExpParams {
+    const T* in;
+    T* out;
+    const T* rec;
+    size_t npts;
+    int times;
+    double fA[2], fV[2];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256) em_exp_kernel(EmExpParams<T> p) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= npts) return;
+    if (i >= p.npts) return;
     cpx<T> u, v;
     double q[6], a;
-    load_point(in, (uint32_t)i, u, v);
-    load_record(rec, (uint32_t)i, q, a);
-    if (times > 0) apply_mat(em_exponential(q, fA0, fV0), u, v);
-    if (times > 1) apply_mat(em_exponential(q, fA1, fV1), u, v);
-    store_point(psi, (uint32_t)i, u, v);
+    load_point(p.in, (uint32_t)i, u, v);
+    load_record(p.rec, (uint32_t)i, q, a);
+    for (int k = 0; k < p.times; ++k) apply_mat(em_exponential(q, p.fA[k], p.fV[k]), u, v);
+    store_point(p.out, (uint32_t)i, u, v);
 }
 
 }  // namespace dirac

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 #include <map>
 #include <mutex>
 #include <new>
@@ -248,7 +249,8 @@ int solver_mode(const dirac_solver* s) { return (s->curved ? 2 : 0) + (s->pml ? 
 // Tuning-cache mode: the kernel mode plus the kernel family (the corrected
 // second-order step and the potential kernels are tuned apart).
 int tune_mode(const dirac_solver* s) {
-    return solver_mode(s) + (s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS ? 4 : 0) + (s->has_em ? 8 : 0);
+    return solver_mode(s) + (s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS ? 4 : 0) +
+           (s->has_em && !em_pass(s) ? 8 : 0);
 }
 
 // Whether the direction kernel carries the write-through store path (every
@@ -331,6 +333,22 @@ EmParams<T> em_params(const dirac_solver* s, int dir, int e_pre, int e_post, int
 
 static constexpr size_t kMaxParams = sizeof(BisParams<double>) > sizeof(EmParams<double>) ? sizeof(BisParams<double>)
                                                                                           : sizeof(EmParams<double>);
+static_assert(sizeof(EmExpParams<double>) <= kMaxParams, "parameter block");
+
+// States whose per-point data (state + potential record, 12 reals a point) fit
+// this many bytes run the potentials' exponentials as a pointwise pass of
+// their own, at full occupancy, with the direction kernels in their plain form:
+// the data stays in the Infinity Cache, so the extra pass is cheap, while the
+// exponentials inside the direction kernels lengthen their latency-bound chains.
+// Larger states keep them in the direction kernels (one HBM round trip less).
+constexpr size_t kEmPassMaxBytes = size_t(128) << 20;
+
+bool em_pass(const dirac_solver* s) {
+    if (!s->has_em) return false;
+    if (s->em_form != 0) return s->em_form == 2;
+    const size_t N = (size_t)s->g.n1 * s->g.n2;
+    return N * 12 * (s->prec == DIRAC_FP32 ? 4 : 8) <= kEmPassMaxBytes;
+}
 
 // One stage launch description (kernel + by-value parameter block).
 struct Launch {
@@ -344,7 +362,10 @@ struct Launch {
 // the potentials; unused otherwise).
 Launch make_launch(const dirac_solver* s, int dir, int e_pre, int e_post, int64_t step = 0) {
     Launch L{};
-    if (s->has_em) {
+    if (em_pass(s)) {              // the exponentials run in their own pass (make_exp_launch)
+        e_pre = 0;
+        e_post = 0;
+    } else if (s->has_em) {
         const int nlines = dir == 0 ? s->g.n2 : s->g.n1;
         const EmEntry* e = em_entry(s->prec, dir == 0 ? s->g.n1 : s->g.n2, dir);
         L.fn = e->fn;
@@ -396,6 +417,34 @@ Launch make_launch(const dirac_solver* s, int dir, int e_pre, int e_post, int64_
     return L;
 }
 
+// The pointwise potentials pass: Step 5 of step - 1 and Step 1 of step
+// (times = 2, at t_{step-1/2} and t_{step+1/2}), Step 1 alone (times = 1,
+// t_{step+1/2}), or Step 5 after the last step (closing, t_{step+1/2}).
+Launch make_exp_launch(const dirac_solver* s, int times, int64_t step) {
+    Launch L{};
+    const size_t npts = (size_t)s->g.n1 * s->g.n2;
+    const double dt = s->g.dt;
+    const double t[2] = {times == 2 ? (step - 0.5) * dt : (step + 0.5) * dt, (step + 0.5) * dt};
+    L.fn = em_exp_fn(s->prec == DIRAC_FP64 ? 0 : 1);
+    L.grid = dim3((unsigned)((npts + 255) / 256));
+    L.block = dim3(256);
+    auto fill = [&](auto* psi, auto* rec) {
+        using T = std::remove_const_t<std::remove_pointer_t<decltype(rec)>>;
+        EmExpParams<T> p{psi, psi, rec, npts, times, {0, 0}, {0, 0}};
+        for (int k = 0; k < times; ++k) {
+            p.fA[k] = envelope_at(s->env_A, t[k]);
+            p.fV[k] = envelope_at(s->env_V, t[k]);
+        }
+        std::memcpy(L.params, &p, sizeof p);
+        L.psize = sizeof p;
+    };
+    if (s->prec == DIRAC_FP64)
+        fill(reinterpret_cast<double*>(s->base + s->lay.psi), reinterpret_cast<const double*>(s->base + s->lay.em));
+    else
+        fill(reinterpret_cast<float*>(s->base + s->lay.psi), reinterpret_cast<const float*>(s->base + s->lay.em));
+    return L;
+}
+
 static hipError_t do_launch(Launch& L, hipStream_t st) {
     void* args[] = {L.params};
     return hipLaunchKernel(L.fn, L.grid, L.block, args, 0, st);
@@ -442,6 +491,20 @@ static dirac_status build_graph(dirac_solver* s) {
 dirac_status enqueue_steps(dirac_solver* s, int64_t nsteps, bool allow_graph) {
     if (nsteps <= 0) return DIRAC_OK;
     hipStream_t st = s->stream;
+    if (em_pass(s)) {
+        // the potentials' time enters the pass's parameters: direct launches
+        const int64_t n0 = s->step;
+        Launch lx = make_launch(s, 0, 0, 0), ly = make_launch(s, 1, 0, 0);
+        for (int64_t k = 0; k < nsteps; ++k) {
+            Launch le = make_exp_launch(s, k == 0 ? 1 : 2, n0 + k);
+            HIP_TRY(do_launch(le, st), "launch potentials pass");
+            HIP_TRY(do_launch(lx, st), "launch x stage");
+            HIP_TRY(do_launch(ly, st), "launch y stage");
+        }
+        Launch lc = make_exp_launch(s, 1, n0 + nsteps - 1);
+        HIP_TRY(do_launch(lc, st), "launch potentials pass");
+        return DIRAC_OK;
+    }
     if (s->has_em) {
         // the potentials' time enters every launch's parameters: direct launches
         const int64_t n0 = s->step;
@@ -915,6 +978,27 @@ dirac_status dirac_get_store_mode(const dirac_solver* s, int32_t* write_through)
     return DIRAC_OK;
 }
 
+dirac_status dirac_set_potential_form(dirac_solver* s, int32_t form) {
+    if (!s) return fail(DIRAC_E_ARG, "null solver");
+    if (!s->has_em) return fail(DIRAC_E_ARG, "the solver has no potentials");
+    if (form < 0 || form > 2) return fail(DIRAC_E_ARG, "form must be 0, 1 or 2");
+    (void)hipStreamSynchronize(s->stream);
+    s->em_form = form;
+    // the kernels of the new form with the schedules and store modes tuned for it
+    const int mode = tune_mode(s);
+    s->sched[0] = pick_entry(s->prec, s->g.n1, 0, s->g.n2, mode);
+    s->sched[1] = pick_entry(s->prec, s->g.n2, 1, s->g.n1, mode);
+    s->store_wt[0] = store_wt_compiled(s, 0) && pick_store_mode(s->prec, s->g.n1, 0, s->g.n2, mode);
+    s->store_wt[1] = store_wt_compiled(s, 1) && pick_store_mode(s->prec, s->g.n2, 1, s->g.n1, mode);
+    return DIRAC_OK;
+}
+
+dirac_status dirac_get_potential_form(const dirac_solver* s, int32_t* pass) {
+    if (!s || !pass) return fail(DIRAC_E_ARG, "null argument");
+    *pass = em_pass(s) ? 1 : 0;
+    return DIRAC_OK;
+}
+
 dirac_status dirac_set_launch_mode(dirac_solver* s, int32_t use_graph, int32_t chunk) {
     if (!s || chunk < 1 || chunk > 4096) return fail(DIRAC_E_ARG, "bad arguments");
     s->use_graph = use_graph != 0;
@@ -935,30 +1019,49 @@ dirac_status dirac_step_n_timed(dirac_solver* s, int64_t nsteps, double* ms_out,
     // timestamps are those of the kernel dispatch itself, so the durations are
     // kernel execution times in the real x, y, x, y ... order, with no extra
     // packets between the launches
-    const size_t nl = (size_t)nsteps * 2;
+    // with a separate potentials pass, the pass before a step's x kernel counts
+    // toward the x class (Steps 5 and 1 belong to it) and the closing pass
+    // toward the last y
+    const bool pass = em_pass(s);
+    const size_t nl = (size_t)nsteps * (pass ? 3 : 2) + (pass ? 1 : 0);
     while (s->events.size() < 2 * nl) {
         hipEvent_t ev;
         HIP_TRY(hipEventCreate(&ev), "hipEventCreate");
         s->events.push_back(ev);
     }
     hipStream_t st = s->stream;
+    std::vector<int> cls;                   // per launch: class, +2 when it is the step's kernel (counted)
+    cls.reserve(nl);
     size_t k = 0;
+    auto timed = [&](Launch& L, int c) -> dirac_status {
+        void* args[] = {L.params};
+        HIP_TRY(hipExtLaunchKernel(L.fn, L.grid, L.block, args, 0, st, s->events[2 * k], s->events[2 * k + 1], 0),
+                "launch stage");
+        cls.push_back(c);
+        ++k;
+        return DIRAC_OK;
+    };
     for (int64_t n = 0; n < nsteps; ++n) {
+        dirac_status r;
+        if (pass) {
+            Launch le = make_exp_launch(s, n == 0 ? 1 : 2, s->step + n);
+            if ((r = timed(le, 0)) != DIRAC_OK) return r;
+        }
         Launch lx = make_launch(s, 0, n == 0 ? 1 : 2, 0, s->step + n);
         Launch ly = make_launch(s, 1, 0, n == nsteps - 1 ? 1 : 0, s->step + n);
-        for (Launch* L : {&lx, &ly}) {
-            void* args[] = {L->params};
-            HIP_TRY(hipExtLaunchKernel(L->fn, L->grid, L->block, args, 0, st, s->events[2 * k],
-                                       s->events[2 * k + 1], 0), "launch stage");
-            ++k;
-        }
+        if ((r = timed(lx, 2)) != DIRAC_OK || (r = timed(ly, 3)) != DIRAC_OK) return r;
+    }
+    if (pass) {
+        Launch lc = make_exp_launch(s, 1, s->step + nsteps - 1);
+        dirac_status r = timed(lc, 1);
+        if (r != DIRAC_OK) return r;
     }
     HIP_TRY(hipStreamSynchronize(st), "synchronise");
     for (size_t i = 0; i < k; ++i) {
         float ms = 0;
         HIP_TRY(hipEventElapsedTime(&ms, s->events[2 * i], s->events[2 * i + 1]), "hipEventElapsedTime");
-        ms_out[i & 1] += ms;
-        counts_out[i & 1] += 1;
+        ms_out[cls[i] & 1] += ms;
+        if (cls[i] & 2) counts_out[cls[i] & 1] += 1;
     }
     s->step += nsteps;
     return DIRAC_OK;
@@ -978,23 +1081,28 @@ dirac_status dirac_time_directions(dirac_solver* s, int32_t reps, double* us_out
     if (hipEventCreate(&ev[1]) != hipSuccess) { (void)hipEventDestroy(ev[0]); return fail(DIRAC_E_DEVICE, "hipEventCreate"); }
     dirac_status result = DIRAC_OK;
     for (int dir = 0; dir < 2 && result == DIRAC_OK; ++dir) {
-        Launch L = make_launch(s, dir, dir == 0 ? 2 : 0, 0, s->step);
+        // the x class includes the potentials pass (Steps 5 and 1) when it is separate
+        std::vector<Launch> Ls;
+        if (dir == 0 && em_pass(s)) Ls.push_back(make_exp_launch(s, 2, s->step));
+        Ls.push_back(make_launch(s, dir, dir == 0 ? 2 : 0, 0, s->step));
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         auto step = [&]() -> dirac_status {
             HIP_TRY(hipGraphCreate(&graph, 0), "hipGraphCreate");
             hipGraphNode_t prev = nullptr;
             for (int k = 0; k < reps; ++k) {
-                void* args[] = {L.params};
-                hipKernelNodeParams kp{};
-                kp.func = const_cast<void*>(L.fn);
-                kp.gridDim = L.grid;
-                kp.blockDim = L.block;
-                kp.kernelParams = args;
-                hipGraphNode_t node;
-                HIP_TRY(hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp),
-                        "hipGraphAddKernelNode");
-                prev = node;
+                for (Launch& L : Ls) {
+                    void* args[] = {L.params};
+                    hipKernelNodeParams kp{};
+                    kp.func = const_cast<void*>(L.fn);
+                    kp.gridDim = L.grid;
+                    kp.blockDim = L.block;
+                    kp.kernelParams = args;
+                    hipGraphNode_t node;
+                    HIP_TRY(hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp),
+                            "hipGraphAddKernelNode");
+                    prev = node;
+                }
             }
             HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
             HIP_TRY(hipGraphLaunch(exec, st), "hipGraphLaunch");          // warm
@@ -1024,7 +1132,7 @@ dirac_status dirac_autotune(dirac_solver* s, int32_t reps) {
         return fail(DIRAC_E_ARG, "the autotuner applies to Scheme II's directional steps");
     // the corrected second-order step and the potential kernels have one
     // schedule each: only their store modes are searched
-    const bool one_schedule = s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || s->has_em;
+    const bool one_schedule = s->scheme.scheme == DIRAC_SCHEME_EXP_SPLIT_2BIS || (s->has_em && !em_pass(s));
     if (!s->has_state) return fail(DIRAC_E_STATE, "set the initial spinor first");
     const size_t N = (size_t)s->g.n1 * s->g.n2;
     const size_t bytes = N * 4 * (s->prec == DIRAC_FP32 ? 4 : 8);

@@ -44,6 +44,9 @@ Layout make_layout(const dirac_grid* g, const dirac_metric* m, const dirac_pml* 
 double envelope_at(const dirac_envelope& e, double t);
 dirac_scheme scheme_or_default(const dirac_scheme* sc);
 dirac_status cn_step_n(dirac_solver* s, int64_t nsteps);
+// Whether a solve with potentials runs its exponentials as a pointwise pass
+// (plain direction kernels) rather than inside the direction kernels.
+bool em_pass(const dirac_solver* s);
 const KernelEntry* pick_entry(int prec, int n, int dir, int other, int mode);
 
 }  // namespace dirac
@@ -76,6 +79,7 @@ struct dirac_solver {
     void* cn_head = nullptr;          // pinned host copies of the two GMRES state heads
     hipEvent_t cn_ev[2] = {nullptr, nullptr};
     bool has_em = false;             // time-dependent potentials
+    int em_form = 0;                 // 0: by size, 1: exponentials inside the x / y kernels, 2: a pointwise pass
     double em_charge = 0;
     dirac_envelope env_V{}, env_A{};
 };

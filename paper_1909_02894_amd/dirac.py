@@ -126,6 +126,8 @@ SIGNATURES = {
     "dirac_get_schedule": (C.c_int32, [_vp, C.c_int32, C.POINTER(Schedule)]),
     "dirac_set_schedule": (C.c_int32, [_vp, C.c_int32, C.POINTER(Schedule)]),
     "dirac_set_launch_mode": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
+    "dirac_set_potential_form": (C.c_int32, [_vp, C.c_int32]),
+    "dirac_get_potential_form": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
     "dirac_set_store_mode": (C.c_int32, [_vp, C.c_int32]),
     "dirac_get_store_mode": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
     "dirac_step_n_timed": (C.c_int32, [_vp, C.c_int64, _dp, C.POINTER(C.c_int64)]),
@@ -390,6 +392,15 @@ class Solver:
 
     def set_launch_mode(self, use_graph: bool, chunk: int = 32):
         _check(lib.dirac_set_launch_mode(self.h, int(use_graph), chunk))
+
+    def set_potential_form(self, form: int):
+        """Potentials: 0 by size, 1 exponentials inside the direction kernels, 2 a pointwise pass."""
+        _check(lib.dirac_set_potential_form(self.h, int(form)))
+
+    def potential_pass(self) -> bool:
+        v = C.c_int32()
+        _check(lib.dirac_get_potential_form(self.h, C.byref(v)))
+        return bool(v.value)
 
     def store_mode(self) -> int:
         """Write-through mask of the direction kernels' state stores: bit 0 x, bit 1 y."""

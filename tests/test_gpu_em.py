@@ -1,6 +1,7 @@
 """GPU parity with time-dependent electromagnetic potentials (Sec. 2, F(t, x)
-with A and A0): the in-kernel Step 1 / Step 5 exponential at t_{n+1/2} against
-the oracle's half_step_exponential_em, for Scheme II (plain and printed
+with A and A0): the Step 1 / Step 5 exponential at t_{n+1/2} -- inside the
+direction kernels (form 1) or in a pointwise pass of its own (form 2) --
+against the oracle's half_step_exponential_em, for Scheme II (plain and printed
 directional steps) and Scheme I, FP64 and FP32, and the observables' energy
 with the potential terms.
 
@@ -37,8 +38,11 @@ def potentials(spec, seed=3, uniform_V=None):
             "env_V": (0.5, 1.0, 6.0, 0.3, 0.0, 0.0), "env_A": (-0.2, 2.0, 9.0, 0.1, 0.05, 0.04)}
 
 
-def gpu(D, spec, steps, pot, precision=0, split=(), **kw):
+def gpu(D, spec, steps, pot, precision=0, split=(), form=0, **kw):
     s = D.Solver.from_spec(spec, precision=precision, potentials=pot, **kw)
+    if form:
+        s.set_potential_form(form)
+        assert s.potential_pass() == (form == 2)
     s.set_initial_spinor(W.initial_spinor(spec))
     done = 0
     for k in sorted(set(split) | {steps}):
@@ -47,11 +51,12 @@ def gpu(D, spec, steps, pot, precision=0, split=(), **kw):
     return s, s.get_spinor()
 
 
+@pytest.mark.parametrize("form", [1, 2])
 @pytest.mark.parametrize("m", [0.0, 1.0])
-def test_em_curved_bump_with_layer_fp64(D, m):
+def test_em_curved_bump_with_layer_fp64(D, m, form):
     spec = W.curved_bump(n=64, steps=12, m=m)
     pot = potentials(spec)
-    s, g = gpu(D, spec, 12, pot, split=(1, 5))
+    s, g = gpu(D, spec, 12, pot, split=(1, 5), form=form)
     T = O.build_tables(oracle_problem(spec, potentials=pot))
     ref = O.run(W.initial_spinor(spec), T, 12)
     assert O.rel_l2(g, ref) < TOL64
@@ -63,12 +68,13 @@ def test_em_curved_bump_with_layer_fp64(D, m):
     assert abs(ob["energy_im"] - ro.energy_im) <= 1e-10 * max(1.0, abs(ro.energy_re))
 
 
+@pytest.mark.parametrize("form", [1, 2])
 @pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL32)])
-def test_em_full_size_grid(D, precision, tol):
+def test_em_full_size_grid(D, precision, tol, form):
     # the benchmark's 512^2 grid: one row or two columns per workgroup
     spec = W.curved_bump(n=512, seed=1909, steps=3, m=1.0)
     pot = potentials(spec, seed=11)
-    _, g = gpu(D, spec, 3, pot, precision=precision, split=(1,))
+    _, g = gpu(D, spec, 3, pot, precision=precision, split=(1,), form=form)
     ref = O.run(W.initial_spinor(spec), O.build_tables(oracle_problem(spec, potentials=pot)), 3)
     assert O.rel_l2(g, ref) < tol
 
@@ -137,3 +143,49 @@ def test_em_store_modes_are_bitwise_and_tuned(D):
     assert s.observables()["step"] == 0
     s.step_n(7)
     assert np.array_equal(s.get_spinor(), outs[0])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_em_forms_agree_bitwise(D, precision):
+    """The pointwise pass and the in-kernel exponentials apply the same arithmetic
+    in the same order (the state is stored in its own precision in between), so
+    with direction kernels of the same radix as the potential kernels (4) the two
+    forms give the same bits, here on a rectangular grid with a layer, steps
+    split over calls, and the per-launch timed path."""
+    spec = W.curved_bump(n=128, steps=9, m=0.7)
+    spec.n2 = 64
+    pot = potentials(spec, seed=5)
+    out = {}
+    for form in (1, 2):
+        s = D.Solver.from_spec(spec, precision=precision, potentials=pot)
+        s.set_potential_form(form)
+        for d, n in ((0, spec.n1), (1, spec.n2)):
+            r, lines, cpt = next(sc for sc in D.schedules(n, precision, d) if sc[0] == 4)
+            s.set_schedule(d, r, lines, cpt)
+        s.set_initial_spinor(W.initial_spinor(spec))
+        for k in (2, 3, 4):
+            s.step_n(k)
+        s.step_n_timed(3)
+        out[form] = s.get_spinor()
+        s.close()
+    assert np.array_equal(out[1], out[2])
+
+
+def test_em_form_by_size(D):
+    """By default small states take the pointwise pass, states whose data exceed
+    128 MiB the in-kernel exponentials; both forms advance such a state alike
+    (to FP32 rounding: the 2048-point direction kernels use radix 8 and 16)."""
+    small = W.curved_bump(n=64, steps=1)
+    s = D.Solver.from_spec(small, precision=D.FP64, potentials=potentials(small))
+    assert s.potential_pass()
+    s.close()
+    big = W.curved_bump(n=2048, seed=1909, steps=2, m=1.0)    # FP32: 4M points x 48 B = 192 MiB
+    pot = potentials(big, seed=2)
+    s, g_auto = gpu(D, big, 2, pot, precision=D.FP32)
+    assert not s.potential_pass()
+    s.close()
+    s, g_pass = gpu(D, big, 2, pot, precision=D.FP32, form=2)
+    s.close()
+    assert O.rel_l2(g_pass, g_auto) < 2e-6
+    with pytest.raises(D.DiracError):
+        D.Solver.from_spec(small, precision=D.FP64).set_potential_form(2)
