@@ -185,11 +185,11 @@ dirac_status cn_step_n(dirac_solver* s, int64_t nsteps) {
     if (nsteps == 0) return DIRAC_OK;
     char* b = s->base;
     const int m = s->scheme.gmres_restart;
-    if (!s->cn_head) {
-        // coherent: the finish kernel's stores reach host memory directly
+    // coherent: the finish kernel's stores reach host memory directly
+    if (!s->cn_head)
         CN_TRY(hipHostMalloc(&s->cn_head, 2 * sizeof(CnHead), hipHostMallocCoherent), "allocate the GMRES state copy");
-        for (int k = 0; k < 2; ++k) CN_TRY(hipEventCreateWithFlags(&s->cn_ev[k], hipEventDisableTiming), "event");
-    }
+    for (int k = 0; k < 2; ++k)
+        if (!s->cn_ev[k]) CN_TRY(hipEventCreateWithFlags(&s->cn_ev[k], hipEventDisableTiming), "create an event");
     const size_t vstride = s->lay.cn_vecbytes / sizeof(double);
     const size_t set_vecs = (size_t)m + 4;
     const size_t coef_set = align_up_256(sizeof(CnCtrl)) + (size_t)m * kCnRecDoubles * 8;
