@@ -51,6 +51,23 @@ static void solve2d(int n, int prec, int kind, int pml, int scheme, bool em, int
         OK(dirac_set_launch_mode(s, 0, 8));
         OK(dirac_step_n(s, 20));
         OK(dirac_step_n_timed(s, 10, ms, c));
+        if (em) {
+            // both forms of the potentials' exponentials, tuned, stepped and timed
+            for (int form : {1, 2, 0}) {
+                OK(dirac_set_potential_form(s, form));
+                OK(dirac_autotune(s, 2));
+                OK(dirac_step_n(s, 7));
+                OK(dirac_step_n_timed(s, 5, ms, c));
+                OK(dirac_time_directions(s, 4, us));
+            }
+            int32_t pass = -1;
+            OK(dirac_get_potential_form(s, &pass));
+            if (pass != 1) { std::printf("FAIL potential form by size\n"); std::exit(1); }
+            if (dirac_set_potential_form(s, 3) != DIRAC_E_ARG) { std::printf("FAIL form 3 accepted\n"); std::exit(1); }
+        } else if (dirac_set_potential_form(s, 1) != DIRAC_E_ARG) {
+            std::printf("FAIL potential form without potentials\n");
+            std::exit(1);
+        }
     }
     OK(dirac_get_spinor(s, psi.data()));
     OK(dirac_destroy(s));
