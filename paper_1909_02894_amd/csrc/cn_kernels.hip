@@ -488,7 +488,7 @@ enum CnFinish { kFinStart = 1, kFinRes = 2, kFinGs = 3 };
 // dots of an Arnoldi iteration, the Givens update of column j.  Every load of
 // the solve state is issued with the partials' loads (one memory round trip).
 // After a cycle (kFinRes), the head of the state is also written to `host`
-// (pinned host memory) for the host's verdict.
+// (pinned host memory) for the host's decision.
 __global__ void __launch_bounds__(kCnThreads) cn_finish_kernel(const double* partials, int nslots, int kind, int j,
                                                                 double* rec, CnCtrl* c, CnHead* host) {
     constexpr int M1 = kCnMaxRestart + 1;

@@ -109,7 +109,7 @@ hipError_t launch_cn_gs_update(double* V, size_t vstride, int j, const double* w
                                CnCtrl* ctrl, hipStream_t s);
 // The end of a cycle (gated on ctrl->done): x += V y with R y = g solved per
 // workgroup, and the residual r = rhs - G x = V (beta e_0 - H_G y) from the
-// Arnoldi relation to r_out with its norm; then the verdict (converged, out of
+// Arnoldi relation to r_out with its norm; then the outcome (converged, out of
 // iterations, or a restart from r).  nk = columns queued (>= the cycle's k).
 // Then the state head is written to `host` (pinned host memory), every time.
 hipError_t launch_cn_update(const double* V, size_t vstride, int nk, double* x, double* r_out, size_t ncplx,

@@ -37,7 +37,7 @@ constexpr int kCnFirstBatch = 4;
 size_t align_up_256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // One of the two sets of solve buffers; step n of a call uses set n mod 2, so
-// that step n + 1 can be queued before step n's verdict is known.
+// that step n + 1 can be queued before step n's outcome is known.
 struct CnCtx {
     dirac_solver* s;
     hipStream_t st;
@@ -259,7 +259,7 @@ dirac_status cn_step_n(dirac_solver* s, int64_t nsteps) {
         CN_TRY(begin_solve(c, batch), "GMRES start");
         return DIRAC_OK;
     };
-    // Step n + 1 is queued before step n's verdict is read (once a cycle length
+    // Step n + 1 is queued before step n's outcome is read (once a cycle length
     // is known), so the host round trip overlaps device work.  If step n needs
     // more iterations, they are queued after it and step n + 1 is queued again
     // (the first copy worked on a state that was not final, in the other set,
