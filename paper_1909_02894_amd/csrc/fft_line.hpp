@@ -215,7 +215,8 @@ struct LineFFT {
     __host__ __device__ static constexpr int lds_elems(int ncomp) {
         return (NPASS > 1) ? (COLS ? ncomp * N * L + (ncomp * N * L / 16) * COL_PAD : L * ncomp * ROW_STRIDE) : 1;
     }
-    static constexpr bool SEQ = CPT == 2 && lds_elems(2) * sizeof(cpx<T>) > kLdsBothMax;
+    static constexpr bool SEQ = CPT == 2 && (lds_elems(2) * sizeof(cpx<T>) > kLdsBothMax ||
+                                              (lds_elems(2) * sizeof(cpx<T>) > kLdsBothMax / 2 && NT <= 256));
     static constexpr int NCL = SEQ ? 1 : 2;        // components held in LDS at once
     static constexpr int LDS_ELEMS = lds_elems(NCL);
     static_assert(LDS_ELEMS * sizeof(cpx<T>) <= 160 * 1024, "exchange buffer exceeds the LDS");

@@ -363,7 +363,9 @@ struct Launch {
 Launch make_launch(const dirac_solver* s, int dir, int e_pre, int e_post, int64_t step = 0) {
     Launch L{};
     if (em_pass(s)) {              // the exponentials run in their own pass (make_exp_launch)
-        e_pre = 0;
+        // curved x kernels always apply their E table once: solves with potentials
+        // hold the identity there (their exponentials come from the record)
+        e_pre = s->curved && dir == 0 ? 1 : 0;
         e_post = 0;
     } else if (s->has_em) {
         const int nlines = dir == 0 ? s->g.n2 : s->g.n1;

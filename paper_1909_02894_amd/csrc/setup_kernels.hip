@@ -164,12 +164,17 @@ __global__ void setup_point_kernel(SetupPointParams p) {
             else { put<double>(p.da_out, 2 * q, dax); put<double>(p.da_out, 2 * q + 1, day); }
         }
         if (p.E_out) {
+            // with potentials the exponentials come from the record: the table holds
+            // the identity, which the plain row kernel then applies (exactly) behind
+            // a potentials pass
+            const bool id = p.em_out != nullptr;
+            const double t0r = id ? 1.0 : e0r, t0i = id ? 0.0 : e0i, t1r = id ? 0.0 : e1r, t1i = id ? 0.0 : e1i;
             if (p.fp32) {
-                put<float>(p.E_out, 4 * q, e0r); put<float>(p.E_out, 4 * q + 1, e0i);
-                put<float>(p.E_out, 4 * q + 2, e1r); put<float>(p.E_out, 4 * q + 3, e1i);
+                put<float>(p.E_out, 4 * q, t0r); put<float>(p.E_out, 4 * q + 1, t0i);
+                put<float>(p.E_out, 4 * q + 2, t1r); put<float>(p.E_out, 4 * q + 3, t1i);
             } else {
-                put<double>(p.E_out, 4 * q, e0r); put<double>(p.E_out, 4 * q + 1, e0i);
-                put<double>(p.E_out, 4 * q + 2, e1r); put<double>(p.E_out, 4 * q + 3, e1i);
+                put<double>(p.E_out, 4 * q, t0r); put<double>(p.E_out, 4 * q + 1, t0i);
+                put<double>(p.E_out, 4 * q + 2, t1r); put<double>(p.E_out, 4 * q + 3, t1i);
             }
         }
         p.obs[q] = exp(chi - f.phi + f.psi);             // weight w

@@ -31,8 +31,8 @@ struct StageParams {
     int n1;                      // points per row
     int nlines;                  // lines of this direction
     int e_pre;                   // Step-1 exponentials applied before the transform: 1 or 2 in
-                                 // direction-x launches (0 when a potentials pass applies them);
-                                 // direction-y kernels ignore it (0 there)
+                                 // direction-x launches (which load E up front; 0 in the flat
+                                 // ones behind a potentials pass); direction-y kernels ignore it
     int e_post;                  // Step-5 exponential applied after the blend (0, 1)
     cpx<T> e0u;                  // uniform e0 when E is null (flat: e^{-i dt m c^2 / 2})
     int wt;                      // 1: write-through state stores (rows; columns of n <= 1024)
@@ -206,8 +206,8 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
     // Step 1 (and Step 5 of the previous step): row `comp` of
     // E = [[e0, e1], [conj e1, conj e0]]: A own + B other with A = e0, B = e1 for
     // component 0 and their conjugates for component 1.  Direction-x launches
-    // of the static metric open with Step 1 (e_pre is 1 or 2), so they load E up
-    // front; with potentials evaluated in a pass of their own they take e_pre = 0.
+    // always open with Step 1 (e_pre is 1 or 2), so they load E up front and
+    // apply it once unconditionally.
     constexpr bool PRELOAD_E = MODE == 2 && !COLS;
     cpx<T> e0[MODE == 2 ? R : 1], e1[MODE == 2 ? R : 1];
     auto loadE = [&]() {
@@ -230,9 +230,7 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
                 });
         }
     };
-    if constexpr (PRELOAD_E) {
-        if (p.e_pre > 0) loadE();
-    }
+    if constexpr (PRELOAD_E) loadE();
     const cpx<T>* tw = p.tw;
     cpx<T> twv[TS::ON ? F::TW_ITER : 1];
     if constexpr (TS::ON) F::tw_load(twv, p.tw, threadIdx.x);
@@ -261,7 +259,7 @@ __device__ __forceinline__ void stage_tile(const StageParams<T>& p, int tile, cp
         tw = twl;
     }
     if constexpr (PRELOAD_E) {
-        if (p.e_pre > 0) applyE(1);
+        applyE(1);                                 // e_pre is 1 or 2 here
         if (p.e_pre > 1) applyE(1);
     } else if constexpr (!COLS) {                  // column launches never open with Step 1
         if (p.e_pre > 0) {

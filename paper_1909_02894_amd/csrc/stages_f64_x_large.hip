@@ -21,3 +21,4 @@ REG(2048, 8, 1, 1)
 REG(2048, 4, 1, 1)
 REGO(4096, 8, 1, 2)
 REG(4096, 8, 1, 1)
+REG(4096, 16, 1, 2)
