@@ -199,3 +199,24 @@ def test_cn_loose_tolerance_keeps_the_initial_guess(D):
     s.cn_set_limits(400, 1e-14)
     s.step_n(2)
     assert O.rel_l2(s.get_spinor(), O.cn_run(psi, T, 2, start=3)) < TOL
+
+
+def test_cn_lookahead_requeues_a_step_that_needs_more_iterations(D):
+    """Two steps at rtol 1e-9 leave a short cycle length; at rtol 1e-14 the next
+    steps need more iterations than the step queued ahead of them was given, so
+    it is discarded and queued again after the current step's extra iterations.
+    The oracle follows the same stopping rules (its own GMRES, from its own
+    initial guess): the states agree to the looser tolerance."""
+    spec = W.curved_bump(n=64, steps=6, m=1.0)
+    psi0 = W.initial_spinor(spec)
+    s = cn_solver(D, spec, rtol=1e-9)
+    s.set_initial_spinor(psi0)
+    s.step_n(2)
+    it2, _ = s.cn_stats()
+    s.cn_set_limits(400, 1e-14)
+    s.step_n(4)
+    it6, res = s.cn_stats()
+    assert res <= 1e-13 and (it6 - it2) / 4 > it2 / 2     # more iterations per step after tightening
+    T = O.build_tables(oracle_problem(spec))
+    ref = O.cn_run(O.cn_run(psi0, T, 2, rtol=1e-9), T, 4, rtol=1e-14, start=2)
+    assert O.rel_l2(s.get_spinor(), ref) < 1e-7
