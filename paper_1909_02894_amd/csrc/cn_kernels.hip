@@ -38,12 +38,16 @@ __host__ __device__ constexpr int cn_lines(int n, bool cols) {
 __host__ __device__ constexpr int cn2_radix(int n) { return cn_radix(n, true); }
 __host__ __device__ constexpr int cn2_lines(int n) { return cn_lines(n, true); }
 constexpr int kCn2Cpt = 1;
+// Spinor components per thread of the per-direction kernels (other grids): one
+// per lane for rows (2048-point FP64 rows 161 -> 139 us), both for columns,
+// which then read whole 32-byte points (one per lane: 118 -> 132 us).
+constexpr int cn_cpt(bool cols) { return cols ? 2 : 1; }
 
 // Tile shape of a pass: the row or column rule, or (M2) the merged kernel's.
 template <int N, bool COLS, bool M2 = false>
 struct CnTile {
     static constexpr int R = M2 ? cn2_radix(N) : cn_radix(N, COLS), L = M2 ? cn2_lines(N) : cn_lines(N, COLS);
-    static constexpr int CPT = M2 ? kCn2Cpt : 2;
+    static constexpr int CPT = M2 ? kCn2Cpt : cn_cpt(COLS);
     using F = LineFFT<double, N, R, L, COLS, CPT>;
     static constexpr int NT = F::NT;
     static constexpr int LDS = F::LDS_ELEMS;
@@ -718,19 +722,23 @@ __global__ void __launch_bounds__(kCnThreads) cn_update_kernel(const double* V, 
 
 // ---------------------------------------------------------------- launchers
 
+template <int N, bool COLS>
+static void launch_apply_n(int nlines, const CnApplyParams& p, hipStream_t s) {
+    using TL = CnTile<N, COLS>;
+    hipLaunchKernelGGL((cn_apply_kernel<N, COLS>), dim3((nlines + TL::L - 1) / TL::L), dim3(TL::NT), 0, s, p);
+}
+
 template <bool COLS>
 static hipError_t launch_apply_dir(int n, int nlines, const CnApplyParams& p, hipStream_t s) {
-    const int L = cn_lines(n, COLS);
-    const dim3 grid((nlines + L - 1) / L), block((n / cn_radix(n, COLS)) * L);
     switch (n) {
-        case 16: hipLaunchKernelGGL((cn_apply_kernel<16, COLS>), grid, block, 0, s, p); break;
-        case 32: hipLaunchKernelGGL((cn_apply_kernel<32, COLS>), grid, block, 0, s, p); break;
-        case 64: hipLaunchKernelGGL((cn_apply_kernel<64, COLS>), grid, block, 0, s, p); break;
-        case 128: hipLaunchKernelGGL((cn_apply_kernel<128, COLS>), grid, block, 0, s, p); break;
-        case 256: hipLaunchKernelGGL((cn_apply_kernel<256, COLS>), grid, block, 0, s, p); break;
-        case 512: hipLaunchKernelGGL((cn_apply_kernel<512, COLS>), grid, block, 0, s, p); break;
-        case 1024: hipLaunchKernelGGL((cn_apply_kernel<1024, COLS>), grid, block, 0, s, p); break;
-        case 2048: hipLaunchKernelGGL((cn_apply_kernel<2048, COLS>), grid, block, 0, s, p); break;
+        case 16: launch_apply_n<16, COLS>(nlines, p, s); break;
+        case 32: launch_apply_n<32, COLS>(nlines, p, s); break;
+        case 64: launch_apply_n<64, COLS>(nlines, p, s); break;
+        case 128: launch_apply_n<128, COLS>(nlines, p, s); break;
+        case 256: launch_apply_n<256, COLS>(nlines, p, s); break;
+        case 512: launch_apply_n<512, COLS>(nlines, p, s); break;
+        case 1024: launch_apply_n<1024, COLS>(nlines, p, s); break;
+        case 2048: launch_apply_n<2048, COLS>(nlines, p, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
