@@ -354,7 +354,7 @@ def bench_serve(count, rate, budget, quantum=64, seed=5000):
 
 VARIANTS = {"batch_256_fp64", "curved_512_fp64", "curved_512_fp32", "flat_2048_precision", "flat_4096_fp32",
             "flat_4096_fp64", "curved_2048_fp64", "curved_4096_fp32", "step2bis_corrected_fp64", "scheme1_cn_gmres",
-            "em_potentials_fp64", "fp32_3d_flat_256", "fp64_3d_curved_128", "serve_poisson"}
+            "scheme1_cn_gmres_2048", "em_potentials_fp64", "fp32_3d_flat_256", "fp64_3d_curved_128", "serve_poisson"}
 
 
 def progress(msg: str):
@@ -526,6 +526,12 @@ def main():
     if want("scheme1_cn_gmres"):
         progress("variant: Scheme I")
         variants["scheme1_cn_gmres"] = bench_cn(D, spec512)
+    if want("scheme1_cn_gmres_2048"):
+        progress("variant: Scheme I, 2048x2048")
+        cb = W.curved_bump(n=2048, seed=1909, steps=20, m=1.0)
+        variants["scheme1_cn_gmres_2048"] = dict(bench_cn(D, cb, steps=20),
+                                                 note="curved bump 2048x2048 FP64 (128 MiB state), separate "
+                                                      "direction launches of the operator")
     if want("em_potentials_fp64"):
         progress("variant: potentials")
         variants["em_potentials_fp64"] = bench_em(D, W, spec512)
