@@ -19,6 +19,7 @@ REG(1024, 8, 2, 2)
 REGO(2048, 8, 2, 2)
 REG(2048, 8, 1, 2)
 REG(2048, 8, 2, 1)
+REG(2048, 16, 2, 2)
 REGO(4096, 8, 1, 2)
 REG(4096, 8, 1, 1)
 REG(4096, 8, 2, 2)
