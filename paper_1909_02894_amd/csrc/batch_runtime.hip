@@ -30,6 +30,8 @@ const void*& batch_multi_kernel_fn(int prec, int dir) {
 // 256-thread tiles (four per compute unit); the smaller groups of a phase
 // share one launch of the multi-group kernel.
 constexpr int kMinGroupTiles = 1024;
+// timed runs per candidate schedule in dirac_batch_autotune (the fastest counts)
+constexpr int kBatchTuneTrials = 3;
 
 static size_t align256b(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -581,9 +583,13 @@ dirac_status dirac_batch_autotune(dirac_batch* b, int32_t reps) {
                 if (!bsched_valid_host(n, sc)) continue;
                 b->sched[d][lg] = sc;
                 ++b->version;
-                float ms = 0;
-                result = timed_run(ms);
-                if (result == DIRAC_OK && ms < best_ms) { best_ms = ms; best = sc; }
+                // the best of a few runs: one group's share of a whole-batch run
+                // is small next to the run-to-run spread of a single run
+                for (int t = 0; t < kBatchTuneTrials && result == DIRAC_OK; ++t) {
+                    float ms = 0;
+                    result = timed_run(ms);
+                    if (result == DIRAC_OK && ms < best_ms) { best_ms = ms; best = sc; }
+                }
             }
             b->sched[d][lg] = best;
             ++b->version;
@@ -605,7 +611,8 @@ dirac_status dirac_batch_autotune(dirac_batch* b, int32_t reps) {
             bool present = false;
             for (int i : occ) present |= __builtin_ctz((unsigned)(d == 0 ? b->slots[i]->g.n1 : b->slots[i]->g.n2)) == lg;
             if (present)
-                for (int sc = 0; sc < kBatchSchedules; ++sc) runs += bsched_valid_host(1 << lg, sc) ? 1 : 0;
+                for (int sc = 0; sc < kBatchSchedules; ++sc)
+                    runs += bsched_valid_host(1 << lg, sc) ? kBatchTuneTrials : 0;
         }
     if (result == DIRAC_OK)
         for (int i : occ) b->slots[i]->step -= (int64_t)runs * reps;
