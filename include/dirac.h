@@ -391,9 +391,11 @@ dirac_status dirac_batch_run(dirac_batch* b, const int64_t* steps);
  * radix 8 or 4, one or both spinor components per thread, 256-thread
  * workgroups, lines per workgroup implied (lines_per_wg 0 = any).  Results
  * depend on the radix only.  dirac_batch_autotune times every valid schedule
- * for each (direction, n) present on `reps` steps of the whole batch (the best
- * of three runs), keeps the fastest, and restores every slot's state and step
- * counter (synchronises). */
+ * for each (direction, n) present on `reps` steps of the whole batch, scored by
+ * the summed duration of the kernels it can change (the size group's own kernel
+ * and the kernel shared by the direction's small groups; per-launch events, the
+ * best of three runs), keeps the lowest-numbered schedule within 1% of the
+ * fastest, and restores every slot's state and step counter (synchronises). */
 int32_t dirac_batch_schedule_count(int32_t n);
 dirac_status dirac_batch_get_schedule(const dirac_batch* b, int32_t n, int32_t dir, dirac_schedule* out);
 dirac_status dirac_batch_set_schedule(dirac_batch* b, int32_t n, int32_t dir, const dirac_schedule* sch);

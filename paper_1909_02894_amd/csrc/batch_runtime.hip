@@ -30,8 +30,10 @@ const void*& batch_multi_kernel_fn(int prec, int dir) {
 // 256-thread tiles (four per compute unit); the smaller groups of a phase
 // share one launch of the multi-group kernel.
 constexpr int kMinGroupTiles = 1024;
-// timed runs per candidate schedule in dirac_batch_autotune (the fastest counts)
+// timed runs per candidate schedule in dirac_batch_autotune (the fastest counts),
+// and the relative margin within which the lower-numbered schedule is kept
 constexpr int kBatchTuneTrials = 3;
+constexpr double kBatchTuneTie = 0.01;
 
 static size_t align256b(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -533,8 +535,13 @@ int32_t dirac_batch_schedule_count(int32_t n) {
 }
 
 // Coordinate search: for every (direction, n) present, time each valid
-// schedule on `reps` steps of the whole batch (direct launches, events on the
-// batch stream) and keep the fastest; states and step counters are restored.
+// schedule on `reps` steps of the whole batch (one launch per group and phase,
+// each between its own events) and score it by the summed time of the kernels
+// it can change (its size group's own kernel and the multi-group kernel of the
+// direction), the best of kBatchTuneTrials runs; the lowest-numbered schedule
+// within kBatchTuneTie of the fastest is kept (schedule 0 is the default), so
+// that near-equal schedules do not flip from one process to the next.  States
+// and step counters are restored.
 dirac_status dirac_batch_autotune(dirac_batch* b, int32_t reps) {
     if (!b || reps < 1 || reps > 10000) return fail(DIRAC_E_ARG, "bad arguments");
     std::vector<int> occ;
@@ -556,47 +563,48 @@ dirac_status dirac_batch_autotune(dirac_batch* b, int32_t reps) {
     }
     std::vector<int64_t> steps(b->capacity, 0);
     for (int i : occ) steps[i] = reps;
-    hipEvent_t ev[2];
-    BTRY(hipEventCreate(&ev[0]), "hipEventCreate");
-    BTRY(hipEventCreate(&ev[1]), "hipEventCreate");
     dirac_status result = DIRAC_OK;
-    auto timed_run = [&](float& ms) -> dirac_status {
-        BTRY(hipEventRecord(ev[0], b->stream), "hipEventRecord");
-        dirac_status r = dirac_batch_run(b, steps.data());
+    // summed kernel time (ms) in one timed run of the launches a schedule of
+    // (direction d, n = 2^lg) can change: that size group's own kernel and the
+    // kernel shared by the small groups of the direction
+    auto timed_run = [&](int d, int lg, double& ms) -> dirac_status {
+        BatchTiming tm{};
+        dirac_status r = batch_run_impl(b, steps.data(), &tm);
         if (r != DIRAC_OK) return r;
-        BTRY(hipEventRecord(ev[1], b->stream), "hipEventRecord");
-        BTRY(hipEventSynchronize(ev[1]), "hipEventSynchronize");
-        BTRY(hipEventElapsedTime(&ms, ev[0], ev[1]), "hipEventElapsedTime");
+        ms = tm.ms[d * 9 + (lg - 4)] + tm.ms[d * 9 + 8];
         return DIRAC_OK;
     };
-    float warm = 0;
-    result = timed_run(warm);
+    double warm = 0;
+    result = timed_run(0, 4, warm);
     for (int d = 0; d < 2 && result == DIRAC_OK; ++d) {
         for (int lg = 4; lg <= 11 && result == DIRAC_OK; ++lg) {
             bool present = false;
             for (int i : occ) present |= __builtin_ctz((unsigned)(d == 0 ? b->slots[i]->g.n1 : b->slots[i]->g.n2)) == lg;
             if (!present) continue;
             const int n = 1 << lg;
-            int best = b->sched[d][lg];
-            float best_ms = 1e30f;
+            const int was = b->sched[d][lg];
+            double t[kBatchSchedules];
+            double fastest = 1e300;
             for (int sc = 0; sc < kBatchSchedules && result == DIRAC_OK; ++sc) {
+                t[sc] = 1e300;
                 if (!bsched_valid_host(n, sc)) continue;
                 b->sched[d][lg] = sc;
                 ++b->version;
-                // the best of a few runs: one group's share of a whole-batch run
-                // is small next to the run-to-run spread of a single run
-                for (int t = 0; t < kBatchTuneTrials && result == DIRAC_OK; ++t) {
-                    float ms = 0;
-                    result = timed_run(ms);
-                    if (result == DIRAC_OK && ms < best_ms) { best_ms = ms; best = sc; }
+                for (int k = 0; k < kBatchTuneTrials && result == DIRAC_OK; ++k) {
+                    double ms = 0;
+                    result = timed_run(d, lg, ms);
+                    if (result == DIRAC_OK) t[sc] = std::min(t[sc], ms);
                 }
+                fastest = std::min(fastest, t[sc]);
             }
-            b->sched[d][lg] = best;
+            int pick = was;
+            if (result == DIRAC_OK)
+                for (int sc = kBatchSchedules - 1; sc >= 0; --sc)
+                    if (t[sc] <= fastest * (1.0 + kBatchTuneTie)) pick = sc;
+            b->sched[d][lg] = pick;
             ++b->version;
         }
     }
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
     for (int i : occ) {
         dirac_solver* s = b->slots[i];
         const size_t bytes = (size_t)s->g.n1 * s->g.n2 * 4 * sz;
