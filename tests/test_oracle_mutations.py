@@ -12,7 +12,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # (what goes wrong, the text in oracle/dirac_oracle.py, what it becomes)
-MUTATIONS = [
+MUTATIONS_2D = [
     ("sign of the directional symbol (R1)",
      "th)[:, None, None] * ID2 - 1j * np.sin", "th)[:, None, None] * ID2 + 1j * np.sin"),
     ("blend without its (1 - b) psi term (eq. (second_scheme))",
@@ -43,33 +43,65 @@ MUTATIONS = [
     ("Scheme I operator without the layer factor 1/S",
      "return c * (T.bx[..., None] * sx + T.by[..., None] * sy)",
      "return c * (T.a[..., None] * sx + T.a[..., None] * sy)"),
+    ("corrected second-order step: sign of its b (1 - b) term (R15)",
+     "(-bb * (1.0 - bb) * d2psi + bb * db[..., None] * d1psi)",
+     "(bb * (1.0 - bb) * d2psi + bb * db[..., None] * d1psi)"),
+    ("corrected second-order step without its b b' term (R15)",
+     "(-bb * (1.0 - bb) * d2psi + bb * db[..., None] * d1psi)", "(-bb * (1.0 - bb) * d2psi)"),
+    ("printed second-order step: correction subtracted (eq. (step2bis))",
+     "out = out + bb * (c * dt) ** 2 * d2Xi", "out = out - bb * (c * dt) ** 2 * d2Xi"),
+    ("potentials: sign of the vector-potential coupling (R16)",
+     "ux = -(dt / 4.0) * c * a * chi_x + 0.5j * dt", "ux = -(dt / 4.0) * c * a * chi_x - 0.5j * dt"),
+    ("potentials: sign of the scalar-potential phase (R16)",
+     "phase = np.exp(0.5j * dt * em.charge * em.V * fv)", "phase = np.exp(-0.5j * dt * em.charge * em.V * fv)"),
+    ("potentials sampled at t_n instead of t_{n+1/2} (R13)",
+     "(n + 0.5) * p.dt)", "n * p.dt)"),
 ]
 
+# the same for oracle/dirac3_oracle.py, checked by the 3-D pins
+MUTATIONS_3D = [
+    ("3-D: sign of the directional symbol",
+     "ID4 - 1j * np.sin(th)[:, None, None] * ALPHA[axis]", "ID4 + 1j * np.sin(th)[:, None, None] * ALPHA[axis]"),
+    ("3-D: y and z directions on each other's array axes",
+     "ARRAY_AXIS = (2, 1, 0)", "ARRAY_AXIS = (2, 0, 1)"),
+    ("3-D: sign of the mass term in E (R17)",
+     "M = (-1j * w[..., None, None] * BETA", "M = (1j * w[..., None, None] * BETA"),
+    ("3-D: blend without its (1 - b) psi term",
+     "return b[..., None] * Xi + (1.0 - b[..., None]) * psi", "return b[..., None] * Xi"),
+    ("3-D: Step 5 dropped",
+     "    return apply_pointwise3(T.E, s)                # Step 5", "    return s"),
+]
 
-def run_pins(tmp_path, name, text):
-    """Run tests/test_oracle_pins.py with `oracle` imported from a copy holding `text`."""
+CASES = ([("dirac_oracle.py", "test_oracle_pins.py") + m for m in MUTATIONS_2D] +
+         [("dirac3_oracle.py", "test_oracle3_pins.py") + m for m in MUTATIONS_3D])
+
+
+def run_pins(tmp_path, name, fname, text, pins):
+    """Run tests/<pins> with `oracle` imported from a copy whose <fname> holds `text`."""
     d = tmp_path / name
     shutil.copytree(os.path.join(ROOT, "oracle"), d / "oracle",
                     ignore=shutil.ignore_patterns("__pycache__"))
-    (d / "oracle" / "dirac_oracle.py").write_text(text)
+    (d / "oracle" / fname).write_text(text)
     env = dict(os.environ, PYTHONPATH=str(d) + os.pathsep + ROOT, PYTHONDONTWRITEBYTECODE="1")
     # --import-mode=append keeps the repository root behind the copy on sys.path
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "--import-mode=append", os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        "--import-mode=append", os.path.join(ROOT, "tests", pins)],
                        capture_output=True, text=True, env=env, cwd=str(d), timeout=600)
     return r
 
 
-def test_unmodified_copy_passes(tmp_path):
-    src = open(os.path.join(ROOT, "oracle", "dirac_oracle.py")).read()
-    r = run_pins(tmp_path, "control", src)
+@pytest.mark.parametrize("fname,pins", [("dirac_oracle.py", "test_oracle_pins.py"),
+                                         ("dirac3_oracle.py", "test_oracle3_pins.py")])
+def test_unmodified_copy_passes(tmp_path, fname, pins):
+    src = open(os.path.join(ROOT, "oracle", fname)).read()
+    r = run_pins(tmp_path, "control", fname, src, pins)
     assert r.returncode == 0, r.stdout[-2000:]
 
 
-@pytest.mark.parametrize("what,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_planted_mistake_fails_a_pin(tmp_path, what, old, new):
-    src = open(os.path.join(ROOT, "oracle", "dirac_oracle.py")).read()
+@pytest.mark.parametrize("fname,pins,what,old,new", CASES, ids=[c[2] for c in CASES])
+def test_planted_mistake_fails_a_pin(tmp_path, fname, pins, what, old, new):
+    src = open(os.path.join(ROOT, "oracle", fname)).read()
     assert src.count(old) == 1, f"mutation site not found: {what}"
-    r = run_pins(tmp_path, "mutant", src.replace(old, new))
+    r = run_pins(tmp_path, "mutant", fname, src.replace(old, new), pins)
     assert r.returncode == 1, (what, r.stdout[-2000:])        # 1: tests ran and one failed
     assert "FAILED" in r.stdout and "error" not in r.stdout.splitlines()[-1].lower(), r.stdout[-2000:]
