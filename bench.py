@@ -232,6 +232,28 @@ def bench_batch(D, W, precision, steps, warmup, timed_steps, count=256, direct=F
             "schedules": {str(n): v for n, v in sched.items()}, "roofline": roof}
 
 
+def measure_copy_peak(torch, nbytes: int = 1 << 30, reps: int = 5) -> dict:
+    """A plain device-to-device copy of `nbytes` (torch's copy_, which runs the
+    runtime's copy kernel), best of `reps`: the streaming rate this part reaches
+    for a read + write mix, next to the nominal HBM peak."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBs": round(2 * nbytes / (best * 1e-3) / 1e9, 1),
+            "what": f"device-to-device copy of {nbytes >> 20} MiB (read + write), best of {reps}"}
+
+
 def load_batch_traffic(kernel: str):
     """HBM bytes per launch of a batch phase kernel from rocprofv3 FETCH_SIZE /
     WRITE_SIZE (profiles/traffic.json, key batch_kernels), or None when absent or
@@ -455,6 +477,9 @@ def main():
                    "state_bytes": hb["state_bytes"], "schedules": hb["schedules"]},
         "roofline": hb["roofline"],
     }
+    cp = measure_copy_peak(torch)
+    cp["frac_of_copy"] = round(hb["roofline"]["achieved"] / cp["GBs"], 4)
+    out["roofline"]["copy"] = cp
     variants = {}
     chosen = None if args.variants is None else set(args.variants.split(","))
     want = lambda k: not args.skip_variants and (chosen is None or k in chosen)
