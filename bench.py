@@ -395,24 +395,38 @@ def single_variant(D, spec, kind, precision, steps, warmup, timed, note, keep_st
     return out, r.get("state")
 
 
-def cpu_baseline_batch(W, steps):
-    """The oracle on a bounded sample of the batch workload: the first solve of
-    each grid size, `steps` steps each, single-threaded."""
+def _oracle_solve(job):
+    """One solve of the oracle for `steps` steps in a worker process; returns its
+    grid-point*steps and the monotonic start/end times of the stepping loop."""
+    sp, steps = job
     from oracle import dirac_oracle as O
+    from paper_1909_02894_amd import workloads as W
     from tests.helpers import oracle_problem
+    T = O.build_tables(oracle_problem(sp))
+    psi = W.initial_spinor(sp)
+    t0 = time.perf_counter()
+    O.run(psi, T, steps)
+    return sp.n1 * sp.n2 * steps, t0, time.perf_counter()
+
+
+def cpu_baseline_batch(W, steps, workers):
+    """The oracle on a bounded sample of the batch workload: the first `workers`
+    solves of the batch, `steps` steps each, one single-threaded process per
+    solve over the host cores (forked before anything touches the GPU); the rate
+    is their total grid-point*steps over the wall time from the first start to
+    the last end of a stepping loop."""
+    import multiprocessing
     specs = W.batch_mix(256, 4000, BATCH_SIZES, steps)
-    sample = [next(sp for sp in specs if sp.n1 == n) for n in BATCH_SIZES]
-    work, secs = 0, 0.0
-    for sp in sample:
-        T = O.build_tables(oracle_problem(sp))
-        psi = W.initial_spinor(sp)
-        t0 = time.perf_counter()
-        O.run(psi, T, steps)
-        secs += time.perf_counter() - t0
-        work += sp.n1 * sp.n2 * steps
-    return {"value": work / secs, "unit": "grid-point*steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of one solve of each size ({', '.join(f'{sp.n1}x{sp.n1} seed {sp.seed}' for sp in sample)}) "
-                      f"of the 256-solve batch (NumPy complex128, single-threaded pocketfft); the host has "
+    sample = specs[:workers]
+    with multiprocessing.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_solve, [(sp, steps) for sp in sample], chunksize=1)
+    work = sum(r[0] for r in res)
+    secs = max(r[2] for r in res) - min(r[1] for r in res)
+    sizes = {n: sum(1 for sp in sample if sp.n1 == n) for n in BATCH_SIZES}
+    return {"value": work / secs, "unit": "grid-point*steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"{steps} steps of each of the first {workers} solves of the 256-solve batch (seeds "
+                      f"4000-{4000 + workers - 1}; " + ", ".join(f"{c} of {n}x{n}" for n, c in sizes.items()) +
+                      "), one single-threaded process per solve (NumPy complex128, pocketfft); the host has "
                       f"{os.cpu_count()} logical CPUs", "seconds": round(secs, 2)}
 
 
@@ -439,9 +453,14 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); a multi-GPU form of this solver is "
               "not built", file=sys.stderr)
         sys.exit(2)
+    from paper_1909_02894_amd import workloads as W
+    cpu = None
+    if not args.skip_cpu and not args.copy_calibration:
+        # the host leg first: its worker processes are forked before the GPU is initialised
+        progress("oracle on the host")
+        cpu = cpu_baseline_batch(W, args.cpu_steps, min(16, os.cpu_count() or 1))
     import torch
     from paper_1909_02894_amd import dirac as D
-    from paper_1909_02894_amd import workloads as W
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
@@ -577,9 +596,8 @@ def main():
         out["latency"] = {"p50_s": variants["serve_poisson"]["p50_s"],
                           "p99_s": variants["serve_poisson"]["p99_s"], "source": "serve_poisson"}
     out["variants"] = variants
-    if not args.skip_cpu:
-        progress("oracle on the host")
-        out["cpu_baseline"] = cpu_baseline_batch(W, args.cpu_steps)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -50,3 +50,13 @@ def test_unknown_variant_names_are_refused():
     r = _run("--variants", "curved_512_fp64,no_such_variant")
     assert r.returncode == 2
     assert "no_such_variant" in r.stderr and r.stdout == ""
+
+
+def test_host_baseline_runs_the_oracle_over_a_process_pool():
+    from paper_1909_02894_amd import workloads as W
+    r = bench.cpu_baseline_batch(W, 2, 3)
+    assert r["kind"] == "oracle" and r["cores"] == 3 and r["unit"] == "grid-point*steps/s"
+    assert r["value"] > 0 and r["seconds"] > 0
+    sizes = [W.batch_mix(256, 4000, bench.BATCH_SIZES, 2)[i].n1 for i in range(3)]
+    assert r["value"] == pytest.approx(sum(n * n * 2 for n in sizes) / r["seconds"], rel=0.02)
+    assert "first 3 solves" in r["sample"]
